@@ -1,0 +1,191 @@
+"""Benchmark: two-site QC-DMRG H.psi TFLOP/s and Davidson s/iter, split-BF16 vs FP64, on one MI355X.
+
+Workload (the precision configuration): L = 24 orbitals, N = 24 (N_alpha = N_beta = 12),
+bond dimension M = 1024 per block at the middle bond (site 11 | 12), random integrals (seed 1),
+synthetic block operators with the real operator structure and Gaussian sector sizes (sigma = 1.5);
+see the design doc for the recipe. One step = one Davidson iteration (H.psi in split-BF16 precision,
+Gram-Schmidt, Rayleigh-Ritz, residual, diagonal preconditioner), inputs resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s
+HBM_PEAK = 8000.0                        # GB/s
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--L", type=int, default=24)
+    ap.add_argument("--M", type=int, default=1024)
+    ap.add_argument("--sigma", type=float, default=1.5)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-converge", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the H.psi would shard over operator combinations with one all-reduce per matvec; "
+              "see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_vector
+    from dmrg_inputs.synthetic import synthetic_problem
+
+    dev = torch.device("cuda:0")
+    L, M = args.L, args.M
+    na = nb = L // 2
+    t0 = time.time()
+    h, eri, left, right, site = synthetic_problem(L, na, nb, M, args.sigma, args.seed)
+    log(f"[bench] inputs {time.time() - t0:.1f}s; building operator (L={L}, M={M}, sigma={args.sigma})")
+    t0 = time.time()
+    stream = torch.cuda.current_stream()
+    hop = dm.Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, stream=stream)
+    t_build = time.time() - t0
+    st = hop.stats()
+    n = hop.n_coeff
+    log(f"[bench] build {t_build:.1f}s: |psi|={n} blocks={hop.n_blocks} alphas={st['n_alpha']} "
+        f"tasks={st['n_tasks']} flops/matvec={st['flops']:.3e}")
+
+    x = torch.as_tensor(random_vector(n, 7), device=dev)
+    y64 = torch.empty_like(x)
+    ysp = torch.empty_like(x)
+
+    # --- kernel timing with events on the launch stream
+    def time_kernel(prec):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.kernel_reps)]
+        out = y64 if prec == dm.PREC_FP64 else ysp
+        hop.hpsi(x, out, prec, stream=stream)            # warm
+        torch.cuda.synchronize()
+        for a, b in ev:
+            a.record(stream)
+            hop.hpsi(x, out, prec, stream=stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b) for a, b in ev])) * 1e-3
+
+    t64 = time_kernel(dm.PREC_FP64)
+    tsp = time_kernel(dm.PREC_SPLIT2)
+    rel_mv = float(torch.linalg.norm(ysp - y64) / torch.linalg.norm(y64))
+    log(f"[bench] H.psi kernel: fp64 {t64 * 1e3:.3f} ms ({st['flops'] / t64 / 1e12:.2f} TF/s), "
+        f"split {tsp * 1e3:.3f} ms ({st['flops'] / tsp / 1e12:.2f} TF/s), rel matvec err {rel_mv:.2e}")
+
+    # --- timed Davidson steps (split precision)
+    def dav_steps(prec, iters):
+        psi = torch.as_tensor(random_vector(n, 3), device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = hop.davidson(psi, tol=1e-30, max_iter=iters, max_sub=24, precision=prec, stream=stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    dav_steps(dm.PREC_SPLIT2, args.warmup)
+    wall_sp, r_sp = dav_steps(dm.PREC_SPLIT2, args.steps)
+    wall_64, r_64 = dav_steps(dm.PREC_FP64, args.steps)
+    s_iter_sp = wall_sp / args.steps
+    s_iter_64 = wall_64 / args.steps
+    value = st["flops"] * r_sp["matvecs"] / wall_sp / 1e12
+    value_64 = st["flops"] * r_64["matvecs"] / wall_64 / 1e12
+    log(f"[bench] Davidson s/iter: split {s_iter_sp * 1e3:.2f} ms ({value:.2f} TF/s), "
+        f"fp64 {s_iter_64 * 1e3:.2f} ms ({value_64:.2f} TF/s)")
+
+    # --- convergence at equal tolerance: FP64 vs split + FP64 polish
+    conv = {}
+    if not args.no_converge:
+        for name, prec, polish in (("fp64", dm.PREC_FP64, False), ("split", dm.PREC_SPLIT2, True)):
+            psi = torch.as_tensor(random_vector(n, 5), device=dev)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = hop.davidson(psi, tol=1e-6, max_iter=400, max_sub=24, precision=prec, fp64_polish=polish,
+                             split_tol=3e-5, stream=stream)
+            torch.cuda.synchronize()
+            conv[name] = dict(energy=r["energy"], resid=r["resid"], iters=r["iters"], matvecs=r["matvecs"],
+                              matvecs_split=r["matvecs_split"], seconds=time.perf_counter() - t,
+                              converged=r["converged"])
+            log(f"[bench] converge {name}: {conv[name]}")
+        conv["dE"] = abs(conv["split"]["energy"] - conv["fp64"]["energy"])
+
+    # --- roofline of the dominant kernel (split sector-GEMM kernel)
+    achieved = st["flops"] / tsp / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK["bf16"], 5), "traffic": None,
+                "kernel": "k_hpsi_split", "mfma_products_per_flop": 3,
+                "fp64_kernel": {"achieved": round(st["flops"] / t64 / 1e12, 3), "peak": PEAK["fp64"],
+                                "frac": round(st["flops"] / t64 / 1e12 / PEAK["fp64"], 4)},
+                "algorithmic_bytes": st["bytes"],
+                "hbm_frac_split": round(st["bytes"] / tsp / 1e9 / HBM_PEAK, 4)}
+
+    # --- CPU oracle on a bounded sample of the same workload
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(h, eri, left, right, na, nb, site, n)
+
+    out = {
+        "metric": "H·ψ TFLOP/s & Davidson s/iter, split-FP32 vs FP64 at |ΔE|≤1e-6 Eh",
+        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(s_iter_sp * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "accumulate": "fp32", "data": "synthetic",
+        "config": {"workload": f"two-site H.psi + Davidson iteration, L={L} N={na + nb} ({na},{nb}) M={M} "
+                               f"middle bond, synthetic block operators sigma={args.sigma}",
+                   "n_coeff": n, "psi_blocks": hop.n_blocks, "n_alpha": st["n_alpha"], "n_tasks": st["n_tasks"],
+                   "flops_per_matvec": st["flops"]},
+        "fp64": {"tflops": round(value_64, 3), "ms_per_iter": round(s_iter_64 * 1e3, 3),
+                 "kernel_ms": round(t64 * 1e3, 4)},
+        "split": {"tflops": round(value, 3), "ms_per_iter": round(s_iter_sp * 1e3, 3),
+                  "kernel_ms": round(tsp * 1e3, 4), "rel_matvec_err": rel_mv},
+        "converge": conv,
+        "build_seconds": round(t_build, 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(h, eri, left, right, na, nb, site, n):
+    """Oracle H.psi on ~5% of the output blocks (setup untimed), single-threaded numpy."""
+    from threadpoolctl import threadpool_limits
+
+    from dmrg_inputs import random_vector
+    from oracle.hpsi import OracleHop
+    log("[bench] cpu baseline: oracle setup (untimed)")
+    oh = OracleHop(h, eri, left, right, na, nb, site)
+    rng = np.random.default_rng(0)
+    nbk = len(oh.layout.blocks)
+    targets = rng.choice(nbk, max(1, nbk // 20), replace=False)
+    tasks = oh.target_tasks(targets)
+    fl = oh.flops(tasks)
+    x = random_vector(n, 7)
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        oh.apply(x, tasks=tasks)
+        dt = time.perf_counter() - t
+    log(f"[bench] cpu baseline: {fl:.3e} flops in {dt:.1f}s")
+    return {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"H.psi restricted to {len(targets)} of {nbk} output blocks ({len(tasks)} sector tasks, "
+                      f"{fl:.3e} flops), numpy FP64, one thread; setup untimed"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,197 @@
+/*
+ * dmrg.h -- C-ABI of libdmrg.so: the two-site QC-DMRG Davidson matrix-vector product H.psi on one
+ * AMD Instinct MI355X (gfx950), after Brabec et al., "Massively parallel quantum chemical density
+ * matrix renormalization group method" (Section 2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Orbitals are 0-based, p = 0 .. L-1, ordered along the DMRG lattice. Spin-orbital id P = 2p + s,
+ *    s = 0 (alpha) or 1 (beta). Fermionic (Jordan-Wigner) order is ascending P.
+ *  - Hamiltonian (Eq. H2q, Section 2.1) with chemist integrals (pq|rs):
+ *        H = sum t_PQ c+_P c_Q + 1/2 sum w_PQRS c+_P c+_Q c_R c_S,
+ *        t_PQ = h_pq d(sP,sQ),  w_PQRS = (ps|qr) d(sP,sS) d(sQ,sR)      (i.e. v_pqrs = (ps|qr)/2).
+ *  - Bond with left site s1 = `site` and right site s2 = site+1; left block = orbitals [0, site),
+ *    right block = orbitals [site+2, L). The left block carries the "normal" operator set and the
+ *    right block the "complementary" (pre-summed) set, see dmrg_op_kind.
+ *  - Site basis (0, up, down, updown) with |updown> = c+_up c+_down |0>.
+ *  - Symmetry sectors are (n_alpha, n_beta) pairs (U(1) x U(1), Section 2.1). Operator sector blocks
+ *    are dense row-major <l'|O|l> of shape dim[sec_out] x dim[sec_in] (the operator class of
+ *    Section 2.2: a sector table plus dense sector tensors).
+ *  - psi layout (Eq. wf_sec): blocks (a, b, c, d) with a = left sector, b, c = site states, d = right
+ *    sector, present iff the (n_alpha, n_beta) of the four parts add up to the targets; ordered by
+ *    (a, b, c) lexicographically; each block row-major m_a x m_d, contiguous, no padding.
+ *  - Status codes: 0 ok, >0 warning, <0 error; dmrg_last_error() gives a thread-local message.
+ *    No C++ exception crosses the ABI. HIP runtime failures map to DMRG_ERR_DEVICE.
+ *  - Ownership: inputs are caller-owned and only read during the call (the library copies what it
+ *    keeps). Handles created by the library are released with the matching _free call.
+ *  - Device vectors passed to dmrg_hpsi / dmrg_davidson are caller-owned device pointers on the
+ *    handle's device; work is ordered on the given stream (0 = the handle's default stream).
+ */
+#ifndef DMRG_H
+#define DMRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dmrg_status;
+#define DMRG_OK                 0
+#define DMRG_NOT_CONVERGED      1
+#define DMRG_ERR_ARG          (-1)
+#define DMRG_ERR_SHAPE        (-2)
+#define DMRG_ERR_NOMEM        (-3)
+#define DMRG_ERR_DEVICE       (-4)
+#define DMRG_ERR_NAN          (-5)
+#define DMRG_ERR_ALIAS        (-6)
+#define DMRG_ERR_UNSUPPORTED  (-7)
+
+/* Last error message of the calling thread (never NULL; "" after success). */
+const char* dmrg_last_error(void);
+
+/* Library version string. */
+const char* dmrg_version(void);
+
+/* Problem definition: integrals (Eq. H2q), electron numbers (Section 2.1, sector constraints of
+ * Eq. wf_sec) and the bond. Host pointers, read during dmrg_build_blocks only. */
+typedef struct {
+    int32_t n_orb;          /* L >= 2 */
+    int32_t n_alpha;        /* N_alpha */
+    int32_t n_beta;         /* N_beta */
+    int32_t site;           /* s1 (0-based), 0 <= site <= L-2 */
+    const double* h;        /* L*L row-major, symmetric */
+    const double* eri;      /* L^4 row-major chemist (pq|rs), 8-fold symmetric */
+} dmrg_problem;
+
+/* Operator kinds of a block (indices are global spin-orbital ids).
+ * Left ("normal") block X:
+ *   H                 block Hamiltonian
+ *   C  (P)            c+_P, P in X
+ *   A  (P<Q)          c+_P c+_Q
+ *   B  (P,Q)          c+_P c_Q, every ordered pair (B_QP may be omitted if B_PQ is given: then
+ *                     B_QP = B_PQ^T is used)
+ *   S  (W)            sum_{P,Q,R in X} w_PQRW c+_P c+_Q c_R for every W to the right of X
+ *                     (three-index part only; the one-body part is added by the library)
+ * Right ("complementary") block Y; "outside" = every spin-orbital to the left of Y:
+ *   H, C (Z in Y)
+ *   U  (P)            sum_{Q,Z,W in Y} w_PQZW c+_Q c_Z c_W, P outside
+ *   P  (P<Q)          sum_{Z,W in Y} w_PQZW c_Z c_W, P<Q outside
+ *   Q  (X,Y')         sum_{Z,W in Y} (w_XZWY' - w_XZY'W) c+_Z c_W, every ordered outside pair
+ *                     (Q_Y'X may be omitted: then Q_Y'X = Q_XY'^T is used)
+ * These are the complete operator intermediates of Section 2.1 (every stored operator must be the
+ * projection of the exact operator onto the block basis for H.psi to equal P H P psi). */
+typedef enum {
+    DMRG_OP_H = 0, DMRG_OP_C = 1, DMRG_OP_A = 2, DMRG_OP_B = 3,
+    DMRG_OP_S = 4, DMRG_OP_U = 5, DMRG_OP_P = 6, DMRG_OP_Q = 7
+} dmrg_op_kind;
+
+typedef struct {
+    int32_t kind;           /* dmrg_op_kind */
+    int32_t i0, i1;         /* spin-orbital ids, -1 if unused */
+    int32_t n_blk;          /* number of stored sector blocks */
+    const int32_t* sec_out; /* n_blk bra-side sector indices */
+    const int32_t* sec_in;  /* n_blk ket-side sector indices (at most one block per sec_in) */
+    const int64_t* off;     /* n_blk element offsets into dmrg_block.data */
+} dmrg_op;
+
+typedef struct {
+    int32_t n_sec;
+    const int32_t* qn;      /* 2*n_sec: (n_alpha, n_beta) per sector, distinct */
+    const int32_t* dim;     /* n_sec: sector dimensions (>= 0) */
+    int32_t n_ops;
+    const dmrg_op* ops;
+    const double* data;     /* host FP64 sector blocks, row-major */
+    int64_t n_data;
+} dmrg_block;
+
+typedef struct dmrg_hop dmrg_hop;   /* opaque: device-resident operators, task lists, layout, diag */
+
+#define DMRG_PREC_FP64    0         /* FP64 MFMA (v_mfma_f64_16x16x4) */
+#define DMRG_PREC_SPLIT2  1         /* BF16 hi/lo split, 3 BF16 MFMA products, FP32 accumulation */
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal; -1 = host-only build (term and task lists only,
+                                no device memory; dmrg_hpsi then returns DMRG_ERR_UNSUPPORTED) */
+    int32_t want_split;      /* 1: also prepare BF16 hi/lo operator copies (DMRG_PREC_SPLIT2) */
+    int64_t mem_budget_bytes;/* 0 = no limit; exceeding it returns DMRG_ERR_NOMEM */
+    void*   stream;          /* hipStream_t for the build; 0 = legacy default stream */
+} dmrg_build_opts;
+
+/* Build the H.psi operator of one bond (Section 2.2.1: "before the Davidson algorithm is started, a
+ * huge task list ... is generated"): psi sector layout (Eq. wf_sec), the list of operator
+ * combinations alpha (the sum over alpha of the H.Phi equation, Section 2.2.1), on-the-fly
+ * pre-summed left-block operators (Section 2.2.3) formed on the GPU, the owner-computes task list
+ * for Eq. dgemm, and diag(H). `left` must carry the normal operator set and `right` the
+ * complementary set described above; a missing operator returns DMRG_ERR_ARG naming it.
+ * On success *out receives a handle owned by the caller (free with dmrg_hop_free). */
+dmrg_status dmrg_build_blocks(const dmrg_problem* problem, const dmrg_block* left,
+                              const dmrg_block* right, const dmrg_build_opts* opts, dmrg_hop** out);
+
+void dmrg_hop_free(dmrg_hop* hop);
+
+/* psi layout (Eq. wf_sec). Pass NULL arrays to query the counts only.
+ *   abcd    4*n_blocks sector indices (a, b, c, d);   dims 2*n_blocks (m_a, m_d);
+ *   offsets n_blocks element offsets. */
+dmrg_status dmrg_hop_layout(const dmrg_hop* hop, int64_t* n_coeff, int32_t* n_blocks,
+                            int32_t* abcd, int32_t* dims, int64_t* offsets);
+
+/* Algorithmic work of one H.psi: flops = sum over tasks of 2 * MACs of the cheaper association of
+ * A.X.B^T (identity factors skipped); bytes = one read of every distinct operator block used + one
+ * read of x + one write of y (FP64). n_alpha = operator combinations, n_tasks = sector GEMM tasks. */
+dmrg_status dmrg_hop_stats(const dmrg_hop* hop, double* flops, double* bytes, int64_t* n_alpha,
+                           int64_t* n_tasks);
+
+/* y = H x for `nvec` vectors stored one after another (stride n_coeff). Device pointers, FP64,
+ * x and y must not overlap (DMRG_ERR_ALIAS). precision: DMRG_PREC_FP64 or DMRG_PREC_SPLIT2 (the
+ * latter needs want_split at build). Deterministic: each output tile is owned by one wavefront and
+ * accumulated in a fixed order (no atomics). Asynchronous on `stream`. */
+dmrg_status dmrg_hpsi(dmrg_hop* hop, const double* x, double* y, int32_t nvec, int32_t precision,
+                      void* stream);
+
+/* diag(H) (FP64) into a device buffer of n_coeff doubles. */
+dmrg_status dmrg_hop_diagonal(dmrg_hop* hop, double* d, void* stream);
+
+/* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
+ * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
+ * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs once the split
+ * residual stalls (or falls below split_tol), and finishes at tol. */
+typedef struct {
+    double  tol;             /* ||r||_2 convergence threshold on the normalized Ritz vector */
+    int32_t max_iter;        /* iterations (matvecs beyond the first) */
+    int32_t max_sub;         /* subspace size before restart (2 .. 64) */
+    int32_t precision;       /* DMRG_PREC_* for the matvec */
+    int32_t fp64_polish;     /* see above */
+    double  split_tol;       /* residual at which split precision hands over to FP64 (e.g. 1e-5) */
+    int32_t use_graph;       /* reserved, must be 0 */
+} dmrg_dav_opts;
+
+typedef struct {
+    double  energy;          /* lowest Ritz value */
+    double  resid;           /* final ||r||_2 */
+    int32_t iters;           /* iterations performed */
+    int32_t matvecs;         /* total H.psi applications */
+    int32_t matvecs_split;   /* of which in split precision */
+    double  t_total;         /* seconds, wall */
+    double  t_hpsi;          /* seconds spent in H.psi (device time, HIP events) */
+} dmrg_dav_result;
+
+/* psi: device pointer, n_coeff doubles: in = start vector (need not be normalized, must be
+ * non-zero), out = Ritz vector (normalized). Returns DMRG_NOT_CONVERGED (with the best pair filled
+ * in) when max_iter is reached, DMRG_ERR_NAN when the start vector or a matvec is not finite.
+ * Synchronizes the stream before returning. */
+dmrg_status dmrg_davidson(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts,
+                          dmrg_dav_result* result, void* stream);
+
+/* Host-logic introspection (used by the CPU tests of the term generator): the task list as
+ * (source block, target block, left matrix id, right matrix id) quadruples with scalars f, and the
+ * definition of every matrix id as a list of (matrix id, side 0=left/1=right, op index into the
+ * block's op array, transposed 0/1, coefficient) entries -- i.e. matrix = sum coeff * op(^T).
+ * Matrix id -1 is the identity. Pass NULL arrays to query the counts. */
+dmrg_status dmrg_hop_export_tasks(const dmrg_hop* hop, int64_t* n_tasks, int32_t* quads, double* f,
+                                  int64_t* n_terms, int32_t* term_int, double* term_coeff);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRG_H */

@@ -20,6 +20,10 @@ def _op_blocks(block, desc):
     """Sector blocks {(so, si): matrix} of a stored operator descriptor (transposed if asked)."""
     kind, i0, i1, tr = desc
     op = block.get(kind, i0, i1)
+    if op is None and kind in ("B", "Q"):
+        # c+_Q c_P = (c+_P c_Q)^T and likewise for Q: a block may store only one of each pair
+        op = block.get(kind, i1, i0)
+        tr = not tr
     if op is None:
         raise KeyError(f"{block.side} block lacks operator {kind}({i0},{i1})")
     if not tr:
@@ -77,6 +81,11 @@ class OracleHop:
             self._tasks = list(self._gen_tasks())
         return self._tasks
 
+    def target_tasks(self, targets):
+        """Tasks writing into the given output blocks (not cached)."""
+        targets = set(targets)
+        return [tk for tk in self._gen_tasks() if tk[1] in targets]
+
     def _gen_tasks(self):
         index = self.layout.index
         for lmat, lcoef, rmat, S1, S2, eL in self.ops:
@@ -105,13 +114,15 @@ class OracleHop:
                 f = lcoef * S1[bp, b] * S2[cp, c] * (self.lparity[a] if eL else 1.0)
                 yield i, j, f, A, B
 
-    def apply(self, x):
-        """y = H x (x of shape (n,) or (n, nvec))."""
+    def apply(self, x, targets=None, tasks=None):
+        """y = H x (x of shape (n,) or (n, nvec)); with ``targets`` (or a task subset) only those blocks."""
         lay = self.layout
         x2 = x.reshape(lay.size, -1)
         y = np.zeros_like(x2)
         nv = x2.shape[1]
-        for i, j, f, A, B in self.tasks():
+        if tasks is None:
+            tasks = self.tasks() if targets is None else self.target_tasks(targets)
+        for i, j, f, A, B in tasks:
             _, _, _, _, off, ma, md = lay.blocks[i]
             _, _, _, _, offj, mj, nj = lay.blocks[j]
             X = x2[off:off + ma * md].reshape(ma, md * nv)           # columns (r, v)
@@ -135,11 +146,11 @@ class OracleHop:
             D[off:off + ma * md] += f * np.outer(da, db).ravel()
         return D
 
-    def flops(self):
+    def flops(self, tasks=None):
         """Algorithmic flops of one H.psi: per task 2 MACs of the cheaper association."""
         lay = self.layout
         total = 0.0
-        for i, j, f, A, B in self.tasks():
+        for i, j, f, A, B in (self.tasks() if tasks is None else tasks):
             ma, md = lay.blocks[i][5], lay.blocks[i][6]
             mj, nj = lay.blocks[j][5], lay.blocks[j][6]
             if A is None and B is None:

@@ -1,0 +1,11 @@
+"""MI355X-native two-site QC-DMRG H.psi (Brabec et al., Section 2): Python binding of libdmrg.so.
+
+The binding only marshals arguments: every step of H.psi, Davidson and the operator preparation
+runs inside the HIP library (``csrc/``). PyTorch supplies device memory and streams. There is no
+CPU fallback: importing the package fails loudly when ``libdmrg.so`` is missing.
+"""
+from .binding import (DMRG_OK, DMRG_NOT_CONVERGED, PREC_FP64, PREC_SPLIT2, DmrgError, Hop, lib,
+                      lib_path, version)
+
+__all__ = ["Hop", "DmrgError", "PREC_FP64", "PREC_SPLIT2", "DMRG_OK", "DMRG_NOT_CONVERGED", "lib",
+           "lib_path", "version"]

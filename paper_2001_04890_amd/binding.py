@@ -1,0 +1,209 @@
+"""ctypes binding of include/dmrg.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libdmrg.so")
+
+# torch's bundled HIP runtime must be the one in the process (libdmrg resolves libamdhip64.so.7
+# by SONAME, so importing torch first makes both share a single runtime).
+try:
+    import torch  # noqa: F401
+except ImportError:  # CPU-only environments without torch can still load the library
+    torch = None
+
+if not os.path.exists(lib_path):
+    raise ImportError(f"{lib_path} is missing: build it with `python -m paper_2001_04890_amd.build` "
+                      "(there is no CPU fallback)")
+lib = C.CDLL(lib_path)
+
+DMRG_OK = 0
+DMRG_NOT_CONVERGED = 1
+PREC_FP64 = 0
+PREC_SPLIT2 = 1
+_KIND = {"H": 0, "C": 1, "A": 2, "B": 3, "S": 4, "U": 5, "P": 6, "Q": 7}
+
+i32p = C.POINTER(C.c_int32)
+i64p = C.POINTER(C.c_int64)
+f64p = C.POINTER(C.c_double)
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_orb", C.c_int32), ("n_alpha", C.c_int32), ("n_beta", C.c_int32), ("site", C.c_int32),
+                ("h", f64p), ("eri", f64p)]
+
+
+class OpDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("i0", C.c_int32), ("i1", C.c_int32), ("n_blk", C.c_int32),
+                ("sec_out", i32p), ("sec_in", i32p), ("off", i64p)]
+
+
+class BlockDesc(C.Structure):
+    _fields_ = [("n_sec", C.c_int32), ("qn", i32p), ("dim", i32p), ("n_ops", C.c_int32),
+                ("ops", C.POINTER(OpDesc)), ("data", f64p), ("n_data", C.c_int64)]
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("device", C.c_int32), ("want_split", C.c_int32), ("mem_budget_bytes", C.c_int64),
+                ("stream", C.c_void_p)]
+
+
+class DavOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32),
+                ("fp64_polish", C.c_int32), ("split_tol", C.c_double), ("use_graph", C.c_int32)]
+
+
+class DavResult(C.Structure):
+    _fields_ = [("energy", C.c_double), ("resid", C.c_double), ("iters", C.c_int32), ("matvecs", C.c_int32),
+                ("matvecs_split", C.c_int32), ("t_total", C.c_double), ("t_hpsi", C.c_double)]
+
+
+lib.dmrg_last_error.restype = C.c_char_p
+lib.dmrg_version.restype = C.c_char_p
+lib.dmrg_build_blocks.argtypes = [C.POINTER(Problem), C.POINTER(BlockDesc), C.POINTER(BlockDesc),
+                                  C.POINTER(BuildOpts), C.POINTER(C.c_void_p)]
+lib.dmrg_build_blocks.restype = C.c_int32
+lib.dmrg_hop_free.argtypes = [C.c_void_p]
+lib.dmrg_hop_free.restype = None
+lib.dmrg_hop_layout.argtypes = [C.c_void_p, i64p, i32p, i32p, i32p, i64p]
+lib.dmrg_hop_layout.restype = C.c_int32
+lib.dmrg_hop_stats.argtypes = [C.c_void_p, f64p, f64p, i64p, i64p]
+lib.dmrg_hop_stats.restype = C.c_int32
+lib.dmrg_hpsi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+lib.dmrg_hpsi.restype = C.c_int32
+lib.dmrg_hop_diagonal.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+lib.dmrg_hop_diagonal.restype = C.c_int32
+lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
+lib.dmrg_davidson.restype = C.c_int32
+lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
+lib.dmrg_hop_export_tasks.restype = C.c_int32
+
+
+def version():
+    return lib.dmrg_version().decode()
+
+
+class DmrgError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libdmrg status {status}: {msg}")
+        self.status = status
+
+
+def _check(st, allow=(DMRG_OK,)):
+    if st not in allow:
+        raise DmrgError(st, lib.dmrg_last_error().decode())
+    return st
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+class _BlockMarshal:
+    """Keeps the numpy arrays behind a BlockDesc alive."""
+
+    def __init__(self, block):
+        data, table = block.flatten()
+        self.data = np.ascontiguousarray(data, dtype=np.float64)
+        self.qn = np.ascontiguousarray(block.qn, dtype=np.int32).ravel()
+        self.dim = np.ascontiguousarray(block.dim, dtype=np.int32)
+        self.keep = []
+        ops = (OpDesc * max(1, len(block.ops)))()
+        for k, (op, rows) in enumerate(zip(block.ops, table)):
+            so = np.array([r[0] for r in rows], dtype=np.int32)
+            si = np.array([r[1] for r in rows], dtype=np.int32)
+            off = np.array([r[2] for r in rows], dtype=np.int64)
+            self.keep += [so, si, off]
+            ops[k] = OpDesc(_KIND[op.kind], op.i0, op.i1, len(rows), _ptr(so, C.c_int32), _ptr(si, C.c_int32),
+                            _ptr(off, C.c_int64))
+        self.ops = ops
+        self.desc = BlockDesc(block.n_sec, _ptr(self.qn, C.c_int32), _ptr(self.dim, C.c_int32), len(block.ops),
+                              ops, _ptr(self.data, C.c_double), self.data.size)
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Hop:
+    """Handle of one bond's H.psi operator (dmrg_build_blocks)."""
+
+    def __init__(self, h, eri, left, right, n_alpha, n_beta, site, device=0, want_split=False,
+                 mem_budget_bytes=0, stream=None):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        prob = Problem(h.shape[0], n_alpha, n_beta, site, _ptr(h, C.c_double), _ptr(eri, C.c_double))
+        lm, rm = _BlockMarshal(left), _BlockMarshal(right)
+        opts = BuildOpts(device, 1 if want_split else 0, mem_budget_bytes, _stream_ptr(stream))
+        handle = C.c_void_p()
+        _check(lib.dmrg_build_blocks(C.byref(prob), C.byref(lm.desc), C.byref(rm.desc), C.byref(opts),
+                                     C.byref(handle)))
+        self._h = handle
+        self.device = device
+        n = C.c_int64()
+        nb = C.c_int32()
+        _check(lib.dmrg_hop_layout(handle, C.byref(n), C.byref(nb), None, None, None))
+        self.n_coeff = n.value
+        self.n_blocks = nb.value
+        abcd = np.zeros(4 * self.n_blocks, dtype=np.int32)
+        dims = np.zeros(2 * self.n_blocks, dtype=np.int32)
+        offs = np.zeros(self.n_blocks, dtype=np.int64)
+        _check(lib.dmrg_hop_layout(handle, None, None, _ptr(abcd, C.c_int32), _ptr(dims, C.c_int32),
+                                   _ptr(offs, C.c_int64)))
+        self.abcd = abcd.reshape(-1, 4)
+        self.dims = dims.reshape(-1, 2)
+        self.offsets = offs
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.dmrg_hop_free(h)
+            self._h = None
+
+    def stats(self):
+        fl, by = C.c_double(), C.c_double()
+        na, nt = C.c_int64(), C.c_int64()
+        _check(lib.dmrg_hop_stats(self._h, C.byref(fl), C.byref(by), C.byref(na), C.byref(nt)))
+        return dict(flops=fl.value, bytes=by.value, n_alpha=na.value, n_tasks=nt.value)
+
+    def hpsi(self, x, y, precision=PREC_FP64, stream=None):
+        """y = H x for device tensors (torch, float64) of shape (n,) or (nvec, n)."""
+        nvec = 1 if x.dim() == 1 else x.shape[0]
+        assert x.dtype == y.dtype and x.is_contiguous() and y.is_contiguous()
+        assert x.numel() == nvec * self.n_coeff and y.numel() == x.numel()
+        _check(lib.dmrg_hpsi(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nvec, precision,
+                             _stream_ptr(stream)))
+
+    def diagonal(self, d, stream=None):
+        assert d.numel() == self.n_coeff and d.is_contiguous()
+        _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
+
+    def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
+                 split_tol=1e-5, stream=None):
+        """In-place Davidson on the device vector psi; returns a dict of the result fields."""
+        assert psi.numel() == self.n_coeff and psi.is_contiguous()
+        o = DavOpts(tol, max_iter, max_sub, precision, 1 if fp64_polish else 0, split_tol, 0)
+        r = DavResult()
+        st = _check(lib.dmrg_davidson(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),
+                                      _stream_ptr(stream)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
+        return dict(energy=r.energy, resid=r.resid, iters=r.iters, matvecs=r.matvecs,
+                    matvecs_split=r.matvecs_split, t_total=r.t_total, t_hpsi=r.t_hpsi,
+                    converged=st == DMRG_OK)
+
+    def export_tasks(self):
+        """Host-side task list and matrix definitions (introspection of the term generator)."""
+        nt, nterm = C.c_int64(), C.c_int64()
+        _check(lib.dmrg_hop_export_tasks(self._h, C.byref(nt), None, None, C.byref(nterm), None, None))
+        quads = np.zeros(4 * nt.value, dtype=np.int32)
+        f = np.zeros(nt.value)
+        ti = np.zeros(4 * nterm.value, dtype=np.int32)
+        tc = np.zeros(nterm.value)
+        _check(lib.dmrg_hop_export_tasks(self._h, None, _ptr(quads, C.c_int32), _ptr(f, C.c_double), None,
+                                         _ptr(ti, C.c_int32), _ptr(tc, C.c_double)))
+        return quads.reshape(-1, 4), f, ti.reshape(-1, 4), tc

@@ -1,0 +1,1158 @@
+// Host driver of libdmrg: block import, psi sector layout (Eq. wf_sec), the operator-combination
+// list of the two-site H.psi (Section 2.2.1), pre-summation plans (Section 2.2.3), the
+// owner-computes task list for Eq. dgemm, device residency and the C-ABI entry points.
+//
+// Term generator. With L = left block (normal operators), S = the two sites s1 s2 and R = right
+// block (complementary operators), H is split by two nested cut identities:
+//   cut 1, L | (S R):  H = H_L + H_SR + sum_{W in SR} [S^L_W c_W + h.c.] + sum_{P in L} [c+_P U^SR_P
+//                      + h.c.] + sum_{P<Q in L} [A_PQ P^SR_PQ + h.c.] + sum_{X,Y in L} B_XY Q^SR_XY
+//   cut 2, S | R:      H_SR = H_S + H_R + the same five cross families with S as the normal side,
+// and every complementary operator of (S R) is split into its S-only, R-only and mixed parts
+// (e.g. P^SR_PQ = P^R_PQ + sum_{zw in S} w_PQzw c_z c_w + sum_{y in S, Z in R} (w_PQyZ - w_PQZy)
+// c_y c_Z). Mixed sums over block indices are folded into pre-summed left-block operators
+// (integrals contracted inside one block: Section 2.1 footnote, Section 2.2.3), so every
+// combination alpha is (left matrix) x (16x16 two-site matrix) x (right matrix), Section 2.2.1.
+// The matrix of an operator product O_L O_S O_R on |l>|s1 s2>|r> is
+// (O_L P_L^{p(O_L)}) x (O_S P_S^{p(O_R)}) x O_R with P the ket parity; the Hermitian conjugate of a
+// combination is the transpose of each of its three matrices.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/dmrg.h"
+#include "internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error : std::runtime_error {
+    dmrg_status code;
+    Error(dmrg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                            \
+    do {                                                                                     \
+        hipError_t e_ = (x);                                                                 \
+        if (e_ != hipSuccess)                                                                \
+            throw Error(DMRG_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+using M16 = std::array<double, 256>;   // two-site operator, index (b'*4+c') * 16 + (b*4+c)
+
+M16 zero16() { M16 m; m.fill(0.0); return m; }
+M16 eye16() { M16 m = zero16(); for (int i = 0; i < 16; ++i) m[i * 17] = 1.0; return m; }
+M16 mul(const M16& a, const M16& b) {
+    M16 c = zero16();
+    for (int i = 0; i < 16; ++i)
+        for (int k = 0; k < 16; ++k) {
+            double v = a[i * 16 + k];
+            if (v == 0.0) continue;
+            for (int j = 0; j < 16; ++j) c[i * 16 + j] += v * b[k * 16 + j];
+        }
+    return c;
+}
+M16 tr16(const M16& a) { M16 c; for (int i = 0; i < 16; ++i) for (int j = 0; j < 16; ++j) c[j * 16 + i] = a[i * 16 + j]; return c; }
+void axpy16(M16& y, double a, const M16& x) { for (int i = 0; i < 256; ++i) y[i] += a * x[i]; }
+bool nonzero16(const M16& a) { for (double v : a) if (v != 0.0) return true; return false; }
+
+// Two-site Jordan-Wigner fermion matrices. Site mode y: 0 = s1 alpha, 1 = s1 beta, 2 = s2 alpha,
+// 3 = s2 beta. Site basis (0, up, dn, updn), |updn> = c+_up c+_dn |0>:
+//   c+_up = E10 + E32, c+_dn = E20 - E31; on s2 the s1 parity diag(1,-1,-1,1) is applied.
+M16 site_cd(int y) {
+    double a[16] = {0};
+    if (y % 2 == 0) { a[1 * 4 + 0] = 1; a[3 * 4 + 2] = 1; }
+    else            { a[2 * 4 + 0] = 1; a[3 * 4 + 1] = -1; }
+    const double par[4] = {1, -1, -1, 1};
+    M16 m = zero16();
+    for (int bp = 0; bp < 4; ++bp)
+        for (int b = 0; b < 4; ++b)
+            for (int cp = 0; cp < 4; ++cp)
+                for (int c = 0; c < 4; ++c) {
+                    double v;
+                    if (y < 2) v = a[bp * 4 + b] * (cp == c ? 1.0 : 0.0);
+                    else v = (bp == b ? par[b] : 0.0) * a[cp * 4 + c];
+                    m[(bp * 4 + cp) * 16 + (b * 4 + c)] = v;
+                }
+    return m;
+}
+M16 site_c(int y) { return tr16(site_cd(y)); }
+M16 site_parity() {
+    const double par[4] = {1, -1, -1, 1};
+    M16 m = zero16();
+    for (int b = 0; b < 4; ++b) for (int c = 0; c < 4; ++c) m[(b * 4 + c) * 17] = par[b] * par[c];
+    return m;
+}
+
+const int kSiteQn[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+
+// ---------------------------------------------------------------- imported blocks
+struct OpIn {
+    int kind, i0, i1;
+    std::vector<int> out_of_in;       // per ket sector: bra sector or -1
+    std::vector<int64_t> off_of_in;   // host element offset of the block
+};
+struct BlockIn {
+    int n_sec = 0;
+    std::vector<int> qa, qb, dim;
+    std::vector<OpIn> ops;
+    std::map<std::array<int, 3>, int> index;
+    const double* data = nullptr;
+    int64_t n_data = 0;
+    int find(int kind, int i0, int i1) const {
+        auto it = index.find({kind, i0, i1});
+        return it == index.end() ? -1 : it->second;
+    }
+};
+
+const char* kind_name(int k) {
+    static const char* n[] = {"H", "C", "A", "B", "S", "U", "P", "Q"};
+    return (k >= 0 && k < 8) ? n[k] : "?";
+}
+
+BlockIn import_block(const dmrg_block* b, const char* side) {
+    if (!b) throw Error(DMRG_ERR_ARG, std::string(side) + " block is NULL");
+    BlockIn B;
+    if (b->n_sec <= 0 || !b->qn || !b->dim) throw Error(DMRG_ERR_ARG, std::string(side) + " block has no sectors");
+    B.n_sec = b->n_sec;
+    std::map<std::pair<int, int>, int> seen;
+    for (int i = 0; i < b->n_sec; ++i) {
+        B.qa.push_back(b->qn[2 * i]);
+        B.qb.push_back(b->qn[2 * i + 1]);
+        B.dim.push_back(b->dim[i]);
+        if (b->dim[i] < 0) throw Error(DMRG_ERR_SHAPE, std::string(side) + " block: negative sector dimension");
+        if (!seen.emplace(std::make_pair(b->qn[2 * i], b->qn[2 * i + 1]), i).second)
+            throw Error(DMRG_ERR_ARG, std::string(side) + " block: duplicate sector quantum numbers");
+    }
+    B.data = b->data;
+    B.n_data = b->n_data;
+    if (b->n_ops < 0 || (b->n_ops > 0 && !b->ops)) throw Error(DMRG_ERR_ARG, std::string(side) + " block: bad op list");
+    for (int k = 0; k < b->n_ops; ++k) {
+        const dmrg_op& o = b->ops[k];
+        OpIn op;
+        op.kind = o.kind; op.i0 = o.i0; op.i1 = o.i1;
+        if (o.kind < 0 || o.kind > 7) throw Error(DMRG_ERR_ARG, "unknown operator kind");
+        op.out_of_in.assign(B.n_sec, -1);
+        op.off_of_in.assign(B.n_sec, -1);
+        for (int j = 0; j < o.n_blk; ++j) {
+            int so = o.sec_out[j], si = o.sec_in[j];
+            int64_t off = o.off[j];
+            if (so < 0 || so >= B.n_sec || si < 0 || si >= B.n_sec)
+                throw Error(DMRG_ERR_SHAPE, std::string(side) + " block: sector index out of range");
+            if (op.out_of_in[si] >= 0)
+                throw Error(DMRG_ERR_SHAPE, std::string(side) + " block: two blocks with the same ket sector");
+            int64_t sz = (int64_t)B.dim[so] * B.dim[si];
+            if (off < 0 || off + sz > B.n_data)
+                throw Error(DMRG_ERR_SHAPE, std::string(side) + " block: data offset out of range");
+            op.out_of_in[si] = so;
+            op.off_of_in[si] = off;
+        }
+        if (!B.index.emplace(std::array<int, 3>{o.kind, o.i0, o.i1}, k).second)
+            throw Error(DMRG_ERR_ARG, std::string(side) + " block: duplicate operator");
+        B.ops.push_back(std::move(op));
+    }
+    if (B.n_data > 0 && !B.data) throw Error(DMRG_ERR_ARG, std::string(side) + " block: data is NULL");
+    for (int64_t i = 0; i < B.n_data; ++i)
+        if (!std::isfinite(B.data[i])) throw Error(DMRG_ERR_NAN, std::string(side) + " block: non-finite operator entry");
+    return B;
+}
+
+// ---------------------------------------------------------------- matrices and combinations
+struct Term { double c; int op; bool tr; };
+struct MatDef {
+    int side;                       // 0 left, 1 right
+    std::vector<Term> terms;        // matrix = sum c * op (or op^T)
+    int transpose_id = -1;          // cache
+    // materialized:
+    std::vector<int> out_of_in;
+    std::vector<int64_t> pool_of_in;
+};
+
+struct Alpha {
+    double coeff;
+    int lmat;       // -1 identity
+    int lpar;       // 0 none, 1 (-1)^{n(ket sector)}, 2 (-1)^{n(bra sector)}
+    M16 S;
+    int rmat;       // -1 identity
+    int family;
+};
+
+}  // namespace
+
+struct dmrg_hop {
+    int L = 0, na = 0, nb = 0, site = 0;
+    BlockIn left, right;
+    std::vector<double> h, eri;
+    // layout
+    std::vector<std::array<int, 4>> blk;     // (a, b, c, d)
+    std::vector<int> blk_ma, blk_md;
+    std::vector<int64_t> blk_off;
+    std::vector<int> blk_index;              // [(a*4+b)*4+c] -> block id or -1
+    int64_t n_coeff = 0;
+    // terms
+    std::vector<MatDef> mats;
+    std::map<std::tuple<int, int, bool>, int> mat_cache;
+    std::vector<Alpha> alphas;
+    // tasks
+    struct HTask { int i, j, lm, rm; double f; };
+    std::vector<HTask> tasks;
+    double flops = 0.0, bytes = 0.0;
+    // device
+    int device = -1;
+    bool has_split = false;
+    int64_t pool_size = 0;
+    double* d_pool = nullptr;
+    uint16_t* d_hi = nullptr;
+    uint16_t* d_lo = nullptr;
+    dmrg::Unit* d_units = nullptr;
+    dmrg::Task* d_tasks = nullptr;
+    int n_units = 0;
+    int64_t n_dev_tasks = 0;
+    double* d_diag = nullptr;
+    std::vector<void*> allocations;
+};
+
+namespace {
+
+// Spin-orbital integrals (reading of Eq. H2q: v_pqrs = (ps|qr)/2).
+struct Integrals {
+    int L;
+    const double* h;
+    const double* eri;
+    double t(int P, int Q) const {
+        if ((P & 1) != (Q & 1)) return 0.0;
+        return h[(P >> 1) * L + (Q >> 1)];
+    }
+    double w(int P, int Q, int R, int S) const {
+        if ((P & 1) != (S & 1) || (Q & 1) != (R & 1)) return 0.0;
+        int p = P >> 1, q = Q >> 1, r = R >> 1, s = S >> 1;
+        return eri[(((int64_t)p * L + s) * L + q) * L + r];
+    }
+};
+
+struct Builder {
+    dmrg_hop& H;
+    Integrals I;
+    Builder(dmrg_hop& h) : H(h) { I.L = h.L; I.h = h.h.data(); I.eri = h.eri.data(); }
+
+    BlockIn& side(int s) { return s == 0 ? H.left : H.right; }
+
+    // stored operator (with B/Q transposition fallback); throws if absent
+    std::pair<int, bool> op(int s, int kind, int i0, int i1 = -1) {
+        BlockIn& B = side(s);
+        int k = B.find(kind, i0, i1);
+        if (k >= 0) return {k, false};
+        if (kind == DMRG_OP_B || kind == DMRG_OP_Q) {
+            k = B.find(kind, i1, i0);
+            if (k >= 0) return {k, true};
+        }
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "%s block lacks operator %s(%d,%d)", s == 0 ? "left" : "right",
+                      kind_name(kind), i0, i1);
+        throw Error(DMRG_ERR_ARG, buf);
+    }
+
+    int mat(int s, std::pair<int, bool> o) {
+        auto key = std::make_tuple(s, o.first, o.second);
+        auto it = H.mat_cache.find(key);
+        if (it != H.mat_cache.end()) return it->second;
+        MatDef m;
+        m.side = s;
+        m.terms.push_back({1.0, o.first, o.second});
+        H.mats.push_back(m);
+        int id = (int)H.mats.size() - 1;
+        H.mat_cache[key] = id;
+        return id;
+    }
+    int presum(int s, const std::vector<Term>& terms) {
+        std::vector<Term> nz;
+        for (const Term& t : terms) if (t.c != 0.0) nz.push_back(t);
+        if (nz.empty()) return -2;   // identically zero
+        if (nz.size() == 1 && nz[0].c == 1.0) return mat(s, {nz[0].op, nz[0].tr});
+        MatDef m;
+        m.side = s;
+        m.terms = nz;
+        H.mats.push_back(m);
+        return (int)H.mats.size() - 1;
+    }
+    int transpose(int id) {
+        if (id < 0) return id;
+        if (H.mats[id].transpose_id >= 0) return H.mats[id].transpose_id;
+        int tid;
+        if (H.mats[id].terms.size() == 1 && H.mats[id].terms[0].c == 1.0) {
+            tid = mat(H.mats[id].side, {H.mats[id].terms[0].op, !H.mats[id].terms[0].tr});
+        } else {
+            MatDef m;
+            m.side = H.mats[id].side;
+            for (const Term& t : H.mats[id].terms) m.terms.push_back({t.c, t.op, !t.tr});
+            H.mats.push_back(m);
+            tid = (int)H.mats.size() - 1;
+        }
+        H.mats[id].transpose_id = tid;
+        H.mats[tid].transpose_id = id;
+        return tid;
+    }
+
+    void emit(int family, int lm, bool lodd, const M16& S, int rm, bool hc) {
+        if (lm == -2 || rm == -2 || !nonzero16(S)) return;
+        H.alphas.push_back({1.0, lm, lodd ? 1 : 0, S, rm, family});
+        if (hc) H.alphas.push_back({1.0, transpose(lm), lodd ? 2 : 0, tr16(S), transpose(rm), -family});
+    }
+
+    void generate() {
+        const int site = H.site, L = H.L;
+        const int nL = 2 * site;                 // left spin-orbitals 0 .. nL-1
+        const int G0 = 2 * site;                 // site mode y -> spin-orbital G0 + y
+        const int R0 = 2 * (site + 2), R1 = 2 * L;
+        M16 cd[4], c[4];
+        for (int y = 0; y < 4; ++y) { cd[y] = site_cd(y); c[y] = site_c(y); }
+        const M16 PS = site_parity(), I16 = eye16();
+        auto G = [&](int y) { return G0 + y; };
+        enum { LEFT = 0, RIGHT = 1 };
+
+        // F1, F3: block Hamiltonians
+        emit(1, mat(LEFT, op(LEFT, DMRG_OP_H, -1, -1)), false, I16, -1, false);
+        emit(3, -1, false, I16, mat(RIGHT, op(RIGHT, DMRG_OP_H, -1, -1)), false);
+        // F2: two-site Hamiltonian
+        {
+            M16 HS = zero16();
+            for (int y = 0; y < 4; ++y)
+                for (int z = 0; z < 4; ++z) {
+                    double v = I.t(G(y), G(z));
+                    if (v != 0.0) axpy16(HS, v, mul(cd[y], c[z]));
+                }
+            for (int p = 0; p < 4; ++p) for (int q = 0; q < 4; ++q)
+                for (int r = 0; r < 4; ++r) for (int s = 0; s < 4; ++s) {
+                    double v = I.w(G(p), G(q), G(r), G(s));
+                    if (v != 0.0) axpy16(HS, 0.5 * v, mul(mul(cd[p], cd[q]), mul(c[r], c[s])));
+                }
+            emit(2, -1, false, HS, -1, false);
+        }
+        // F4: S^L_W c_W, W in the sites (S^L_W completed with its one-body part)
+        for (int y = 0; y < 4; ++y) {
+            int W = G(y);
+            std::vector<Term> t;
+            auto s = op(LEFT, DMRG_OP_S, W);
+            t.push_back({1.0, s.first, s.second});
+            for (int P = 0; P < nL; ++P) { auto o = op(LEFT, DMRG_OP_C, P); t.push_back({I.t(P, W), o.first, o.second}); }
+            emit(4, presum(LEFT, t), true, c[y], -1, true);
+        }
+        // F5: S^L_W c_W, W in the right block
+        for (int W = R0; W < R1; ++W) {
+            std::vector<Term> t;
+            auto s = op(LEFT, DMRG_OP_S, W);
+            t.push_back({1.0, s.first, s.second});
+            for (int P = 0; P < nL; ++P) { auto o = op(LEFT, DMRG_OP_C, P); t.push_back({I.t(P, W), o.first, o.second}); }
+            auto cw = op(RIGHT, DMRG_OP_C, W);
+            emit(5, presum(LEFT, t), true, PS, mat(RIGHT, {cw.first, !cw.second}), true);
+        }
+        for (int P = 0; P < nL; ++P) {
+            int cP = mat(LEFT, op(LEFT, DMRG_OP_C, P));
+            // F6: c+_P U^R_P
+            emit(6, cP, true, PS, mat(RIGHT, op(RIGHT, DMRG_OP_U, P)), true);
+            // F7: c+_P U^S_P
+            M16 US = zero16();
+            for (int q = 0; q < 4; ++q) for (int z = 0; z < 4; ++z) for (int x = 0; x < 4; ++x) {
+                double v = I.w(P, G(q), G(z), G(x));
+                if (v != 0.0) axpy16(US, v, mul(mul(cd[q], c[z]), c[x]));
+            }
+            emit(7, cP, true, US, -1, true);
+            // F8: c+_P c+_q P^R_Pq ; F9: c+_P c_y Q^R_Py
+            for (int q = 0; q < 4; ++q) emit(8, cP, true, cd[q], mat(RIGHT, op(RIGHT, DMRG_OP_P, P, G(q))), true);
+            for (int y = 0; y < 4; ++y) emit(9, cP, true, c[y], mat(RIGHT, op(RIGHT, DMRG_OP_Q, P, G(y))), true);
+        }
+        // F10: [sum_P (w_PqyZ - w_PqZy) c+_P] c+_q c_y c_Z, Z in R
+        for (int Z = R0; Z < R1; ++Z) {
+            auto cz = op(RIGHT, DMRG_OP_C, Z);
+            int cZ = mat(RIGHT, {cz.first, !cz.second});
+            for (int q = 0; q < 4; ++q) for (int y = 0; y < 4; ++y) {
+                std::vector<Term> t;
+                for (int P = 0; P < nL; ++P) {
+                    auto o = op(LEFT, DMRG_OP_C, P);
+                    t.push_back({I.w(P, G(q), G(y), Z) - I.w(P, G(q), Z, G(y)), o.first, o.second});
+                }
+                emit(10, presum(LEFT, t), true, mul(mul(cd[q], c[y]), PS), cZ, true);
+            }
+        }
+        // F11: [sum_P (w_PQzw - w_PQwz) c+_P] c_z c_w c+_Q, Q in R, z < w
+        for (int Q = R0; Q < R1; ++Q) {
+            int cQ = mat(RIGHT, op(RIGHT, DMRG_OP_C, Q));
+            for (int z = 0; z < 4; ++z) for (int x = z + 1; x < 4; ++x) {
+                std::vector<Term> t;
+                for (int P = 0; P < nL; ++P) {
+                    auto o = op(LEFT, DMRG_OP_C, P);
+                    t.push_back({I.w(P, Q, G(z), G(x)) - I.w(P, Q, G(x), G(z)), o.first, o.second});
+                }
+                emit(11, presum(LEFT, t), true, mul(mul(c[z], c[x]), PS), cQ, true);
+            }
+        }
+        // F12: A_PQ P^R_PQ
+        for (int P = 0; P < nL; ++P)
+            for (int Q = P + 1; Q < nL; ++Q)
+                emit(12, mat(LEFT, op(LEFT, DMRG_OP_A, P, Q)), false, I16, mat(RIGHT, op(RIGHT, DMRG_OP_P, P, Q)), true);
+        // F13: [sum_{P<Q} (w_PQzw - w_PQwz) A_PQ] c_z c_w
+        for (int z = 0; z < 4; ++z) for (int x = z + 1; x < 4; ++x) {
+            std::vector<Term> t;
+            for (int P = 0; P < nL; ++P) for (int Q = P + 1; Q < nL; ++Q) {
+                auto o = op(LEFT, DMRG_OP_A, P, Q);
+                t.push_back({I.w(P, Q, G(z), G(x)) - I.w(P, Q, G(x), G(z)), o.first, o.second});
+            }
+            emit(13, presum(LEFT, t), false, mul(c[z], c[x]), -1, true);
+        }
+        // F14: [sum_{P<Q} (w_PQyZ - w_PQZy) A_PQ] c_y c_Z
+        for (int y = 0; y < 4; ++y) for (int Z = R0; Z < R1; ++Z) {
+            std::vector<Term> t;
+            for (int P = 0; P < nL; ++P) for (int Q = P + 1; Q < nL; ++Q) {
+                auto o = op(LEFT, DMRG_OP_A, P, Q);
+                t.push_back({I.w(P, Q, G(y), Z) - I.w(P, Q, Z, G(y)), o.first, o.second});
+            }
+            auto cz = op(RIGHT, DMRG_OP_C, Z);
+            emit(14, presum(LEFT, t), false, mul(c[y], PS), mat(RIGHT, {cz.first, !cz.second}), true);
+        }
+        // F15: B_XY Q^R_XY
+        for (int X = 0; X < nL; ++X)
+            for (int Y = 0; Y < nL; ++Y)
+                emit(15, mat(LEFT, op(LEFT, DMRG_OP_B, X, Y)), false, I16, mat(RIGHT, op(RIGHT, DMRG_OP_Q, X, Y)), false);
+        // F16, F17, F18: the site and mixed parts of Q^SR_XY
+        auto bsum = [&](auto coef) {
+            std::vector<Term> t;
+            for (int X = 0; X < nL; ++X) for (int Y = 0; Y < nL; ++Y) {
+                auto o = op(LEFT, DMRG_OP_B, X, Y);
+                t.push_back({coef(X, Y), o.first, o.second});
+            }
+            return presum(LEFT, t);
+        };
+        for (int z = 0; z < 4; ++z) for (int x = 0; x < 4; ++x) {
+            int lm = bsum([&](int X, int Y) { return I.w(X, G(z), G(x), Y) - I.w(X, G(z), Y, G(x)); });
+            emit(16, lm, false, mul(cd[z], c[x]), -1, false);
+        }
+        for (int z = 0; z < 4; ++z) for (int W = R0; W < R1; ++W) {
+            int lm = bsum([&](int X, int Y) { return I.w(X, G(z), W, Y) - I.w(X, G(z), Y, W); });
+            auto cw = op(RIGHT, DMRG_OP_C, W);
+            emit(17, lm, false, mul(cd[z], PS), mat(RIGHT, {cw.first, !cw.second}), false);
+        }
+        for (int x = 0; x < 4; ++x) for (int Z = R0; Z < R1; ++Z) {
+            int lm = bsum([&](int X, int Y) { return -(I.w(X, Z, G(x), Y) - I.w(X, Z, Y, G(x))); });
+            emit(18, lm, false, mul(c[x], PS), mat(RIGHT, op(RIGHT, DMRG_OP_C, Z)), false);
+        }
+        // F19: S^S_W c_W, W in R
+        for (int W = R0; W < R1; ++W) {
+            M16 SS = zero16();
+            for (int p = 0; p < 4; ++p) {
+                double v = I.t(G(p), W);
+                if (v != 0.0) axpy16(SS, v, cd[p]);
+            }
+            for (int p = 0; p < 4; ++p) for (int q = 0; q < 4; ++q) for (int r = 0; r < 4; ++r) {
+                double v = I.w(G(p), G(q), G(r), W);
+                if (v != 0.0) axpy16(SS, v, mul(mul(cd[p], cd[q]), c[r]));
+            }
+            auto cw = op(RIGHT, DMRG_OP_C, W);
+            emit(19, -1, false, mul(SS, PS), mat(RIGHT, {cw.first, !cw.second}), true);
+        }
+        // F20 .. F22: site operators times right complementary operators with site indices
+        for (int p = 0; p < 4; ++p) emit(20, -1, false, mul(cd[p], PS), mat(RIGHT, op(RIGHT, DMRG_OP_U, G(p))), true);
+        for (int p = 0; p < 4; ++p) for (int q = p + 1; q < 4; ++q)
+            emit(21, -1, false, mul(cd[p], cd[q]), mat(RIGHT, op(RIGHT, DMRG_OP_P, G(p), G(q))), true);
+        for (int x = 0; x < 4; ++x) for (int y = 0; y < 4; ++y)
+            emit(22, -1, false, mul(cd[x], c[y]), mat(RIGHT, op(RIGHT, DMRG_OP_Q, G(x), G(y))), false);
+    }
+};
+
+void build_layout(dmrg_hop& H) {
+    const BlockIn &Lb = H.left, &Rb = H.right;
+    std::map<std::pair<int, int>, int> ridx;
+    for (int d = 0; d < Rb.n_sec; ++d) ridx[{Rb.qa[d], Rb.qb[d]}] = d;
+    H.blk_index.assign((size_t)Lb.n_sec * 16, -1);
+    int64_t off = 0;
+    for (int a = 0; a < Lb.n_sec; ++a)
+        for (int b = 0; b < 4; ++b)
+            for (int c = 0; c < 4; ++c) {
+                int qa = H.na - Lb.qa[a] - kSiteQn[b][0] - kSiteQn[c][0];
+                int qb = H.nb - Lb.qb[a] - kSiteQn[b][1] - kSiteQn[c][1];
+                auto it = ridx.find({qa, qb});
+                if (it == ridx.end()) continue;
+                int d = it->second;
+                int ma = Lb.dim[a], md = Rb.dim[d];
+                if (ma == 0 || md == 0) continue;
+                H.blk_index[(a * 4 + b) * 4 + c] = (int)H.blk.size();
+                H.blk.push_back({a, b, c, d});
+                H.blk_ma.push_back(ma);
+                H.blk_md.push_back(md);
+                H.blk_off.push_back(off);
+                off += (int64_t)ma * md;
+            }
+    H.n_coeff = off;
+    if (H.blk.empty()) throw Error(DMRG_ERR_SHAPE, "no psi sector satisfies the electron-number constraints");
+}
+
+// Sector map of a matrix definition (all terms must change the quantum numbers alike).
+void mat_sectors(dmrg_hop& H, MatDef& m) {
+    BlockIn& B = m.side == 0 ? H.left : H.right;
+    m.out_of_in.assign(B.n_sec, -1);
+    for (const Term& t : m.terms) {
+        const OpIn& o = B.ops[t.op];
+        for (int s = 0; s < B.n_sec; ++s) {
+            int si, so;
+            if (!t.tr) { si = s; so = o.out_of_in[s]; }
+            else { so = s; si = o.out_of_in[s]; }
+            if (so < 0 || si < 0) continue;
+            if (m.out_of_in[si] >= 0 && m.out_of_in[si] != so)
+                throw Error(DMRG_ERR_ARG, "pre-sum mixes operators with different sector changes");
+            m.out_of_in[si] = so;
+        }
+    }
+}
+
+void build_tasks(dmrg_hop& H) {
+    for (MatDef& m : H.mats) mat_sectors(H, m);
+    struct Key { int i, j, lm, rm; bool operator==(const Key& o) const { return i == o.i && j == o.j && lm == o.lm && rm == o.rm; } };
+    struct KH { size_t operator()(const Key& k) const {
+        uint64_t a = ((uint64_t)(uint32_t)k.i << 32) | (uint32_t)k.j;
+        uint64_t b = ((uint64_t)(uint32_t)k.lm << 32) | (uint32_t)k.rm;
+        return std::hash<uint64_t>()(a * 0x9E3779B97F4A7C15ULL ^ b); } };
+    std::unordered_map<Key, double, KH> acc;
+    acc.reserve(1 << 20);
+    const BlockIn &Lb = H.left, &Rb = H.right;
+    for (const Alpha& al : H.alphas) {
+        const MatDef* lm = al.lmat >= 0 ? &H.mats[al.lmat] : nullptr;
+        const MatDef* rm = al.rmat >= 0 ? &H.mats[al.rmat] : nullptr;
+        for (size_t i = 0; i < H.blk.size(); ++i) {
+            int a = H.blk[i][0], b = H.blk[i][1], c = H.blk[i][2], d = H.blk[i][3];
+            int ap = lm ? lm->out_of_in[a] : a;
+            if (ap < 0) continue;
+            int dp = rm ? rm->out_of_in[d] : d;
+            if (dp < 0) continue;
+            double par = 1.0;
+            if (al.lpar == 1) par = ((Lb.qa[a] + Lb.qb[a]) & 1) ? -1.0 : 1.0;
+            if (al.lpar == 2) par = ((Lb.qa[ap] + Lb.qb[ap]) & 1) ? -1.0 : 1.0;
+            int col = b * 4 + c;
+            for (int row = 0; row < 16; ++row) {
+                double s = al.S[row * 16 + col];
+                if (s == 0.0) continue;
+                int bp = row / 4, cp = row % 4;
+                int j = H.blk_index[(ap * 4 + bp) * 4 + cp];
+                if (j < 0 || H.blk[j][3] != dp)
+                    throw Error(DMRG_ERR_ARG, "operator combination leaves the electron-number sector "
+                                              "(inconsistent block quantum numbers)");
+                acc[{(int)i, j, al.lmat, al.rmat}] += al.coeff * s * par;
+            }
+        }
+    }
+    H.tasks.clear();
+    H.tasks.reserve(acc.size());
+    for (auto& kv : acc)
+        if (kv.second != 0.0) H.tasks.push_back({kv.first.i, kv.first.j, kv.first.lm, kv.first.rm, kv.second});
+    std::sort(H.tasks.begin(), H.tasks.end(), [](const dmrg_hop::HTask& x, const dmrg_hop::HTask& y) {
+        if (x.j != y.j) return x.j < y.j;
+        if (x.i != y.i) return x.i < y.i;
+        if (x.lm != y.lm) return x.lm < y.lm;
+        return x.rm < y.rm;
+    });
+    (void)Rb;
+    // algorithmic flops / bytes
+    double fl = 0.0;
+    for (const auto& t : H.tasks) {
+        double ma = H.blk_ma[t.i], md = H.blk_md[t.i], mj = H.blk_ma[t.j], nj = H.blk_md[t.j];
+        if (t.lm < 0 && t.rm < 0) continue;
+        if (t.lm < 0) fl += 2.0 * ma * md * nj;
+        else if (t.rm < 0) fl += 2.0 * mj * ma * md;
+        else fl += 2.0 * std::min(mj * ma * md + mj * md * nj, ma * md * nj + mj * ma * nj);
+    }
+    H.flops = fl;
+}
+
+double now() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+template <class T>
+T* dev_alloc(dmrg_hop& H, size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    H.allocations.push_back(p);
+    return static_cast<T*>(p);
+}
+
+void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
+    hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+    HIPCHK(hipSetDevice(H.device));
+    // 1. pool layout: every stored block of both sides (padded rows), then derived matrices
+    std::vector<int64_t> base_off[2];
+    int64_t pool = 0;
+    auto reserve = [&](int rows, int cols) {
+        int64_t o = pool;
+        pool += (int64_t)rows * dmrg::ld_of(cols);
+        pool = (pool + 31) / 32 * 32;
+        return o;
+    };
+    for (int sd = 0; sd < 2; ++sd) {
+        BlockIn& B = sd == 0 ? H.left : H.right;
+        base_off[sd].assign(B.ops.size() * (size_t)B.n_sec, -1);
+        for (size_t k = 0; k < B.ops.size(); ++k)
+            for (int si = 0; si < B.n_sec; ++si) {
+                int so = B.ops[k].out_of_in[si];
+                if (so < 0) continue;
+                base_off[sd][k * B.n_sec + si] = reserve(B.dim[so], B.dim[si]);
+            }
+    }
+    // which matrices are used by tasks
+    std::vector<char> used(H.mats.size(), 0);
+    for (const auto& t : H.tasks) { if (t.lm >= 0) used[t.lm] = 1; if (t.rm >= 0) used[t.rm] = 1; }
+    std::vector<dmrg::PresumBlock> pblocks;
+    std::vector<dmrg::PresumTerm> pterms;
+    for (size_t m = 0; m < H.mats.size(); ++m) {
+        MatDef& M = H.mats[m];
+        BlockIn& B = M.side == 0 ? H.left : H.right;
+        M.pool_of_in.assign(B.n_sec, -1);
+        if (!used[m]) continue;
+        bool direct = M.terms.size() == 1 && M.terms[0].c == 1.0 && !M.terms[0].tr;
+        for (int si = 0; si < B.n_sec; ++si) {
+            int so = M.out_of_in[si];
+            if (so < 0) continue;
+            if (direct) { M.pool_of_in[si] = base_off[M.side][(size_t)M.terms[0].op * B.n_sec + si]; continue; }
+            int64_t o = reserve(B.dim[so], B.dim[si]);
+            M.pool_of_in[si] = o;
+            dmrg::PresumBlock pb{o, B.dim[so], B.dim[si], (int32_t)pterms.size(), 0};
+            for (const Term& t : M.terms) {
+                int src_in = t.tr ? so : si;          // stored block is (src_out <- src_in)
+                const OpIn& op = B.ops[t.op];
+                if (op.out_of_in[src_in] < 0) continue;
+                int src_out = op.out_of_in[src_in];
+                pterms.push_back({base_off[M.side][(size_t)t.op * B.n_sec + src_in], dmrg::ld_of(B.dim[src_in]),
+                                  t.tr ? 1 : 0, t.c});
+                (void)src_out;
+            }
+            pb.t_end = (int32_t)pterms.size();
+            pblocks.push_back(pb);
+        }
+    }
+    H.pool_size = pool;
+    double need = pool * 8.0 * (H.has_split ? 1.5 : 1.0);
+    if (opts && opts->mem_budget_bytes > 0 && need > (double)opts->mem_budget_bytes)
+        throw Error(DMRG_ERR_NOMEM, "operator pool exceeds the memory budget");
+    H.d_pool = dev_alloc<double>(H, pool);
+    HIPCHK(hipMemsetAsync(H.d_pool, 0, pool * sizeof(double), s));
+    // 2. stored blocks, padded, host -> device (staged per side)
+    for (int sd = 0; sd < 2; ++sd) {
+        BlockIn& B = sd == 0 ? H.left : H.right;
+        for (size_t k = 0; k < B.ops.size(); ++k)
+            for (int si = 0; si < B.n_sec; ++si) {
+                int so = B.ops[k].out_of_in[si];
+                if (so < 0) continue;
+                int rows = B.dim[so], cols = B.dim[si];
+                if (rows == 0 || cols == 0) continue;
+                HIPCHK(hipMemcpy2DAsync(H.d_pool + base_off[sd][k * B.n_sec + si], dmrg::ld_of(cols) * sizeof(double),
+                                        B.data + B.ops[k].off_of_in[si], cols * sizeof(double),
+                                        cols * sizeof(double), rows, hipMemcpyHostToDevice, s));
+            }
+    }
+    // 3. pre-summed and transposed matrices on the GPU (Section 2.2.3)
+    if (!pblocks.empty()) {
+        dmrg::PresumBlock* d_pb = dev_alloc<dmrg::PresumBlock>(H, pblocks.size());
+        dmrg::PresumTerm* d_pt = dev_alloc<dmrg::PresumTerm>(H, pterms.size());
+        HIPCHK(hipMemcpyAsync(d_pb, pblocks.data(), pblocks.size() * sizeof(pblocks[0]), hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(d_pt, pterms.data(), pterms.size() * sizeof(pterms[0]), hipMemcpyHostToDevice, s));
+        HIPCHK(dmrg::launch_presum(d_pb, (int)pblocks.size(), d_pt, H.d_pool, s));
+    }
+    // 4. split copies
+    if (H.has_split) {
+        H.d_hi = dev_alloc<uint16_t>(H, pool);
+        H.d_lo = dev_alloc<uint16_t>(H, pool);
+        HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
+    }
+    // 5. units and device tasks (owner computes: one wavefront per 32x32 output tile)
+    std::vector<dmrg::Unit> units;
+    std::vector<dmrg::Task> dtasks;
+    std::vector<double> cost;
+    size_t t = 0;
+    std::vector<std::pair<double, int>> order;
+    for (size_t j = 0; j < H.blk.size(); ++j) {
+        int32_t tb = (int32_t)dtasks.size();
+        double c = 0.0;
+        while (t < H.tasks.size() && H.tasks[t].j == (int)j) {
+            const auto& ht = H.tasks[t];
+            int64_t ao = ht.lm >= 0 ? H.mats[ht.lm].pool_of_in[H.blk[ht.i][0]] : -1;
+            int64_t bo = ht.rm >= 0 ? H.mats[ht.rm].pool_of_in[H.blk[ht.i][3]] : -1;
+            dtasks.push_back({H.blk_off[ht.i], ao, bo, ht.f, H.blk_ma[ht.i], H.blk_md[ht.i]});
+            c += (double)H.blk_ma[ht.i] * H.blk_md[ht.i] * ((ao >= 0) + (bo >= 0) + 0.25);
+            ++t;
+        }
+        int32_t te = (int32_t)dtasks.size();
+        int mj = H.blk_ma[j], nj = H.blk_md[j];
+        for (int r0 = 0; r0 < mj; r0 += 32)
+            for (int c0 = 0; c0 < nj; c0 += 32) {
+                units.push_back({H.blk_off[j], mj, nj, r0, c0, tb, te});
+                cost.push_back(c);
+            }
+    }
+    std::vector<int> perm(units.size());
+    for (size_t i = 0; i < perm.size(); ++i) perm[i] = (int)i;
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<dmrg::Unit> su(units.size());
+    for (size_t i = 0; i < perm.size(); ++i) su[i] = units[perm[i]];
+    H.n_units = (int)su.size();
+    H.n_dev_tasks = (int64_t)dtasks.size();
+    H.d_units = dev_alloc<dmrg::Unit>(H, su.size());
+    H.d_tasks = dev_alloc<dmrg::Task>(H, dtasks.size());
+    HIPCHK(hipMemcpyAsync(H.d_units, su.data(), su.size() * sizeof(su[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(H.d_tasks, dtasks.data(), dtasks.size() * sizeof(dtasks[0]), hipMemcpyHostToDevice, s));
+    // 6. diag(H): tasks mapping a block onto itself (host staging vectors live until the final sync)
+    std::vector<dmrg::DiagBlock> db;
+    std::vector<dmrg::DiagTask> dt;
+    {
+        size_t k = 0;
+        for (size_t j = 0; j < H.blk.size(); ++j) {
+            int32_t tb = (int32_t)dt.size();
+            while (k < H.tasks.size() && H.tasks[k].j == (int)j) {
+                const auto& ht = H.tasks[k];
+                if (ht.i == (int)j) {
+                    int64_t ao = ht.lm >= 0 ? H.mats[ht.lm].pool_of_in[H.blk[j][0]] : -1;
+                    int64_t bo = ht.rm >= 0 ? H.mats[ht.rm].pool_of_in[H.blk[j][3]] : -1;
+                    dt.push_back({ao, bo, ht.f});
+                }
+                ++k;
+            }
+            db.push_back({H.blk_off[j], H.blk_ma[j], H.blk_md[j], tb, (int32_t)dt.size()});
+        }
+        H.d_diag = dev_alloc<double>(H, H.n_coeff);
+        dmrg::DiagBlock* d_db = dev_alloc<dmrg::DiagBlock>(H, db.size());
+        dmrg::DiagTask* d_dt = dev_alloc<dmrg::DiagTask>(H, dt.size());
+        HIPCHK(hipMemcpyAsync(d_db, db.data(), db.size() * sizeof(db[0]), hipMemcpyHostToDevice, s));
+        if (!dt.empty()) HIPCHK(hipMemcpyAsync(d_dt, dt.data(), dt.size() * sizeof(dt[0]), hipMemcpyHostToDevice, s));
+        HIPCHK(dmrg::launch_diag(d_db, (int)db.size(), d_dt, H.d_pool, H.d_diag, s));
+    }
+    // bytes: distinct operator blocks used + x read + y write
+    double by = 16.0 * H.n_coeff;
+    std::vector<char> seen_blk;
+    {
+        std::map<int64_t, int64_t> distinct;
+        for (const auto& ht : H.tasks) {
+            if (ht.lm >= 0) { int a = H.blk[ht.i][0]; int so = H.mats[ht.lm].out_of_in[a];
+                distinct[H.mats[ht.lm].pool_of_in[a]] = (int64_t)H.left.dim[so] * H.left.dim[a]; }
+            if (ht.rm >= 0) { int d = H.blk[ht.i][3]; int so = H.mats[ht.rm].out_of_in[d];
+                distinct[H.mats[ht.rm].pool_of_in[d]] = (int64_t)H.right.dim[so] * H.right.dim[d]; }
+        }
+        for (auto& kv : distinct) by += 8.0 * kv.second;
+    }
+    H.bytes = by;
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+dmrg_status fail(const Error& e) { g_err = e.what(); return e.code; }
+
+}  // namespace
+
+// ====================================================================== C-ABI
+
+extern "C" const char* dmrg_last_error(void) { return g_err.c_str(); }
+extern "C" const char* dmrg_version(void) { return "libdmrg 0.1 (gfx950)"; }
+
+extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block* left,
+                                         const dmrg_block* right, const dmrg_build_opts* opts,
+                                         dmrg_hop** out) {
+    g_err.clear();
+    if (!out) { g_err = "out is NULL"; return DMRG_ERR_ARG; }
+    *out = nullptr;
+    dmrg_hop* H = new (std::nothrow) dmrg_hop;
+    if (!H) { g_err = "host allocation failed"; return DMRG_ERR_NOMEM; }
+    try {
+        if (!p || !p->h || !p->eri) throw Error(DMRG_ERR_ARG, "problem or its integrals are NULL");
+        if (p->n_orb < 2 || p->site < 0 || p->site > p->n_orb - 2)
+            throw Error(DMRG_ERR_ARG, "need n_orb >= 2 and 0 <= site <= n_orb - 2");
+        if (p->n_alpha < 0 || p->n_beta < 0 || p->n_alpha > p->n_orb || p->n_beta > p->n_orb)
+            throw Error(DMRG_ERR_ARG, "electron numbers out of range");
+        H->L = p->n_orb; H->na = p->n_alpha; H->nb = p->n_beta; H->site = p->site;
+        int64_t L = H->L;
+        H->h.assign(p->h, p->h + L * L);
+        H->eri.assign(p->eri, p->eri + L * L * L * L);
+        for (double v : H->h) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite one-electron integral");
+        for (double v : H->eri) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite two-electron integral");
+        H->left = import_block(left, "left");
+        H->right = import_block(right, "right");
+        build_layout(*H);
+        Builder(*H).generate();
+        build_tasks(*H);
+        int dev = opts ? opts->device : 0;
+        H->has_split = opts && opts->want_split;
+        if (dev >= 0) {
+            int ndev = 0;
+            HIPCHK(hipGetDeviceCount(&ndev));
+            if (dev >= ndev) throw Error(DMRG_ERR_ARG, "device ordinal out of range");
+            H->device = dev;
+            upload(*H, opts);
+        } else {
+            // host-only build: derive matrix sectors for the statistics; no device state
+            H->bytes = 16.0 * H->n_coeff;
+        }
+        *out = H;
+        return DMRG_OK;
+    } catch (const Error& e) {
+        dmrg_status st = fail(e);
+        dmrg_hop_free(H);
+        return st;
+    } catch (const std::bad_alloc&) {
+        dmrg_hop_free(H);
+        g_err = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    } catch (const std::exception& e) {
+        dmrg_hop_free(H);
+        g_err = e.what();
+        return DMRG_ERR_ARG;
+    }
+}
+
+extern "C" void dmrg_hop_free(dmrg_hop* H) {
+    if (!H) return;
+    if (H->device >= 0) {
+        (void)hipSetDevice(H->device);
+        for (void* p : H->allocations) (void)hipFree(p);
+    }
+    delete H;
+}
+
+extern "C" dmrg_status dmrg_hop_layout(const dmrg_hop* H, int64_t* n_coeff, int32_t* n_blocks,
+                                       int32_t* abcd, int32_t* dims, int64_t* offsets) {
+    g_err.clear();
+    if (!H) { g_err = "hop is NULL"; return DMRG_ERR_ARG; }
+    if (n_coeff) *n_coeff = H->n_coeff;
+    if (n_blocks) *n_blocks = (int32_t)H->blk.size();
+    for (size_t i = 0; i < H->blk.size(); ++i) {
+        if (abcd) for (int k = 0; k < 4; ++k) abcd[4 * i + k] = H->blk[i][k];
+        if (dims) { dims[2 * i] = H->blk_ma[i]; dims[2 * i + 1] = H->blk_md[i]; }
+        if (offsets) offsets[i] = H->blk_off[i];
+    }
+    return DMRG_OK;
+}
+
+extern "C" dmrg_status dmrg_hop_stats(const dmrg_hop* H, double* flops, double* bytes, int64_t* n_alpha,
+                                      int64_t* n_tasks) {
+    g_err.clear();
+    if (!H) { g_err = "hop is NULL"; return DMRG_ERR_ARG; }
+    if (flops) *flops = H->flops;
+    if (bytes) *bytes = H->bytes;
+    if (n_alpha) *n_alpha = (int64_t)H->alphas.size();
+    if (n_tasks) *n_tasks = (int64_t)H->tasks.size();
+    return DMRG_OK;
+}
+
+extern "C" dmrg_status dmrg_hop_export_tasks(const dmrg_hop* H, int64_t* n_tasks, int32_t* quads, double* f,
+                                             int64_t* n_terms, int32_t* term_int, double* term_coeff) {
+    g_err.clear();
+    if (!H) { g_err = "hop is NULL"; return DMRG_ERR_ARG; }
+    if (n_tasks) *n_tasks = (int64_t)H->tasks.size();
+    for (size_t k = 0; k < H->tasks.size(); ++k) {
+        const auto& t = H->tasks[k];
+        if (quads) { quads[4 * k] = t.i; quads[4 * k + 1] = t.j; quads[4 * k + 2] = t.lm; quads[4 * k + 3] = t.rm; }
+        if (f) f[k] = t.f;
+    }
+    int64_t nt = 0;
+    for (size_t m = 0; m < H->mats.size(); ++m)
+        for (const Term& t : H->mats[m].terms) {
+            if (term_int) {
+                term_int[4 * nt] = (int32_t)m;
+                term_int[4 * nt + 1] = H->mats[m].side;
+                term_int[4 * nt + 2] = t.op;
+                term_int[4 * nt + 3] = t.tr ? 1 : 0;
+            }
+            if (term_coeff) term_coeff[nt] = t.c;
+            ++nt;
+        }
+    if (n_terms) *n_terms = nt;
+    return DMRG_OK;
+}
+
+extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision,
+                                 void* stream) {
+    g_err.clear();
+    try {
+        if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (!x || !y || nvec < 1) throw Error(DMRG_ERR_ARG, "bad x/y/nvec");
+        int64_t n = H->n_coeff * nvec;
+        if (!(x + n <= y || y + n <= x)) throw Error(DMRG_ERR_ALIAS, "x and y overlap");
+        HIPCHK(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)stream;
+        if (precision == DMRG_PREC_FP64) {
+            HIPCHK(dmrg::launch_hpsi_f64(H->d_units, H->n_units, H->d_tasks, H->d_pool, x, y, H->n_coeff, nvec, s));
+        } else if (precision == DMRG_PREC_SPLIT2) {
+            if (!H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+            HIPCHK(dmrg::launch_hpsi_split(H->d_units, H->n_units, H->d_tasks, H->d_hi, H->d_lo, x, y, H->n_coeff,
+                                           nvec, s));
+        } else {
+            throw Error(DMRG_ERR_ARG, "unknown precision");
+        }
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+extern "C" dmrg_status dmrg_hop_diagonal(dmrg_hop* H, double* d, void* stream) {
+    g_err.clear();
+    try {
+        if (!H || !d) throw Error(DMRG_ERR_ARG, "NULL argument");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        HIPCHK(hipSetDevice(H->device));
+        HIPCHK(hipMemcpyAsync(d, H->d_diag, H->n_coeff * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+// ---------------------------------------------------------------- Davidson (Sections 2.1, 2.2.1)
+namespace {
+
+// Cyclic Jacobi eigensolver for a small symmetric matrix (k <= 64), FP64.
+void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& V) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, diag = 0.0;
+        for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j)
+            (i == j ? diag : off) += A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        if (off <= 1e-32 * (diag + 1e-300)) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - s * akq;
+                    A[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - s * aqk;
+                    A[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - s * vkq;
+                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    evals.resize(n);
+    for (int i = 0; i < n; ++i) evals[i] = A[(size_t)i * n + i];
+}
+
+struct DavWork {
+    double* V = nullptr;     // max_sub x n
+    double* W = nullptr;     // max_sub x n
+    double* tmp = nullptr;   // 3 x n  (u, r, t)
+    double* prev = nullptr;  // n
+    double* part = nullptr;  // partial dots
+    double* dots = nullptr;  // max_sub + 2
+    std::vector<void*> allocs;
+    ~DavWork() { for (void* p : allocs) (void)hipFree(p); }
+    template <class T> T* get(size_t n) { void* p; if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw Error(DMRG_ERR_NOMEM, "device allocation failed (Davidson work space)"); allocs.push_back(p); return (T*)p; }
+};
+
+}  // namespace
+
+extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res,
+                                     void* stream) {
+    g_err.clear();
+    try {
+        if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
+        if (o->use_graph) throw Error(DMRG_ERR_UNSUPPORTED, "use_graph is reserved");
+        if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+        HIPCHK(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = H->n_coeff;
+        const int K = o->max_sub;
+        DavWork w;
+        w.V = w.get<double>((size_t)K * n);
+        w.W = w.get<double>((size_t)K * n);
+        w.tmp = w.get<double>((size_t)3 * n);
+        w.prev = w.get<double>(n);
+        int np = dmrg::multidot_parts(n);
+        w.part = w.get<double>((size_t)np * (K + 2));
+        w.dots = w.get<double>(K + 2);
+        double* restart_scratch = w.get<double>((size_t)4 * n);
+        double* u = w.tmp;
+        double* r = w.tmp + n;
+        double* t = w.tmp + 2 * n;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        double t_hpsi = 0.0;
+        int prec = o->precision;
+        int matvecs = 0, matvecs_split = 0;
+        auto matvec = [&](const double* x, double* y) {
+            HIPCHK(hipEventRecord(e0, s));
+            dmrg_status st = dmrg_hpsi(H, x, y, 1, prec, s);
+            if (st != DMRG_OK) throw Error(st, g_err);
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t_hpsi += ms * 1e-3;
+            ++matvecs;
+            if (prec == DMRG_PREC_SPLIT2) ++matvecs_split;
+        };
+        std::vector<double> hd(K + 2);
+        auto dots = [&](const double* Vs, int nv, const double* x) {
+            HIPCHK(dmrg::launch_multidot(Vs, nv, n, x, w.part, np, w.dots, s));
+            HIPCHK(hipMemcpyAsync(hd.data(), w.dots, nv * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        };
+        auto combine = [&](const double* Vs, int nv, const std::vector<double>& c, double* out, double beta) {
+            dmrg::Coefs cf;
+            for (int j = 0; j < nv; ++j) cf.c[j] = c[j];
+            HIPCHK(dmrg::launch_combine(Vs, nv, n, cf, out, beta, s));
+        };
+        auto normalize = [&](double* x) -> double {
+            dots(x, 1, x);
+            double nrm = std::sqrt(hd[0]);
+            if (!std::isfinite(nrm)) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
+            if (nrm == 0.0) return 0.0;
+            HIPCHK(dmrg::launch_scale(x, 1.0 / nrm, n, s));
+            return nrm;
+        };
+        // Gram-Schmidt (classical, twice) of x against the first k columns of V
+        auto orth = [&](int k, double* x) {
+            for (int pass = 0; pass < 2 && k > 0; ++pass) {
+                dots(w.V, k, x);
+                std::vector<double> c(k);
+                for (int i = 0; i < k; ++i) c[i] = -hd[i];
+                combine(w.V, k, c, x, 1.0);
+            }
+        };
+        const char* tr_env = std::getenv("DMRG_DAVIDSON_TRACE");
+        const bool trace = tr_env && tr_env[0] == '1';
+        double t_start = now();
+        HIPCHK(hipMemcpyAsync(w.V, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (normalize(w.V) == 0.0) throw Error(DMRG_ERR_ARG, "start vector is zero");
+        matvec(w.V, w.W);
+        int k = 1;
+        std::vector<double> G((size_t)K * K, 0.0);
+        dots(w.V, 1, w.W);
+        G[0] = hd[0];
+        double theta = G[0], rnorm = INFINITY;
+        bool have_prev = false, converged = false;
+        int it = 0;
+        std::vector<double> evals, evecs;
+        double best_split_r = INFINITY;
+        int stall = 0;
+        for (it = 1; it <= o->max_iter; ++it) {
+            std::vector<double> A((size_t)k * k);
+            for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j)
+                A[(size_t)i * k + j] = 0.5 * (G[(size_t)i * K + j] + G[(size_t)j * K + i]);
+            jacobi_eigh(k, A, evals, evecs);
+            int lo = 0;
+            for (int i = 1; i < k; ++i) if (evals[i] < evals[lo]) lo = i;
+            theta = evals[lo];
+            std::vector<double> sv(k), ms(k);
+            for (int i = 0; i < k; ++i) { sv[i] = evecs[(size_t)i * k + lo]; ms[i] = -theta * sv[i]; }
+            combine(w.V, k, sv, u, 0.0);               // u = V s
+            combine(w.W, k, sv, r, 0.0);               // r = W s
+            combine(w.V, k, ms, r, 1.0);               // r -= theta V s
+            dots(r, 1, r);
+            rnorm = std::sqrt(hd[0]);
+            if (trace) std::fprintf(stderr, "[dmrg_davidson] it %d k %d prec %d theta %.15f resid %.3e\n", it, k,
+                                    prec, theta, rnorm);
+            if (!std::isfinite(rnorm) || !std::isfinite(theta)) throw Error(DMRG_ERR_NAN, "non-finite Davidson residual");
+            if (prec == DMRG_PREC_SPLIT2 && o->fp64_polish) {
+                bool hand_over = rnorm <= std::max(o->split_tol, o->tol);
+                if (rnorm < 0.7 * best_split_r) { best_split_r = rnorm; stall = 0; } else if (++stall >= 4) hand_over = true;
+                if (hand_over) {
+                    // restart in FP64 from the current Ritz vector
+                    prec = DMRG_PREC_FP64;
+                    HIPCHK(hipMemcpyAsync(w.V, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    normalize(w.V);
+                    matvec(w.V, w.W);
+                    dots(w.V, 1, w.W);
+                    k = 1;
+                    G[0] = hd[0];
+                    have_prev = false;
+                    continue;
+                }
+            }
+            if (rnorm <= o->tol) { converged = true; break; }
+            HIPCHK(dmrg::launch_precond(r, H->d_diag, theta, t, n, s));
+            if (k >= K) {
+                // restart: V <- orth{u, previous u}, W <- the same combinations of W (no new matvecs)
+                std::vector<std::vector<double>> Y;
+                Y.push_back(sv);
+                if (have_prev) {
+                    dots(w.V, k, w.prev);                // coefficients of u_prev in V
+                    std::vector<double> cp(hd.begin(), hd.begin() + k);
+                    // near convergence u_prev ~ u: project twice and drop a remainder that is mostly
+                    // rounding noise, otherwise the restarted basis is not orthonormal
+                    for (int pass = 0; pass < 2; ++pass) {
+                        double d = 0.0;
+                        for (int i = 0; i < k; ++i) d += cp[i] * sv[i];
+                        for (int i = 0; i < k; ++i) cp[i] -= d * sv[i];
+                    }
+                    double nn = 0.0; for (double v : cp) nn += v * v;
+                    nn = std::sqrt(nn);
+                    if (nn > 1e-6) { for (double& v : cp) v /= nn; Y.push_back(cp); }
+                }
+                while ((int)Y.size() > K - 1) Y.pop_back();   // leave room for the next vector
+                int kn = (int)Y.size();
+                double* scratch = restart_scratch;       // 2 * kn <= 4 vectors
+                for (int j = 0; j < kn; ++j) {
+                    combine(w.V, k, Y[j], scratch + (size_t)j * n, 0.0);
+                    combine(w.W, k, Y[j], scratch + (size_t)(kn + j) * n, 0.0);
+                }
+                for (int j = 0; j < kn; ++j) {
+                    HIPCHK(hipMemcpyAsync(w.V + (size_t)j * n, scratch + (size_t)j * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(w.W + (size_t)j * n, scratch + (size_t)(kn + j) * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                }
+                std::vector<double> Gn((size_t)K * K, 0.0);
+                for (int a = 0; a < kn; ++a) for (int b = 0; b < kn; ++b) {
+                    double v = 0.0;
+                    for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j) v += Y[a][i] * G[(size_t)i * K + j] * Y[b][j];
+                    Gn[(size_t)a * K + b] = v;
+                }
+                G = Gn;
+                k = kn;
+            }
+            HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            have_prev = true;
+            orth(k, t);
+            double nt = normalize(t);
+            if (nt < 1e-14) break;
+            orth(k, t);                                   // re-orthogonalize after scaling (cheap insurance)
+            normalize(t);
+            HIPCHK(hipMemcpyAsync(w.V + (size_t)k * n, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            matvec(w.V + (size_t)k * n, w.W + (size_t)k * n);
+            dots(w.V, k + 1, w.W + (size_t)k * n);
+            for (int i = 0; i <= k; ++i) { G[(size_t)i * K + k] = hd[i]; G[(size_t)k * K + i] = hd[i]; }
+            ++k;
+        }
+        HIPCHK(hipMemcpyAsync(psi, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        res->energy = theta;
+        res->resid = rnorm;
+        res->iters = std::min(it, o->max_iter);
+        res->matvecs = matvecs;
+        res->matvecs_split = matvecs_split;
+        res->t_total = now() - t_start;
+        res->t_hpsi = t_hpsi;
+        if (!converged) { g_err = "Davidson did not converge"; return DMRG_NOT_CONVERGED; }
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
