@@ -213,10 +213,17 @@ struct dmrg_hop {
     double* d_pool = nullptr;
     uint16_t* d_hi = nullptr;
     uint16_t* d_lo = nullptr;
-    dmrg::Unit* d_units = nullptr;
     dmrg::Task* d_tasks = nullptr;
-    int n_units = 0;
+    dmrg::HpsiPlan plan{};
+    std::vector<dmrg::HpsiLaunch> launches;
+    std::vector<dmrg::HpsiPhase> phases;
+    std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
+    int n_items = 0;
     int64_t n_dev_tasks = 0;
+    int tune_max_tq = 8;       // widest output tile, in 16-column MFMA tiles (1..8)
+    int tune_items = 32768;    // target number of work items per H.psi launch
+    int tune_order = 2;        // item launch order (see build_plan)
+    int tune_phases = 1;       // 0: from the operator footprint and kCacheBudget
     double* d_diag = nullptr;
     std::vector<void*> allocations;
 };
@@ -583,6 +590,274 @@ T* dev_alloc(dmrg_hop& H, size_t n) {
     return static_cast<T*>(p);
 }
 
+template <class T>
+T* plan_alloc(dmrg_hop& H, size_t n) {
+    void* p = nullptr;
+    if (n == 0) n = 1;
+    HIPCHK(hipMalloc(&p, n * sizeof(T)));
+    H.plan_allocations.push_back(p);
+    return static_cast<T*>(p);
+}
+
+// Bytes of a matrix definition as stored in the pool (all its sector blocks, padded).
+double mat_bytes(const dmrg_hop& H, int m) {
+    if (m < 0) return 0.0;
+    const MatDef& M = H.mats[m];
+    const BlockIn& B = M.side == 0 ? H.left : H.right;
+    double b = 0.0;
+    for (int si = 0; si < B.n_sec; ++si) {
+        int so = M.out_of_in[si];
+        if (so >= 0) b += 8.0 * dmrg::rows_of(B.dim[so]) * dmrg::ld_of(B.dim[si]);
+    }
+    return b;
+}
+
+// Launch plan of H.psi: packed input layout, phases, work items, reductions (see internal.h).
+//  * Phases: the distinct (left matrix, right matrix) pairs are sorted by (right, left) and cut into
+//    groups of about kCacheBudget bytes of operators, so that the operators of one phase stay in
+//    the last-level cache while all target tiles are updated.
+//  * Items: in each phase every output tile (16 or 32 rows x up to 16 * tune_max_tq columns) gets
+//    the phase's tasks of its target block, cut into chunks of bounded MFMA cost (about
+//    tune_items items per matvec); a tile split over several chunks writes partial tiles that the
+//    phase's reduction adds in order.
+void build_plan(dmrg_hop& H, hipStream_t s) {
+    for (void* p : H.plan_allocations) (void)hipFree(p);
+    H.plan_allocations.clear();
+    constexpr double kCacheBudget = 96.0 * 1024 * 1024;
+    // packed input layout: every psi block padded to multiples of 32 in both directions
+    std::vector<dmrg::PackBlock> packs;
+    std::vector<int64_t> pk_off(H.blk.size());
+    int64_t psize = 0;
+    for (size_t i = 0; i < H.blk.size(); ++i) {
+        int pa = dmrg::ld_of(H.blk_ma[i]), pd = dmrg::ld_of(H.blk_md[i]);
+        pk_off[i] = psize;
+        packs.push_back({H.blk_off[i], psize, H.blk_ma[i], H.blk_md[i], pa, pd});
+        psize += (int64_t)pa * pd;
+    }
+    // phases over (left, right) matrix pairs
+    std::map<std::pair<int, int>, int> pair_phase;
+    {
+        std::vector<std::pair<int, int>> pairs;
+        for (const auto& t : H.tasks) pairs.push_back({t.rm, t.lm});
+        std::sort(pairs.begin(), pairs.end());
+        pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
+        std::vector<double> pb(pairs.size());
+        double total = 0.0;
+        for (size_t k = 0; k < pairs.size(); ++k) { pb[k] = mat_bytes(H, pairs[k].first) + mat_bytes(H, pairs[k].second); total += pb[k]; }
+        int np = H.tune_phases > 0 ? H.tune_phases : std::max(1, (int)std::ceil(total / kCacheBudget));
+        np = std::min<int>(np, std::max<size_t>(1, pairs.size()));
+        double cum = 0.0;
+        for (size_t k = 0; k < pairs.size(); ++k) {
+            int ph = std::min(np - 1, (int)(np * (cum + 0.5 * pb[k]) / std::max(total, 1.0)));
+            pair_phase[{pairs[k].second, pairs[k].first}] = ph;
+            cum += pb[k];
+        }
+        H.plan.n_phases = np;
+    }
+    const int np = H.plan.n_phases;
+    // device tasks, grouped per target block and phase (stable: source order kept inside)
+    std::vector<dmrg::Task> dtasks;
+    dtasks.reserve(H.tasks.size());
+    // trange[j * np + ph] = task range of target j in phase ph
+    std::vector<std::pair<int32_t, int32_t>> trange(H.blk.size() * np, {0, 0});
+    auto r16 = [](int m) { return (m + 15) / 16 * 16; };
+    {
+        size_t t = 0;
+        std::vector<std::vector<size_t>> by_phase(np);
+        for (size_t j = 0; j < H.blk.size(); ++j) {
+            for (auto& v : by_phase) v.clear();
+            while (t < H.tasks.size() && H.tasks[t].j == (int)j) {
+                by_phase[pair_phase[{H.tasks[t].lm, H.tasks[t].rm}]].push_back(t);
+                ++t;
+            }
+            for (int ph = 0; ph < np; ++ph) {
+                int32_t tb = (int32_t)dtasks.size();
+                for (size_t k : by_phase[ph]) {
+                    const auto& ht = H.tasks[k];
+                    int64_t ao = ht.lm >= 0 ? H.mats[ht.lm].pool_of_in[H.blk[ht.i][0]] : -1;
+                    int64_t bo = ht.rm >= 0 ? H.mats[ht.rm].pool_of_in[H.blk[ht.i][3]] : -1;
+                    const int ma = H.blk_ma[ht.i], md = H.blk_md[ht.i];
+                    dtasks.push_back({pk_off[ht.i], ao, bo, ht.f, dmrg::ld_of(ma), dmrg::ld_of(md), r16(ma), r16(md)});
+                }
+                trange[j * np + ph] = {tb, (int32_t)dtasks.size()};
+            }
+        }
+    }
+    auto task_cost = [&](const dmrg::Task& T, int tp, int tq) -> double {
+        double c = 8.0;                                   // per-task overhead
+        if (T.a_off < 0 && T.b_off < 0) return c + 1.0;
+        if (T.b_off < 0) return c + (double)(T.ka / 4) * tp * tq;
+        if (T.a_off < 0) return c + (double)(T.kd / 4) * tp * tq;
+        return c + (double)(T.kd / 16) * (tp * (T.ka / 4) + 4.0 * tp * tq);
+    };
+    struct Tile { int j, r0, c0, tp, tq; };
+    std::vector<Tile> tiles;
+    double total = 0.0, max_task = 0.0;
+    const int tile_cols = 16 * H.tune_max_tq;
+    for (size_t j = 0; j < H.blk.size(); ++j) {
+        int mj = H.blk_ma[j], nj = H.blk_md[j];
+        for (int r0 = 0; r0 < mj; r0 += dmrg::kTileRows)
+            for (int c0 = 0; c0 < nj; c0 += tile_cols) {
+                int tp = mj - r0 <= 16 ? 1 : 2;
+                int tq = (std::min(tile_cols, nj - c0) + 15) / 16;
+                for (int32_t t = trange[j * np].first; t < trange[j * np + np - 1].second; ++t) {
+                    double tc = task_cost(dtasks[t], tp, tq);
+                    total += tc;
+                    max_task = std::max(max_task, tc);
+                }
+                tiles.push_back({(int)j, r0, c0, tp, tq});
+            }
+    }
+    const double cmax = std::max({total / std::max(1, H.tune_items), max_task, 256.0});
+    std::vector<dmrg::Item> all_items;
+    std::vector<dmrg::Reduce> all_red;
+    H.launches.clear();
+    H.phases.clear();
+    int64_t part_max = 0;
+    for (int ph = 0; ph < np; ++ph) {
+        std::vector<dmrg::Item> items;
+        std::vector<double> icost;
+        std::vector<int> iclass, igroup;
+        std::vector<dmrg::Reduce> reduces;
+        int64_t part_size = 0;
+        for (const Tile& T : tiles) {
+            const int j = T.j;
+            const auto tr = trange[j * np + ph];
+            if (tr.first == tr.second) continue;
+            std::vector<std::pair<int32_t, int32_t>> chunks;
+            std::vector<double> ccost;
+            int32_t b = tr.first;
+            double c = 0.0;
+            for (int32_t t = tr.first; t < tr.second; ++t) {
+                double tc = task_cost(dtasks[t], T.tp, T.tq);
+                if (c + tc > cmax && t > b) { chunks.push_back({b, t}); ccost.push_back(c); b = t; c = 0.0; }
+                c += tc;
+            }
+            chunks.push_back({b, tr.second});
+            ccost.push_back(c);
+            const int cls = (T.tp - 1) * 8 + (T.tq - 1);
+            const int tm = 16 * T.tp, tn = 16 * T.tq;
+            const int grp = H.blk[j][0];                     // target left sector: shares left operators
+            if (chunks.size() == 1) {
+                items.push_back({H.blk_off[j], -1, H.blk_ma[j], H.blk_md[j], T.r0, T.c0, chunks[0].first, chunks[0].second});
+                icost.push_back(ccost[0]);
+                iclass.push_back(cls);
+                igroup.push_back(grp);
+            } else {
+                reduces.push_back({H.blk_off[j], part_size, H.blk_ma[j], H.blk_md[j], T.r0, T.c0, tm, tn,
+                                   (int32_t)chunks.size(), 0});
+                for (size_t k = 0; k < chunks.size(); ++k) {
+                    items.push_back({H.blk_off[j], part_size, H.blk_ma[j], H.blk_md[j], T.r0, T.c0, chunks[k].first,
+                                     chunks[k].second});
+                    part_size += (int64_t)tm * tn;
+                    icost.push_back(ccost[k]);
+                    iclass.push_back(cls);
+                    igroup.push_back(grp);
+                }
+            }
+        }
+        part_max = std::max(part_max, part_size);
+        // Launch order inside a tile class. 0: heaviest first. 1: target order. 2: XCD-aware -- items
+        // whose targets share the left sector (hence the left operators) are placed at positions of
+        // the same residue mod 8, i.e. on the same XCD and its L2, groups balanced over the 8 XCDs.
+        std::vector<int> perm(items.size());
+        for (size_t i = 0; i < perm.size(); ++i) perm[i] = (int)i;
+        std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+            if (iclass[a] != iclass[b]) return iclass[a] < iclass[b];
+            if (H.tune_order == 0) return icost[a] > icost[b];
+            if (H.tune_order == 2 && igroup[a] != igroup[b]) return igroup[a] < igroup[b];
+            return false;
+        });
+        if (H.tune_order == 2) {
+            const int nx = 8;
+            std::vector<int> out;
+            out.reserve(perm.size());
+            size_t c0 = 0;
+            while (c0 < perm.size()) {
+                size_t c1 = c0;
+                while (c1 < perm.size() && iclass[perm[c1]] == iclass[perm[c0]]) ++c1;
+                std::map<int, std::vector<int>> grp;
+                std::map<int, double> gcost;
+                for (size_t i = c0; i < c1; ++i) { grp[igroup[perm[i]]].push_back(perm[i]); gcost[igroup[perm[i]]] += icost[perm[i]]; }
+                std::vector<std::pair<double, int>> order;
+                for (auto& kv : gcost) order.push_back({-kv.second, kv.first});
+                std::sort(order.begin(), order.end());
+                std::vector<double> load(nx, 0.0);
+                std::vector<std::vector<int>> lane(nx);
+                for (auto& og : order) {
+                    int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                    load[x] -= og.first;
+                    for (int it : grp[og.second]) lane[x].push_back(it);
+                }
+                std::vector<size_t> pos(nx, 0);
+                size_t left = c1 - c0;
+                for (size_t p = 0; left > 0; ++p) {
+                    int x = (int)(p % nx);
+                    if (pos[x] < lane[x].size()) { out.push_back(lane[x][pos[x]++]); --left; }
+                    else {
+                        int best = -1;
+                        size_t rem = 0;
+                        for (int y = 0; y < nx; ++y) if (lane[y].size() - pos[y] > rem) { rem = lane[y].size() - pos[y]; best = y; }
+                        out.push_back(lane[best][pos[best]++]);
+                        --left;
+                    }
+                }
+                c0 = c1;
+            }
+            perm = out;
+        }
+        dmrg::HpsiPhase P;
+        P.launch_begin = (int)H.launches.size();
+        const int base = (int)all_items.size();
+        for (size_t i = 0; i < perm.size(); ++i) {
+            all_items.push_back(items[perm[i]]);
+            const int cls = iclass[perm[i]];
+            if (H.launches.size() == (size_t)P.launch_begin || H.launches.back().cls != cls)
+                H.launches.push_back({cls, base + (int)i, 0});
+            H.launches.back().item_count++;
+        }
+        P.launch_end = (int)H.launches.size();
+        P.reduce_begin = (int)all_red.size();
+        for (const auto& r : reduces) all_red.push_back(r);
+        P.reduce_end = (int)all_red.size();
+        H.phases.push_back(P);
+    }
+    H.n_items = (int)all_items.size();
+    H.n_dev_tasks = (int64_t)dtasks.size();
+    if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
+        if (e[0] == '1')
+            std::fprintf(stderr, "[dmrg plan] phases %d items %zu launches %zu reduces %zu partial %.1f MB packed %.1f MB\n",
+                         np, all_items.size(), H.launches.size(), all_red.size(), part_max * 8e-6, psize * 8e-6);
+    dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, all_items.size());
+    dmrg::Task* d_tasks = plan_alloc<dmrg::Task>(H, dtasks.size());
+    dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, all_red.size());
+    dmrg::PackBlock* d_packs = plan_alloc<dmrg::PackBlock>(H, packs.size());
+    HIPCHK(hipMemcpyAsync(d_items, all_items.data(), all_items.size() * sizeof(all_items[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_tasks, dtasks.data(), dtasks.size() * sizeof(dtasks[0]), hipMemcpyHostToDevice, s));
+    if (!all_red.empty())
+        HIPCHK(hipMemcpyAsync(d_red, all_red.data(), all_red.size() * sizeof(all_red[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_packs, packs.data(), packs.size() * sizeof(packs[0]), hipMemcpyHostToDevice, s));
+    H.d_tasks = d_tasks;
+    H.plan.items = d_items;
+    H.plan.reduces = d_red;
+    H.plan.tasks = d_tasks;
+    H.plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1) * dmrg::kPartialVecs);
+    H.plan.partial_size = part_max;
+    H.plan.launches = H.launches.data();
+    H.plan.phases = H.phases.data();
+    H.plan.packs = d_packs;
+    H.plan.n_packs = (int)packs.size();
+    H.plan.packed_size = psize;
+    H.plan.xp = plan_alloc<double>(H, (size_t)psize * dmrg::kPartialVecs);
+    if (H.has_split) {
+        H.plan.xr_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        H.plan.xr_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        H.plan.xt_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        H.plan.xt_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
 void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
     HIPCHK(hipSetDevice(H.device));
@@ -591,7 +866,7 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     int64_t pool = 0;
     auto reserve = [&](int rows, int cols) {
         int64_t o = pool;
-        pool += (int64_t)rows * dmrg::ld_of(cols);
+        pool += (int64_t)dmrg::rows_of(rows) * dmrg::ld_of(cols);
         pool = (pool + 31) / 32 * 32;
         return o;
     };
@@ -670,43 +945,9 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
         H.d_lo = dev_alloc<uint16_t>(H, pool);
         HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
     }
-    // 5. units and device tasks (owner computes: one wavefront per 32x32 output tile)
-    std::vector<dmrg::Unit> units;
-    std::vector<dmrg::Task> dtasks;
-    std::vector<double> cost;
-    size_t t = 0;
-    std::vector<std::pair<double, int>> order;
-    for (size_t j = 0; j < H.blk.size(); ++j) {
-        int32_t tb = (int32_t)dtasks.size();
-        double c = 0.0;
-        while (t < H.tasks.size() && H.tasks[t].j == (int)j) {
-            const auto& ht = H.tasks[t];
-            int64_t ao = ht.lm >= 0 ? H.mats[ht.lm].pool_of_in[H.blk[ht.i][0]] : -1;
-            int64_t bo = ht.rm >= 0 ? H.mats[ht.rm].pool_of_in[H.blk[ht.i][3]] : -1;
-            dtasks.push_back({H.blk_off[ht.i], ao, bo, ht.f, H.blk_ma[ht.i], H.blk_md[ht.i]});
-            c += (double)H.blk_ma[ht.i] * H.blk_md[ht.i] * ((ao >= 0) + (bo >= 0) + 0.25);
-            ++t;
-        }
-        int32_t te = (int32_t)dtasks.size();
-        int mj = H.blk_ma[j], nj = H.blk_md[j];
-        for (int r0 = 0; r0 < mj; r0 += 32)
-            for (int c0 = 0; c0 < nj; c0 += 32) {
-                units.push_back({H.blk_off[j], mj, nj, r0, c0, tb, te});
-                cost.push_back(c);
-            }
-    }
-    std::vector<int> perm(units.size());
-    for (size_t i = 0; i < perm.size(); ++i) perm[i] = (int)i;
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<dmrg::Unit> su(units.size());
-    for (size_t i = 0; i < perm.size(); ++i) su[i] = units[perm[i]];
-    H.n_units = (int)su.size();
-    H.n_dev_tasks = (int64_t)dtasks.size();
-    H.d_units = dev_alloc<dmrg::Unit>(H, su.size());
-    H.d_tasks = dev_alloc<dmrg::Task>(H, dtasks.size());
-    HIPCHK(hipMemcpyAsync(H.d_units, su.data(), su.size() * sizeof(su[0]), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(H.d_tasks, dtasks.data(), dtasks.size() * sizeof(dtasks[0]), hipMemcpyHostToDevice, s));
-    // 6. diag(H): tasks mapping a block onto itself (host staging vectors live until the final sync)
+    // 5. packed input layout, work items and launch plan
+    build_plan(H, s);
+    // 7. diag(H): tasks mapping a block onto itself (host staging vectors live until the final sync)
     std::vector<dmrg::DiagBlock> db;
     std::vector<dmrg::DiagTask> dt;
     {
@@ -783,6 +1024,10 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         Builder(*H).generate();
         build_tasks(*H);
         int dev = opts ? opts->device : 0;
+        if (const char* e = std::getenv("DMRG_MAX_TQ")) H->tune_max_tq = std::max(1, std::min(8, std::atoi(e)));
+        if (const char* e = std::getenv("DMRG_ITEMS")) H->tune_items = std::max(256, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_ORDER")) H->tune_order = std::max(0, std::min(2, std::atoi(e)));
+        if (const char* e = std::getenv("DMRG_PHASES")) H->tune_phases = std::max(0, std::atoi(e));
         H->has_split = opts && opts->want_split;
         if (dev >= 0) {
             int ndev = 0;
@@ -816,6 +1061,7 @@ extern "C" void dmrg_hop_free(dmrg_hop* H) {
     if (H->device >= 0) {
         (void)hipSetDevice(H->device);
         for (void* p : H->allocations) (void)hipFree(p);
+        for (void* p : H->plan_allocations) (void)hipFree(p);
     }
     delete H;
 }
@@ -882,14 +1128,18 @@ extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_
         if (!(x + n <= y || y + n <= x)) throw Error(DMRG_ERR_ALIAS, "x and y overlap");
         HIPCHK(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)stream;
-        if (precision == DMRG_PREC_FP64) {
-            HIPCHK(dmrg::launch_hpsi_f64(H->d_units, H->n_units, H->d_tasks, H->d_pool, x, y, H->n_coeff, nvec, s));
-        } else if (precision == DMRG_PREC_SPLIT2) {
-            if (!H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
-            HIPCHK(dmrg::launch_hpsi_split(H->d_units, H->n_units, H->d_tasks, H->d_hi, H->d_lo, x, y, H->n_coeff,
-                                           nvec, s));
-        } else {
-            throw Error(DMRG_ERR_ARG, "unknown precision");
+        if (precision != DMRG_PREC_FP64 && precision != DMRG_PREC_SPLIT2) throw Error(DMRG_ERR_ARG, "unknown precision");
+        if (precision == DMRG_PREC_SPLIT2 && !H->has_split)
+            throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+        const int step = dmrg::kPartialVecs;   // packed-input and partial buffers hold this many vectors
+        for (int v0 = 0; v0 < nvec; v0 += step) {
+            const int nv = std::min(step, nvec - v0);
+            const double* xv = x + (int64_t)v0 * H->n_coeff;
+            double* yv = y + (int64_t)v0 * H->n_coeff;
+            if (precision == DMRG_PREC_FP64)
+                HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
+            else
+                HIPCHK(dmrg::launch_hpsi_split(H->plan, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
         }
         return DMRG_OK;
     } catch (const Error& e) {

@@ -1,29 +1,66 @@
 // Device-side data structures shared by the host driver (host.cpp) and the HIP kernels
 // (kernels.hip). Plain structs, no HIP types, so host-only builds can include it.
+//
+// Padded layouts. Every operator block in the pool is stored row-major with its rows padded to a
+// multiple of 16 and its leading dimension (columns) padded to a multiple of 32, zero-filled.
+// Before each H.psi the input vector is packed into the same kind of layout (rows and columns of
+// every psi block padded to multiples of 32). MFMA tiles therefore never need bounds masks.
 #pragma once
 #include <stdint.h>
 
 namespace dmrg {
 
+constexpr int kRowPad = 16;    // row padding of pool blocks (MFMA tile height)
+constexpr int kLd = 32;        // leading-dimension padding of pool blocks and packed psi blocks
+inline int32_t ld_of(int32_t m) { return (m + kLd - 1) / kLd * kLd; }
+inline int32_t rows_of(int32_t m) { return (m + kRowPad - 1) / kRowPad * kRowPad; }
+
 // One sector-GEMM contribution to an output psi block (Eq. dgemm, Section 2.2.1):
 //   Y_target += f * A . X_source . B^T
-// A (m_a' x m_a) and B (m_d' x m_d) live in the operator pool, row-major with leading dimension
-// ld(m) = round_up(m, kLd). a_off / b_off < 0 mean identity.
+// A (m_a' x m_a) and B (m_d' x m_d) live in the operator pool (padded layout); a_off / b_off < 0
+// mean identity. X is read from the packed input (pa x pd, row-major, ld = pd; and for the split
+// path also its transpose, ld = pa).
 struct Task {
-    int64_t x_off;   // element offset of the source block in x
+    int64_t x_off;   // element offset of the packed source block
     int64_t a_off;   // pool offset of A, or -1
     int64_t b_off;   // pool offset of B, or -1
     double  f;
-    int32_t m_a;     // source rows
-    int32_t m_d;     // source cols
+    int32_t pa;      // source rows padded to 32 (leading dimension of A and of the packed X^T)
+    int32_t pd;      // source cols padded to 32 (leading dimension of B and of the packed X)
+    int32_t ka;      // source rows padded to 16 (FP64 reduction bound over m_a)
+    int32_t kd;      // source cols padded to 16 (FP64 reduction bound over m_d)
 };
 
-// One output tile owned by one wavefront: rows [r0, r0 + TM) x cols [c0, c0 + TN) of a target block.
-struct Unit {
+// One wavefront's work: a contiguous range of the tasks writing one output tile of a target block
+// (rows [r0, r0 + 16*TP) x cols [c0, c0 + 16*TQ)). slot < 0: the item owns the whole tile and stores
+// it into y; otherwise it stores a partial tile into partial slot `slot` and a reduction item adds
+// the slots of the tile in a fixed order (deterministic, no atomics).
+struct Item {
     int64_t y_off;
+    int64_t part_off;        // < 0: store into y; else offset of this item's partial tile (tm x tn)
     int32_t m_ap, m_dp;
     int32_t r0, c0;
     int32_t t_begin, t_end;
+};
+constexpr int kTileRows = 32;                  // max rows of a tile (TP <= 2)
+constexpr int kPartialVecs = 4;                // vectors per launch
+
+struct Reduce {
+    int64_t y_off;
+    int64_t part_off;        // first partial tile; the tile's n_parts partials follow contiguously
+    int32_t m_ap, m_dp;
+    int32_t r0, c0;
+    int32_t tm, tn;          // tile extent
+    int32_t n_parts;
+    int32_t pad;
+};
+
+// Packing of one psi block into the padded input layout.
+struct PackBlock {
+    int64_t src_off;         // offset in the caller's x (m_a x m_d, row-major)
+    int64_t dst_off;         // offset in the packed buffers
+    int32_t m_a, m_d;
+    int32_t pa, pd;
 };
 
 // Pre-summed / transposed operator block (Section 2.2.3): out = sum_k coeff_k * src_k (or src_k^T).
@@ -50,23 +87,45 @@ struct DiagBlock {
     int32_t t_begin, t_end;
 };
 
-constexpr int kLd = 8;     // leading-dimension alignment of pool blocks (64 B in FP64, 16 B in BF16)
-inline int32_t ld_of(int32_t m) { return (m + kLd - 1) / kLd * kLd; }
-
 }  // namespace dmrg
 
 #ifndef DMRG_HOST_ONLY
 #include <hip/hip_runtime.h>
 namespace dmrg {
+// H.psi launch plan. Work items are grouped by phase (a subset of the operator combinations whose
+// operators fit in the last-level cache) and, inside a phase, by tile class
+// c = (TP - 1) * 8 + (TQ - 1), TP in 1..2, TQ in 1..8. y is zeroed first; every item and every
+// reduction then adds its tile into y (each tile has one owner per phase, phases run in order).
+constexpr int kClasses = 16;
+struct HpsiLaunch { int cls, item_begin, item_count; };
+struct HpsiPhase { int launch_begin, launch_end, reduce_begin, reduce_end; };
+struct HpsiPlan {
+    const Item* items;            // device
+    const Reduce* reduces;        // device
+    const Task* tasks;            // device
+    double* partial;              // device, partial_size * kPartialVecs doubles
+    int64_t partial_size;         // elements of the partial tiles of one vector (largest phase)
+    const HpsiLaunch* launches;   // host
+    const HpsiPhase* phases;      // host
+    int n_phases;
+    const PackBlock* packs;       // device
+    int n_packs;
+    int64_t packed_size;          // elements of one packed vector
+    double* xp;                   // packed FP64 input, kPartialVecs vectors
+    uint16_t* xr_hi;              // packed BF16 split input, row-major
+    uint16_t* xr_lo;
+    uint16_t* xt_hi;              // packed BF16 split input, transposed
+    uint16_t* xt_lo;
+};
+
 // Launchers (kernels.hip). All asynchronous on `s`.
 hipError_t launch_presum(const PresumBlock* blocks, int n_blocks, const PresumTerm* terms,
                          double* pool, hipStream_t s);
 hipError_t launch_split(const double* pool, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t s);
-hipError_t launch_hpsi_f64(const Unit* units, int n_units, const Task* tasks, const double* pool,
-                           const double* x, double* y, int64_t n_coeff, int nvec, hipStream_t s);
-hipError_t launch_hpsi_split(const Unit* units, int n_units, const Task* tasks, const uint16_t* hi,
-                             const uint16_t* lo, const double* x, double* y, int64_t n_coeff,
-                             int nvec, hipStream_t s);
+hipError_t launch_hpsi_f64(const HpsiPlan& plan, const double* pool, const double* x, double* y,
+                           int64_t n_coeff, int nvec, hipStream_t s);
+hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
+                             double* y, int64_t n_coeff, int nvec, hipStream_t s);
 hipError_t launch_diag(const DiagBlock* blocks, int n_blocks, const DiagTask* tasks,
                        const double* pool, double* d, hipStream_t s);
 // Davidson vector kernels (FP64).

@@ -25,8 +25,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x4 __attribute__((ext_vector_type(4)));
 
-constexpr int TP = 2;   // 16-row tiles per wavefront
-constexpr int TQ = 2;   // 16-col tiles per wavefront
+// Register budget per tile class: two wavefronts per SIMD where that fits without spills.
+constexpr int min_waves_f64(int tp, int tq) { return tp * tq <= 8 ? 2 : 1; }
+constexpr int min_waves_split(int tp, int tq) { return tp * tq <= 12 ? 2 : 1; }
 
 __device__ __forceinline__ int ldo(int m) { return (m + kLd - 1) / kLd * kLd; }
 
@@ -93,143 +94,254 @@ hipError_t launch_split(const double* pool, int64_t n, uint16_t* hi, uint16_t* l
     return hipGetLastError();
 }
 
-// ------------------------------------------------------------------ FP64 sector GEMMs
-__global__ __launch_bounds__(64) void k_hpsi_f64(const Unit* __restrict__ units, const Task* __restrict__ tasks,
-                                                 const double* __restrict__ pool, const double* __restrict__ xall,
-                                                 double* __restrict__ yall, int64_t n_coeff) {
-    const Unit U = units[blockIdx.x];
-    const double* __restrict__ x = xall + (int64_t)blockIdx.y * n_coeff;
-    double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
-    const int lane = threadIdx.x;
-    const int li = lane & 15, g = lane >> 4;
-    f64x4 acc[TP][TQ];
-#pragma unroll
-    for (int p = 0; p < TP; ++p)
-#pragma unroll
-        for (int q = 0; q < TQ; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-    for (int t = U.t_begin; t < U.t_end; ++t) {
-        const Task T = tasks[t];
-        const double* __restrict__ X = x + T.x_off;
-        const int ma = T.m_a, md = T.m_d;
-        const double f = T.f;
-        if (T.a_off < 0 && T.b_off < 0) {
-            // Y += f X (same block shape)
-#pragma unroll
-            for (int p = 0; p < TP; ++p)
-#pragma unroll
-                for (int q = 0; q < TQ; ++q)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = U.r0 + 16 * p + g + 4 * v, col = U.c0 + 16 * q + li;
-                        if (row < ma && col < md) acc[p][q][v] += f * X[(int64_t)row * md + col];
-                    }
-        } else if (T.b_off < 0) {
-            // Y += f A X : rows of Y from A, columns from X (m_d' = m_d)
-            const double* __restrict__ A = pool + T.a_off;
-            const int lda = ldo(ma);
-            for (int k0 = 0; k0 < ma; k0 += 4) {
-                const int k = k0 + g;
-                double av[TP], bv[TQ];
-#pragma unroll
-                for (int p = 0; p < TP; ++p) {
-                    const int row = U.r0 + 16 * p + li;
-                    av[p] = (row < U.m_ap && k < ma) ? f * A[(int64_t)row * lda + k] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < TQ; ++q) {
-                    const int col = U.c0 + 16 * q + li;
-                    bv[q] = (k < ma && col < md) ? X[(int64_t)k * md + col] : 0.0;
-                }
-#pragma unroll
-                for (int p = 0; p < TP; ++p)
-#pragma unroll
-                    for (int q = 0; q < TQ; ++q)
-                        acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
-            }
-        } else if (T.a_off < 0) {
-            // Y += f X B^T (m_a' = m_a)
-            const double* __restrict__ B = pool + T.b_off;
-            const int ldb = ldo(md);
-            for (int k0 = 0; k0 < md; k0 += 4) {
-                const int k = k0 + g;
-                double av[TP], bv[TQ];
-#pragma unroll
-                for (int p = 0; p < TP; ++p) {
-                    const int row = U.r0 + 16 * p + li;
-                    av[p] = (row < ma && k < md) ? X[(int64_t)row * md + k] : 0.0;
-                }
-#pragma unroll
-                for (int q = 0; q < TQ; ++q) {
-                    const int col = U.c0 + 16 * q + li;
-                    bv[q] = (col < U.m_dp && k < md) ? f * B[(int64_t)col * ldb + k] : 0.0;
-                }
-#pragma unroll
-                for (int p = 0; p < TP; ++p)
-#pragma unroll
-                    for (int q = 0; q < TQ; ++q)
-                        acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[p], bv[q], acc[p][q], 0, 0, 0);
-            }
-        } else {
-            // Y += f A X B^T, chained through registers over 16-column chunks of X
-            const double* __restrict__ A = pool + T.a_off;
-            const double* __restrict__ B = pool + T.b_off;
-            const int lda = ldo(ma), ldb = ldo(md);
-            for (int j0 = 0; j0 < md; j0 += 16) {
-                f64x4 tt[TP];
-#pragma unroll
-                for (int p = 0; p < TP; ++p) tt[p] = f64x4{0.0, 0.0, 0.0, 0.0};
-                const int jx = j0 + li;
-                for (int k0 = 0; k0 < ma; k0 += 4) {
-                    const int k = k0 + g;
-                    const double xa = (k < ma && jx < md) ? X[(int64_t)k * md + jx] : 0.0;
-#pragma unroll
-                    for (int p = 0; p < TP; ++p) {
-                        const int row = U.r0 + 16 * p + li;
-                        const double ab = (row < U.m_ap && k < ma) ? A[(int64_t)row * lda + k] : 0.0;
-                        tt[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(xa, ab, tt[p], 0, 0, 0);
-                    }
-                }
-                // tt[p][v] = T'[row = r0 + 16p + li][j = j0 + g + 4v]
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int j = j0 + g + 4 * v;
-                    double bb[TQ];
-#pragma unroll
-                    for (int q = 0; q < TQ; ++q) {
-                        const int col = U.c0 + 16 * q + li;
-                        bb[q] = (col < U.m_dp && j < md) ? f * B[(int64_t)col * ldb + j] : 0.0;
-                    }
-#pragma unroll
-                    for (int p = 0; p < TP; ++p)
-#pragma unroll
-                        for (int q = 0; q < TQ; ++q)
-                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(tt[p][v], bb[q], acc[p][q], 0, 0, 0);
-                }
-            }
+// ------------------------------------------------------------------ input packing (Eq. wf_sec blocks)
+// xp: FP64, every block pa x pd row-major (zero padding). Split path: BF16 hi/lo of the same block
+// row-major (xr) and transposed (xt, pd x pa).
+__global__ void k_pack(const PackBlock* __restrict__ packs, const double* __restrict__ xall, int64_t n_coeff,
+                       int64_t psize, double* __restrict__ xpall, uint16_t* __restrict__ xrh, uint16_t* __restrict__ xrl,
+                       uint16_t* __restrict__ xth, uint16_t* __restrict__ xtl, int split) {
+    const PackBlock P = packs[blockIdx.x];
+    const double* __restrict__ x = xall + (int64_t)blockIdx.y * n_coeff + P.src_off;
+    const int64_t vo = (int64_t)blockIdx.y * psize + P.dst_off;
+    const int n = P.pa * P.pd;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int i = e / P.pd, j = e - (e / P.pd) * P.pd;
+        const double v = (i < P.m_a && j < P.m_d) ? x[(int64_t)i * P.m_d + j] : 0.0;
+        xpall[vo + e] = v;
+        if (split) {
+            unsigned short h, l;
+            split2(v, h, l);
+            xrh[vo + e] = h;
+            xrl[vo + e] = l;
+            const int64_t t = vo + (int64_t)j * P.pa + i;
+            xth[t] = h;
+            xtl[t] = l;
         }
     }
+}
+
+// ------------------------------------------------------------------ tile store (direct or partial tile)
+template <int TP, int TQ, class Acc>
+__device__ __forceinline__ void store_tile(const Item& I, double* __restrict__ y, double* __restrict__ part,
+                                           const Acc& acc, int li, int g, bool f64_layout) {
 #pragma unroll
     for (int p = 0; p < TP; ++p)
 #pragma unroll
         for (int q = 0; q < TQ; ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = U.r0 + 16 * p + g + 4 * v, col = U.c0 + 16 * q + li;
-                if (row < U.m_ap && col < U.m_dp) y[U.y_off + (int64_t)row * U.m_dp + col] = acc[p][q][v];
+                const int rr = 16 * p + (f64_layout ? g + 4 * v : 4 * g + v);
+                const int cc = 16 * q + li;
+                const int row = I.r0 + rr, col = I.c0 + cc;
+                if (I.part_off < 0) {
+                    if (row < I.m_ap && col < I.m_dp) y[I.y_off + (int64_t)row * I.m_dp + col] += acc[p][q][v];
+                } else {
+                    part[I.part_off + rr * (16 * TQ) + cc] = acc[p][q][v];
+                }
             }
 }
 
-hipError_t launch_hpsi_f64(const Unit* units, int n_units, const Task* tasks, const double* pool, const double* x,
-                           double* y, int64_t n_coeff, int nvec, hipStream_t s) {
-    if (n_units <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hpsi_f64, dim3(n_units, nvec), dim3(64), 0, s, units, tasks, pool, x, y, n_coeff);
+// y_tile += sum of its partial tiles, in item order
+__global__ void k_reduce(const Reduce* __restrict__ red, const double* __restrict__ partall, double* __restrict__ yall,
+                         int64_t n_coeff, int64_t part_stride) {
+    const Reduce R = red[blockIdx.x];
+    const double* __restrict__ part = partall + (int64_t)blockIdx.y * part_stride + R.part_off;
+    double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
+    const int n = R.tm * R.tn;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int rr = e / R.tn, cc = e - (e / R.tn) * R.tn;
+        const int row = R.r0 + rr, col = R.c0 + cc;
+        if (row >= R.m_ap || col >= R.m_dp) continue;
+        double s = 0.0;
+        for (int k = 0; k < R.n_parts; ++k) s += part[(int64_t)k * n + e];
+        y[R.y_off + (int64_t)row * R.m_dp + col] += s;
+    }
+}
+
+__device__ __forceinline__ f64x4 ld4(const double* p) { return *reinterpret_cast<const f64x4*>(p); }
+
+// ------------------------------------------------------------------ FP64 sector GEMMs
+// Operands are read without masks from the padded pool and the packed input. The reduction index of
+// GEMM1 is permuted (instruction v takes k = k0 + 4g + v in lane group g) so that A rows are read
+// as 32-byte vectors; GEMM1's X operand uses columns j0 + pl(li), pl(r) = 4 (r % 4) + r / 4, so that
+// result slot v of lane group g holds column j0 + 4g + v and B rows are read as 32-byte vectors too.
+template <int TP, int TQ>
+__global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const Item* __restrict__ items, const Task* __restrict__ tasks,
+                                                 const double* __restrict__ pool, const double* __restrict__ xpall,
+                                                 double* __restrict__ yall, double* __restrict__ partall,
+                                                 int64_t n_coeff, int64_t psize, int64_t slot_stride) {
+    const Item I = items[blockIdx.x];
+    const double* __restrict__ xp = xpall + (int64_t)blockIdx.y * psize;
+    double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
+    double* __restrict__ part = partall + (int64_t)blockIdx.y * slot_stride;
+    const int lane = threadIdx.x;
+    const int li = lane & 15, g = lane >> 4;
+    const int pl = 4 * (li & 3) + (li >> 2);
+    f64x4 acc[TP][TQ];
+#pragma unroll
+    for (int p = 0; p < TP; ++p)
+#pragma unroll
+        for (int q = 0; q < TQ; ++q) acc[p][q] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    Task Tn = tasks[I.t_begin];   // descriptor of the next task, loaded one task ahead
+    for (int t = I.t_begin; t < I.t_end; ++t) {
+        const Task T = Tn;
+        if (t + 1 < I.t_end) Tn = tasks[t + 1];
+        const double* __restrict__ X = xp + T.x_off;
+        const int pa = T.pa, pd = T.pd;
+        const double f = T.f;
+        if (T.a_off < 0 && T.b_off < 0) {
+#pragma unroll
+            for (int p = 0; p < TP; ++p)
+#pragma unroll
+                for (int q = 0; q < TQ; ++q)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[p][q][v] += f * X[(I.r0 + 16 * p + g + 4 * v) * pd + I.c0 + 16 * q + li];
+        } else if (T.b_off < 0) {
+            // Y += f A X (right identity)
+            const double* __restrict__ A = pool + T.a_off;
+            for (int k0 = 0; k0 < T.ka; k0 += 16) {
+                f64x4 a4[TP];
+#pragma unroll
+                for (int p = 0; p < TP; ++p) a4[p] = f * ld4(A + (I.r0 + 16 * p + li) * pa + k0 + 4 * g);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double xv[TQ];
+#pragma unroll
+                    for (int q = 0; q < TQ; ++q) xv[q] = X[(k0 + 4 * g + v) * pd + I.c0 + 16 * q + li];
+#pragma unroll
+                    for (int p = 0; p < TP; ++p)
+#pragma unroll
+                        for (int q = 0; q < TQ; ++q)
+                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[p][v], xv[q], acc[p][q], 0, 0, 0);
+                }
+            }
+        } else if (T.a_off < 0) {
+            // Y += f X B^T (left identity)
+            const double* __restrict__ B = pool + T.b_off;
+            for (int k0 = 0; k0 < T.kd; k0 += 16) {
+                f64x4 x4[TP], b4[TQ];
+#pragma unroll
+                for (int p = 0; p < TP; ++p) x4[p] = f * ld4(X + (I.r0 + 16 * p + li) * pd + k0 + 4 * g);
+#pragma unroll
+                for (int q = 0; q < TQ; ++q) b4[q] = ld4(B + (I.c0 + 16 * q + li) * pd + k0 + 4 * g);
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int p = 0; p < TP; ++p)
+#pragma unroll
+                        for (int q = 0; q < TQ; ++q)
+                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x4[p][v], b4[q][v], acc[p][q], 0, 0, 0);
+            }
+        } else {
+            // Y += f A X B^T, chained through registers over 16-column chunks of X
+            const double* __restrict__ A = pool + T.a_off;
+            const double* __restrict__ B = pool + T.b_off;
+            for (int j0 = 0; j0 < T.kd; j0 += 16) {
+                f64x4 tt[TP];
+#pragma unroll
+                for (int p = 0; p < TP; ++p) tt[p] = f64x4{0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < T.ka; k0 += 16) {
+                    f64x4 a4[TP];
+#pragma unroll
+                    for (int p = 0; p < TP; ++p) a4[p] = ld4(A + (I.r0 + 16 * p + li) * pa + k0 + 4 * g);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double xv = X[(k0 + 4 * g + v) * pd + j0 + pl];
+#pragma unroll
+                        for (int p = 0; p < TP; ++p)
+                            tt[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, a4[p][v], tt[p], 0, 0, 0);
+                    }
+                }
+                // tt[p][v] = T'[r0 + 16p + li][j0 + 4g + v]
+                f64x4 b4[TQ];
+#pragma unroll
+                for (int q = 0; q < TQ; ++q) b4[q] = ld4(B + (I.c0 + 16 * q + li) * pd + j0 + 4 * g);
+#pragma unroll
+                for (int p = 0; p < TP; ++p) tt[p] *= f;
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+#pragma unroll
+                    for (int p = 0; p < TP; ++p)
+#pragma unroll
+                        for (int q = 0; q < TQ; ++q)
+                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(tt[p][v], b4[q][v], acc[p][q], 0, 0, 0);
+            }
+        }
+    }
+    store_tile<TP, TQ>(I, y, part, acc, li, g, true);
+}
+
+__global__ void k_zero(double* __restrict__ y, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = 0.0;
+}
+
+static hipError_t launch_pack(const HpsiPlan& plan, const double* x, int64_t n_coeff, int nvec, int split,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_pack, dim3(plan.n_packs, nvec), dim3(256), 0, s, plan.packs, x, n_coeff, plan.packed_size,
+                       plan.xp, plan.xr_hi, plan.xr_lo, plan.xt_hi, plan.xt_lo, split);
     return hipGetLastError();
+}
+
+// y = 0, then phase by phase: the item launches of every tile class, then the phase's reductions
+template <class F>
+static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, int nvec, hipStream_t s, F&& launch_one) {
+    int64_t n = n_coeff * nvec, blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
+    for (int ph = 0; ph < plan.n_phases; ++ph) {
+        const HpsiPhase& P = plan.phases[ph];
+        for (int l = P.launch_begin; l < P.launch_end; ++l) {
+            const HpsiLaunch& L = plan.launches[l];
+            launch_one(L.cls, L.item_begin, L.item_count);
+        }
+        const int nr = P.reduce_end - P.reduce_begin;
+        if (nr > 0)
+            hipLaunchKernelGGL(k_reduce, dim3(nr, nvec), dim3(256), 0, s, plan.reduces + P.reduce_begin, plan.partial,
+                               y, n_coeff, plan.partial_size);
+    }
+    return hipGetLastError();
+}
+
+#define DMRG_CLASS_SWITCH(KERNEL, ...)                                                                 \
+    switch (c) {                                                                                       \
+        case 0: hipLaunchKernelGGL((KERNEL<1, 1>), __VA_ARGS__); break;                                \
+        case 1: hipLaunchKernelGGL((KERNEL<1, 2>), __VA_ARGS__); break;                                \
+        case 2: hipLaunchKernelGGL((KERNEL<1, 3>), __VA_ARGS__); break;                                \
+        case 3: hipLaunchKernelGGL((KERNEL<1, 4>), __VA_ARGS__); break;                                \
+        case 4: hipLaunchKernelGGL((KERNEL<1, 5>), __VA_ARGS__); break;                                \
+        case 5: hipLaunchKernelGGL((KERNEL<1, 6>), __VA_ARGS__); break;                                \
+        case 6: hipLaunchKernelGGL((KERNEL<1, 7>), __VA_ARGS__); break;                                \
+        case 7: hipLaunchKernelGGL((KERNEL<1, 8>), __VA_ARGS__); break;                                \
+        case 8: hipLaunchKernelGGL((KERNEL<2, 1>), __VA_ARGS__); break;                                \
+        case 9: hipLaunchKernelGGL((KERNEL<2, 2>), __VA_ARGS__); break;                                \
+        case 10: hipLaunchKernelGGL((KERNEL<2, 3>), __VA_ARGS__); break;                               \
+        case 11: hipLaunchKernelGGL((KERNEL<2, 4>), __VA_ARGS__); break;                               \
+        case 12: hipLaunchKernelGGL((KERNEL<2, 5>), __VA_ARGS__); break;                               \
+        case 13: hipLaunchKernelGGL((KERNEL<2, 6>), __VA_ARGS__); break;                               \
+        case 14: hipLaunchKernelGGL((KERNEL<2, 7>), __VA_ARGS__); break;                               \
+        default: hipLaunchKernelGGL((KERNEL<2, 8>), __VA_ARGS__); break;                               \
+    }
+
+hipError_t launch_hpsi_f64(const HpsiPlan& plan, const double* pool, const double* x, double* y, int64_t n_coeff,
+                           int nvec, hipStream_t s) {
+    hipError_t e = launch_pack(plan, x, n_coeff, nvec, 0, s);
+    if (e != hipSuccess) return e;
+    const int64_t ss = plan.partial_size;
+    return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
+        DMRG_CLASS_SWITCH(k_hpsi_f64, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, pool, plan.xp, y,
+                          plan.partial, n_coeff, plan.packed_size, ss)
+    });
 }
 
 // ------------------------------------------------------------------ split-BF16 sector GEMMs
 // Operands as BF16 hi/lo pairs; each product a.b is hi.hi + hi.lo + lo.hi on
 // v_mfma_f32_16x16x32_bf16 with FP32 accumulation inside a task; task results are added in FP64.
+// All operand reads are 16-byte vectors: pool rows, packed X rows and packed X^T rows. GEMM1's X^T
+// operand row li of chunk h (h = 0, 1) is column j0 + 8 (li / 4) + 4 h + li % 4, which puts column
+// j0 + 8g + u into k-position 8g + u of GEMM2 (u = 4h + v).
 __device__ __forceinline__ bf16x8 as_bf(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
 __device__ __forceinline__ f32x4 mma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f32x4 c) {
@@ -238,37 +350,20 @@ __device__ __forceinline__ f32x4 mma3(u16x8 ah, u16x8 al, u16x8 bh, u16x8 bl, f3
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf(al), as_bf(bh), c, 0, 0, 0);
     return c;
 }
+__device__ __forceinline__ u16x8 ld8(const uint16_t* p) { return *reinterpret_cast<const u16x8*>(p); }
 
-// 8 consecutive bf16 of a pool row starting at column k (masked beyond `lim`); 16-byte aligned.
-__device__ __forceinline__ void load8(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t base,
-                                      int k, int lim, bool ok, u16x8& h, u16x8& l) {
-    if (ok && k + 8 <= lim + 7 && k < lim) {
-        // rows are padded with zeros up to ld (multiple of 8), so a full 8-vector read stays in the row
-        h = *reinterpret_cast<const u16x8*>(hi + base + k);
-        l = *reinterpret_cast<const u16x8*>(lo + base + k);
-    } else {
-        h = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-        l = h;
-    }
-}
-__device__ __forceinline__ void load4(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t base,
-                                      int k, int lim, bool ok, u16x4& h, u16x4& l) {
-    if (ok && k < lim) {
-        h = *reinterpret_cast<const u16x4*>(hi + base + k);
-        l = *reinterpret_cast<const u16x4*>(lo + base + k);
-    } else {
-        h = u16x4{0, 0, 0, 0};
-        l = h;
-    }
-}
-
-__global__ __launch_bounds__(64) void k_hpsi_split(const Unit* __restrict__ units, const Task* __restrict__ tasks,
+template <int TP, int TQ>
+__global__ __launch_bounds__(64, min_waves_split(TP, TQ)) void k_hpsi_split(const Item* __restrict__ items, const Task* __restrict__ tasks,
                                                    const uint16_t* __restrict__ phi, const uint16_t* __restrict__ plo,
-                                                   const double* __restrict__ xall, double* __restrict__ yall,
-                                                   int64_t n_coeff) {
-    const Unit U = units[blockIdx.x];
-    const double* __restrict__ x = xall + (int64_t)blockIdx.y * n_coeff;
+                                                   const double* __restrict__ xpall, const uint16_t* __restrict__ xrh,
+                                                   const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xth,
+                                                   const uint16_t* __restrict__ xtl, double* __restrict__ yall,
+                                                   double* __restrict__ partall, int64_t n_coeff, int64_t psize,
+                                                   int64_t slot_stride) {
+    const Item I = items[blockIdx.x];
+    const int64_t vo = (int64_t)blockIdx.y * psize;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
+    double* __restrict__ part = partall + (int64_t)blockIdx.y * slot_stride;
     const int lane = threadIdx.x;
     const int li = lane & 15, g = lane >> 4;
     double acc[TP][TQ][4];
@@ -279,176 +374,133 @@ __global__ __launch_bounds__(64) void k_hpsi_split(const Unit* __restrict__ unit
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[p][q][v] = 0.0;
 
-    for (int t = U.t_begin; t < U.t_end; ++t) {
-        const Task T = tasks[t];
-        const double* __restrict__ X = x + T.x_off;
-        const int ma = T.m_a, md = T.m_d;
+    Task Tn = tasks[I.t_begin];   // descriptor of the next task, loaded one task ahead
+    for (int t = I.t_begin; t < I.t_end; ++t) {
+        const Task T = Tn;
+        if (t + 1 < I.t_end) Tn = tasks[t + 1];
+        const int pa = T.pa, pd = T.pd;
+        const int64_t xo = vo + T.x_off;
         const double f = T.f;
+        if (T.a_off < 0 && T.b_off < 0) {
+            const double* __restrict__ X = xpall + xo;
+#pragma unroll
+            for (int p = 0; p < TP; ++p)
+#pragma unroll
+                for (int q = 0; q < TQ; ++q)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[p][q][v] += f * X[(I.r0 + 16 * p + 4 * g + v) * pd + I.c0 + 16 * q + li];
+            continue;
+        }
         f32x4 c32[TP][TQ];
 #pragma unroll
         for (int p = 0; p < TP; ++p)
 #pragma unroll
             for (int q = 0; q < TQ; ++q) c32[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-        if (T.a_off < 0 && T.b_off < 0) {
-#pragma unroll
-            for (int p = 0; p < TP; ++p)
-#pragma unroll
-                for (int q = 0; q < TQ; ++q)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = U.r0 + 16 * p + 4 * g + v, col = U.c0 + 16 * q + li;
-                        if (row < ma && col < md) acc[p][q][v] += f * X[(int64_t)row * md + col];
-                    }
-            continue;
-        } else if (T.b_off < 0) {
-            // Y += f A X: A-operand rows of A (8 consecutive k), B-operand X (split on the fly)
-            const int lda = ldo(ma);
-            for (int k0 = 0; k0 < ma; k0 += 32) {
-                const int kb = k0 + 8 * g;
+        double scale = f;
+        if (T.b_off < 0) {
+            // Y += f A X: A-operand rows of A, B-operand columns of X (rows of X^T)
+            const int64_t ab = T.a_off;
+            for (int k0 = 0; k0 < pa; k0 += 32) {
                 u16x8 ah[TP], al[TP];
 #pragma unroll
                 for (int p = 0; p < TP; ++p) {
-                    const int row = U.r0 + 16 * p + li;
-                    load8(phi, plo, T.a_off + (int64_t)row * lda, kb, ma, row < U.m_ap, ah[p], al[p]);
+                    const int64_t o = ab + (I.r0 + 16 * p + li) * pa + k0 + 8 * g;
+                    ah[p] = ld8(phi + o);
+                    al[p] = ld8(plo + o);
                 }
 #pragma unroll
                 for (int q = 0; q < TQ; ++q) {
-                    const int col = U.c0 + 16 * q + li;
-                    u16x8 bh, bl;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int k = kb + u;
-                        const double xv = (k < ma && col < md) ? X[(int64_t)k * md + col] : 0.0;
-                        unsigned short h, l;
-                        split2(xv, h, l);
-                        bh[u] = h;
-                        bl[u] = l;
-                    }
+                    const int64_t o = xo + (I.c0 + 16 * q + li) * pa + k0 + 8 * g;
+                    const u16x8 bh = ld8(xth + o), bl = ld8(xtl + o);
 #pragma unroll
                     for (int p = 0; p < TP; ++p) c32[p][q] = mma3(ah[p], al[p], bh, bl, c32[p][q]);
                 }
             }
         } else if (T.a_off < 0) {
-            // Y += f X B^T: A-operand rows of X (split), B-operand rows of B (8 consecutive k)
-            const int ldb = ldo(md);
-            for (int k0 = 0; k0 < md; k0 += 32) {
-                const int kb = k0 + 8 * g;
+            // Y += f X B^T: A-operand rows of X, B-operand rows of B
+            const int64_t bb = T.b_off;
+            for (int k0 = 0; k0 < pd; k0 += 32) {
                 u16x8 xh[TP], xl[TP];
 #pragma unroll
                 for (int p = 0; p < TP; ++p) {
-                    const int row = U.r0 + 16 * p + li;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int k = kb + u;
-                        const double xv = (row < ma && k < md) ? X[(int64_t)row * md + k] : 0.0;
-                        unsigned short h, l;
-                        split2(xv, h, l);
-                        xh[p][u] = h;
-                        xl[p][u] = l;
-                    }
+                    const int64_t o = xo + (I.r0 + 16 * p + li) * pd + k0 + 8 * g;
+                    xh[p] = ld8(xrh + o);
+                    xl[p] = ld8(xrl + o);
                 }
 #pragma unroll
                 for (int q = 0; q < TQ; ++q) {
-                    const int col = U.c0 + 16 * q + li;
-                    u16x8 bh, bl;
-                    load8(phi, plo, T.b_off + (int64_t)col * ldb, kb, md, col < U.m_dp, bh, bl);
+                    const int64_t o = bb + (I.c0 + 16 * q + li) * pd + k0 + 8 * g;
+                    const u16x8 bh = ld8(phi + o), bl = ld8(plo + o);
 #pragma unroll
                     for (int p = 0; p < TP; ++p) c32[p][q] = mma3(xh[p], xl[p], bh, bl, c32[p][q]);
                 }
             }
         } else {
-            const int lda = ldo(ma), ldb = ldo(md);
-            for (int j0 = 0; j0 < md; j0 += 32) {
-                // GEMM1: T'^T for two 16-column chunks (j0 .. j0+15 and j0+16 .. j0+31)
+            const int64_t ab = T.a_off, bb = T.b_off;
+            const int jl = 8 * (li >> 2) + (li & 3);
+            for (int j0 = 0; j0 < pd; j0 += 32) {
                 f32x4 tt[2][TP];
 #pragma unroll
                 for (int h2 = 0; h2 < 2; ++h2)
 #pragma unroll
                     for (int p = 0; p < TP; ++p) tt[h2][p] = f32x4{0.f, 0.f, 0.f, 0.f};
-                for (int k0 = 0; k0 < ma; k0 += 32) {
-                    const int kb = k0 + 8 * g;
+                for (int k0 = 0; k0 < pa; k0 += 32) {
                     u16x8 ah[TP], al[TP];
 #pragma unroll
                     for (int p = 0; p < TP; ++p) {
-                        const int row = U.r0 + 16 * p + li;
-                        load8(phi, plo, T.a_off + (int64_t)row * lda, kb, ma, row < U.m_ap, ah[p], al[p]);
+                        const int64_t o = ab + (I.r0 + 16 * p + li) * pa + k0 + 8 * g;
+                        ah[p] = ld8(phi + o);
+                        al[p] = ld8(plo + o);
                     }
 #pragma unroll
                     for (int h2 = 0; h2 < 2; ++h2) {
-                        const int jx = j0 + 16 * h2 + li;
-                        u16x8 xh, xl;
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int k = kb + u;
-                            const double xv = (k < ma && jx < md) ? X[(int64_t)k * md + jx] : 0.0;
-                            unsigned short hh, ll;
-                            split2(xv, hh, ll);
-                            xh[u] = hh;
-                            xl[u] = ll;
-                        }
+                        const int64_t o = xo + (int64_t)(j0 + jl + 4 * h2) * pa + k0 + 8 * g;
+                        const u16x8 xh = ld8(xth + o), xl = ld8(xtl + o);
 #pragma unroll
                         for (int p = 0; p < TP; ++p) tt[h2][p] = mma3(xh, xl, ah[p], al[p], tt[h2][p]);
                     }
                 }
-                // tt[h2][p][v] = T'[row = r0+16p+li][j = j0 + 16 h2 + 4g + v]; k-position 8g+u <->
-                // j = j0 + 4g + u (u < 4), j0 + 16 + 4g + (u - 4) (u >= 4)
+                // tt[h][p][v] = T'[r0 + 16p + li][j0 + 8g + 4h + v]
                 u16x8 th[TP], tl[TP];
 #pragma unroll
                 for (int p = 0; p < TP; ++p)
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        const float v = (float)f * tt[u >> 2][p][u & 3];
                         unsigned short hh, ll;
-                        split2f(v, hh, ll);
+                        split2f((float)f * tt[u >> 2][p][u & 3], hh, ll);
                         th[p][u] = hh;
                         tl[p][u] = ll;
                     }
 #pragma unroll
                 for (int q = 0; q < TQ; ++q) {
-                    const int col = U.c0 + 16 * q + li;
-                    const bool okc = col < U.m_dp;
-                    const int64_t base = T.b_off + (int64_t)col * ldb;
-                    u16x4 bh0, bl0, bh1, bl1;
-                    load4(phi, plo, base, j0 + 4 * g, md, okc, bh0, bl0);
-                    load4(phi, plo, base, j0 + 16 + 4 * g, md, okc, bh1, bl1);
-                    u16x8 bh = u16x8{bh0[0], bh0[1], bh0[2], bh0[3], bh1[0], bh1[1], bh1[2], bh1[3]};
-                    u16x8 bl = u16x8{bl0[0], bl0[1], bl0[2], bl0[3], bl1[0], bl1[1], bl1[2], bl1[3]};
+                    const int64_t o = bb + (I.c0 + 16 * q + li) * pd + j0 + 8 * g;
+                    const u16x8 bh = ld8(phi + o), bl = ld8(plo + o);
 #pragma unroll
                     for (int p = 0; p < TP; ++p) c32[p][q] = mma3(th[p], tl[p], bh, bl, c32[p][q]);
                 }
             }
-            // f already applied to T'
-#pragma unroll
-            for (int p = 0; p < TP; ++p)
-#pragma unroll
-                for (int q = 0; q < TQ; ++q)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[p][q][v] += (double)c32[p][q][v];
-            continue;
+            scale = 1.0;   // f already applied to T'
         }
 #pragma unroll
         for (int p = 0; p < TP; ++p)
 #pragma unroll
             for (int q = 0; q < TQ; ++q)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[p][q][v] += f * (double)c32[p][q][v];
+                for (int v = 0; v < 4; ++v) acc[p][q][v] += scale * (double)c32[p][q][v];
     }
-#pragma unroll
-    for (int p = 0; p < TP; ++p)
-#pragma unroll
-        for (int q = 0; q < TQ; ++q)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = U.r0 + 16 * p + 4 * g + v, col = U.c0 + 16 * q + li;
-                if (row < U.m_ap && col < U.m_dp) y[U.y_off + (int64_t)row * U.m_dp + col] = acc[p][q][v];
-            }
+    store_tile<TP, TQ>(I, y, part, acc, li, g, false);
 }
 
-hipError_t launch_hpsi_split(const Unit* units, int n_units, const Task* tasks, const uint16_t* hi, const uint16_t* lo,
-                             const double* x, double* y, int64_t n_coeff, int nvec, hipStream_t s) {
-    if (n_units <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_hpsi_split, dim3(n_units, nvec), dim3(64), 0, s, units, tasks, hi, lo, x, y, n_coeff);
-    return hipGetLastError();
+hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x, double* y,
+                             int64_t n_coeff, int nvec, hipStream_t s) {
+    hipError_t e = launch_pack(plan, x, n_coeff, nvec, 1, s);
+    if (e != hipSuccess) return e;
+    const int64_t ss = plan.partial_size;
+    return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
+        DMRG_CLASS_SWITCH(k_hpsi_split, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, hi, lo, plan.xp,
+                          plan.xr_hi, plan.xr_lo, plan.xt_hi, plan.xt_lo, y, plan.partial, n_coeff, plan.packed_size, ss)
+    });
 }
 
 // ------------------------------------------------------------------ diag(H)
