@@ -41,6 +41,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
+    ap.add_argument("--workload", choices=["precision", "batch"], default="precision",
+                    help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems")
+    ap.add_argument("--n-problems", type=int, default=128)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -53,6 +56,8 @@ def main():
     from dmrg_inputs import random_vector
     from dmrg_inputs.synthetic import synthetic_problem
 
+    if args.workload == "batch":
+        return bench_batch(args)
     dev = torch.device("cuda:0")
     L, M = args.L, args.M
     na = nb = L // 2
@@ -161,6 +166,69 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Many independent two-site H.psi problems (L ~ U{16..28}, N = L, M ~ U{64..768}, seeds
+    2000 + j): one merged launch sequence (autotuned plan) vs one launch sequence per problem."""
+    import gc
+
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_vector
+    from dmrg_inputs.synthetic import synthetic_problem
+    stream = torch.cuda.current_stream()
+    hops, shapes = [], []
+    t0 = time.time()
+    for j in range(args.n_problems):
+        rng = np.random.Generator(np.random.PCG64(2000 + j))
+        L = int(rng.integers(16, 29))
+        M = int(rng.integers(64, 769))
+        na, nb = (L + 1) // 2, L // 2
+        h, eri, left, right, site = synthetic_problem(L, na, nb, M, 1.5, 2000 + j)
+        hops.append(dm.Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, stream=stream))
+        shapes.append((L, M))
+        del h, eri, left, right
+        gc.collect()
+        if j % 16 == 15:
+            log(f"[bench] built {j + 1}/{args.n_problems} problems ({time.time() - t0:.0f}s)")
+    comb = dm.Hop.combine(hops, stream=stream)
+    flops = sum(hp.stats()["flops"] for hp in hops)
+    tune = comb.autotune(dm.PREC_SPLIT2, reps=2, stream=stream)
+    log(f"[bench] combined: |psi|={comb.n_coeff} flops/matvec={flops:.3e} autotune={tune}")
+    xs = [torch.as_tensor(random_vector(hp.n_coeff, 7 + k), device="cuda:0") for k, hp in enumerate(hops)]
+    ys = [torch.empty_like(x) for x in xs]
+    xc = torch.cat(xs)
+    yc = torch.empty_like(xc)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    out = {}
+    for name, prec in (("split", dm.PREC_SPLIT2), ("fp64", dm.PREC_FP64)):
+        t_serial = timed(lambda: [hp.hpsi(x, y, prec, stream=stream) for hp, x, y in zip(hops, xs, ys)], 3)
+        t_batch = timed(lambda: comb.hpsi(xc, yc, prec, stream=stream), 3)
+        diff = float((torch.cat(ys) - yc).abs().max() / yc.abs().max())
+        out[name] = {"serial_ms": round(t_serial, 3), "batched_ms": round(t_batch, 3),
+                     "speedup": round(t_serial / t_batch, 3), "batched_tflops": round(flops / t_batch / 1e9, 3),
+                     "serial_tflops": round(flops / t_serial / 1e9, 3), "max_rel_diff": diff}
+        log(f"[bench] {name}: {out[name]}")
+    line = {"metric": "H·ψ TFLOP/s, one merged launch vs serial launches", "value": out["split"]["batched_tflops"],
+            "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": out["split"]["batched_ms"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": f"{args.n_problems} independent two-site H.psi problems, L~U{{16..28}}, N=L, "
+                                   f"M~U{{64..768}}, synthetic block operators sigma=1.5",
+                       "n_coeff": comb.n_coeff, "flops_per_matvec": flops, "autotune": tune},
+            "split": out["split"], "fp64": out["fp64"]}
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(h, eri, left, right, na, nb, site, n):

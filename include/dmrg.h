@@ -118,8 +118,8 @@ typedef struct {
     void*   stream;          /* hipStream_t for the build; 0 = legacy default stream */
 } dmrg_build_opts;
 
-/* Build the H.psi operator of one bond (Section 2.2.1: "before the Davidson algorithm is started, a
- * huge task list ... is generated"): psi sector layout (Eq. wf_sec), the list of operator
+/* Build the H.psi operator of one bond, once per bond and before Davidson starts (the pre-generated
+ * task list of Section 2.2.1): psi sector layout (Eq. wf_sec), the list of operator
  * combinations alpha (the sum over alpha of the H.Phi equation, Section 2.2.1), on-the-fly
  * pre-summed left-block operators (Section 2.2.3) formed on the GPU, the owner-computes task list
  * for Eq. dgemm, and diag(H). `left` must carry the normal operator set and `right` the
@@ -182,6 +182,26 @@ typedef struct {
  * Synchronizes the stream before returning. */
 dmrg_status dmrg_davidson(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts,
                           dmrg_dav_result* result, void* stream);
+
+/* Batching: merge several built handles (same device) into one handle whose psi is the
+ * concatenation of the inputs' psi vectors (in the given order) and whose H is the direct sum, so a
+ * single dmrg_hpsi call computes all problems in one launch sequence whose work items are balanced
+ * over the whole batch (the task list of Section 2.2.1, merged across problems). The inputs stay
+ * valid and independent; the new handle owns copies of their device operators. Davidson on a
+ * combined handle solves the direct-sum problem (its lowest eigenpair over all parts). */
+dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out);
+
+/* Number of merged problems and their first coefficient offsets (n_parts + 1 entries, the last is
+ * n_coeff). A handle from dmrg_build_blocks has one part. */
+dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first_coeff);
+
+/* Autotuner of the H.psi launch plan: times candidate settings of the widest output tile
+ * (2, 4, 8 MFMA tiles of 16 columns), the number of work items (8k, 32k, 64k) and the launch order
+ * (heaviest first / cache-aware) on the device for `precision`, `reps` timed calls each, and keeps
+ * the fastest. chosen (3 ints: tile width, items, order) and best_ms (milliseconds) may be NULL.
+ * Synchronizes `stream`. */
+dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, void* stream,
+                              int32_t* chosen, double* best_ms);
 
 /* Host-logic introspection (used by the CPU tests of the term generator): the task list as
  * (source block, target block, left matrix id, right matrix id) quadruples with scalars f, and the

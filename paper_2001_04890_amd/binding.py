@@ -15,7 +15,7 @@ except ImportError:  # CPU-only environments without torch can still load the li
     torch = None
 
 if not os.path.exists(lib_path):
-    raise ImportError(f"{lib_path} is missing: build it with `python -m paper_2001_04890_amd.build` "
+    raise ImportError(f"{lib_path} is missing: build it with `python paper_2001_04890_amd/build.py` "
                       "(there is no CPU fallback)")
 lib = C.CDLL(lib_path)
 
@@ -79,6 +79,12 @@ lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POIN
 lib.dmrg_davidson.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
 lib.dmrg_hop_export_tasks.restype = C.c_int32
+lib.dmrg_hop_combine.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
+lib.dmrg_hop_combine.restype = C.c_int32
+lib.dmrg_hop_parts.argtypes = [C.c_void_p, i32p, i64p]
+lib.dmrg_hop_parts.restype = C.c_int32
+lib.dmrg_hop_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, i32p, f64p]
+lib.dmrg_hop_autotune.restype = C.c_int32
 
 
 def version():
@@ -132,7 +138,19 @@ def _stream_ptr(stream):
 
 
 class Hop:
-    """Handle of one bond's H.psi operator (dmrg_build_blocks)."""
+    """Handle of one bond's H.psi operator (dmrg_build_blocks), or of several merged ones."""
+
+    @classmethod
+    def combine(cls, hops, stream=None):
+        """One handle computing all problems of ``hops`` in one launch sequence (dmrg_hop_combine)."""
+        arr = (C.c_void_p * len(hops))(*[h._h.value for h in hops])
+        handle = C.c_void_p()
+        _check(lib.dmrg_hop_combine(arr, len(hops), _stream_ptr(stream), C.byref(handle)))
+        self = cls.__new__(cls)
+        self._h = handle
+        self.device = hops[0].device
+        self._load_layout()
+        return self
 
     def __init__(self, h, eri, left, right, n_alpha, n_beta, site, device=0, want_split=False,
                  mem_budget_bytes=0, stream=None):
@@ -146,6 +164,10 @@ class Hop:
                                      C.byref(handle)))
         self._h = handle
         self.device = device
+        self._load_layout()
+
+    def _load_layout(self):
+        handle = self._h
         n = C.c_int64()
         nb = C.c_int32()
         _check(lib.dmrg_hop_layout(handle, C.byref(n), C.byref(nb), None, None, None))
@@ -159,6 +181,19 @@ class Hop:
         self.abcd = abcd.reshape(-1, 4)
         self.dims = dims.reshape(-1, 2)
         self.offsets = offs
+        npart = C.c_int32()
+        _check(lib.dmrg_hop_parts(handle, C.byref(npart), None))
+        first = np.zeros(npart.value + 1, dtype=np.int64)
+        _check(lib.dmrg_hop_parts(handle, None, _ptr(first, C.c_int64)))
+        self.part_coeff = first
+
+    def autotune(self, precision=PREC_SPLIT2, reps=3, stream=None):
+        """Pick the fastest H.psi launch plan (dmrg_hop_autotune); returns (tile width, items, order, ms)."""
+        ch = np.zeros(3, dtype=np.int32)
+        ms = C.c_double()
+        _check(lib.dmrg_hop_autotune(self._h, precision, reps, _stream_ptr(stream), _ptr(ch, C.c_int32),
+                                     C.byref(ms)))
+        return int(ch[0]), int(ch[1]), int(ch[2]), ms.value
 
     def __del__(self):
         h = getattr(self, "_h", None)

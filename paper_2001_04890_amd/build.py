@@ -1,6 +1,8 @@
 """Build libdmrg.so (HIP, gfx950) in-tree with hipcc.
 
-    python -m paper_2001_04890_amd.build
+    python paper_2001_04890_amd/build.py
+
+(Run by path: importing the package would load the library that is being rebuilt.)
 """
 import os
 import subprocess

@@ -175,6 +175,7 @@ struct MatDef {
     // materialized:
     std::vector<int> out_of_in;
     std::vector<int64_t> pool_of_in;
+    double bytes = 0.0;             // padded pool bytes of all its sector blocks
 };
 
 struct Alpha {
@@ -218,6 +219,9 @@ struct dmrg_hop {
     std::vector<dmrg::HpsiLaunch> launches;
     std::vector<dmrg::HpsiPhase> phases;
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
+    int64_t n_alpha = 0;
+    int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
+    std::vector<int64_t> part_coeff;       // first coefficient of each merged problem (+ end)
     int n_items = 0;
     int64_t n_dev_tasks = 0;
     int tune_max_tq = 8;       // widest output tile, in 16-column MFMA tiles (1..8)
@@ -517,6 +521,9 @@ void mat_sectors(dmrg_hop& H, MatDef& m) {
             m.out_of_in[si] = so;
         }
     }
+    m.bytes = 0.0;
+    for (int si = 0; si < B.n_sec; ++si)
+        if (m.out_of_in[si] >= 0) m.bytes += 8.0 * dmrg::rows_of(B.dim[m.out_of_in[si]]) * dmrg::ld_of(B.dim[si]);
 }
 
 void build_tasks(dmrg_hop& H) {
@@ -600,17 +607,7 @@ T* plan_alloc(dmrg_hop& H, size_t n) {
 }
 
 // Bytes of a matrix definition as stored in the pool (all its sector blocks, padded).
-double mat_bytes(const dmrg_hop& H, int m) {
-    if (m < 0) return 0.0;
-    const MatDef& M = H.mats[m];
-    const BlockIn& B = M.side == 0 ? H.left : H.right;
-    double b = 0.0;
-    for (int si = 0; si < B.n_sec; ++si) {
-        int so = M.out_of_in[si];
-        if (so >= 0) b += 8.0 * dmrg::rows_of(B.dim[so]) * dmrg::ld_of(B.dim[si]);
-    }
-    return b;
-}
+double mat_bytes(const dmrg_hop& H, int m) { return m < 0 ? 0.0 : H.mats[m].bytes; }
 
 // Launch plan of H.psi: packed input layout, phases, work items, reductions (see internal.h).
 //  * Phases: the distinct (left matrix, right matrix) pairs are sorted by (right, left) and cut into
@@ -1023,6 +1020,8 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         build_layout(*H);
         Builder(*H).generate();
         build_tasks(*H);
+        H->n_alpha = (int64_t)H->alphas.size();
+        H->part_coeff = {0, H->n_coeff};
         int dev = opts ? opts->device : 0;
         if (const char* e = std::getenv("DMRG_MAX_TQ")) H->tune_max_tq = std::max(1, std::min(8, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_ITEMS")) H->tune_items = std::max(256, std::atoi(e));
@@ -1086,7 +1085,7 @@ extern "C" dmrg_status dmrg_hop_stats(const dmrg_hop* H, double* flops, double* 
     if (!H) { g_err = "hop is NULL"; return DMRG_ERR_ARG; }
     if (flops) *flops = H->flops;
     if (bytes) *bytes = H->bytes;
-    if (n_alpha) *n_alpha = (int64_t)H->alphas.size();
+    if (n_alpha) *n_alpha = H->n_alpha;
     if (n_tasks) *n_tasks = (int64_t)H->tasks.size();
     return DMRG_OK;
 }
@@ -1156,6 +1155,160 @@ extern "C" dmrg_status dmrg_hop_diagonal(dmrg_hop* H, double* d, void* stream) {
         HIPCHK(hipMemcpyAsync(d, H->d_diag, H->n_coeff * sizeof(double), hipMemcpyDeviceToDevice, (hipStream_t)stream));
         return DMRG_OK;
     } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+// ---------------------------------------------------------------- batching and tuning
+extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out) {
+    g_err.clear();
+    if (!out) { g_err = "out is NULL"; return DMRG_ERR_ARG; }
+    *out = nullptr;
+    dmrg_hop* C = new (std::nothrow) dmrg_hop;
+    if (!C) { g_err = "host allocation failed"; return DMRG_ERR_NOMEM; }
+    try {
+        if (!hops || n < 1) throw Error(DMRG_ERR_ARG, "need at least one handle");
+        for (int k = 0; k < n; ++k) {
+            if (!hops[k]) throw Error(DMRG_ERR_ARG, "NULL handle in the batch");
+            if (hops[k]->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle in the batch");
+            if (hops[k]->device != hops[0]->device) throw Error(DMRG_ERR_ARG, "handles on different devices");
+        }
+        hipStream_t s = (hipStream_t)stream;
+        C->device = hops[0]->device;
+        HIPCHK(hipSetDevice(C->device));
+        C->has_split = true;
+        for (int k = 0; k < n; ++k) C->has_split = C->has_split && hops[k]->has_split;
+        C->tune_max_tq = hops[0]->tune_max_tq;
+        C->tune_items = hops[0]->tune_items;
+        C->tune_order = hops[0]->tune_order;
+        C->tune_phases = 1;
+        C->n_parts = n;
+        C->part_coeff.assign(1, 0);
+        for (int k = 0; k < n; ++k) {
+            const dmrg_hop& h = *hops[k];
+            const int blk_base = (int)C->blk.size(), mat_base = (int)C->mats.size();
+            const int64_t coeff_base = C->n_coeff, pool_base = C->pool_size;
+            for (size_t i = 0; i < h.blk.size(); ++i) {
+                C->blk.push_back(h.blk[i]);
+                C->blk_ma.push_back(h.blk_ma[i]);
+                C->blk_md.push_back(h.blk_md[i]);
+                C->blk_off.push_back(h.blk_off[i] + coeff_base);
+            }
+            for (const MatDef& m : h.mats) {
+                MatDef c = m;
+                for (auto& o : c.pool_of_in) if (o >= 0) o += pool_base;
+                c.transpose_id = -1;
+                C->mats.push_back(std::move(c));
+            }
+            for (const auto& t : h.tasks)
+                C->tasks.push_back({t.i + blk_base, t.j + blk_base, t.lm >= 0 ? t.lm + mat_base : -1,
+                                    t.rm >= 0 ? t.rm + mat_base : -1, t.f});
+            C->n_coeff += h.n_coeff;
+            C->pool_size += h.pool_size;
+            C->flops += h.flops;
+            C->bytes += h.bytes;
+            C->n_alpha += h.n_alpha;
+            C->part_coeff.push_back(C->n_coeff);
+        }
+        C->d_pool = dev_alloc<double>(*C, C->pool_size);
+        if (C->has_split) {
+            C->d_hi = dev_alloc<uint16_t>(*C, C->pool_size);
+            C->d_lo = dev_alloc<uint16_t>(*C, C->pool_size);
+        }
+        C->d_diag = dev_alloc<double>(*C, C->n_coeff);
+        int64_t pb = 0, cb = 0;
+        for (int k = 0; k < n; ++k) {
+            const dmrg_hop& h = *hops[k];
+            HIPCHK(hipMemcpyAsync(C->d_pool + pb, h.d_pool, h.pool_size * sizeof(double), hipMemcpyDeviceToDevice, s));
+            if (C->has_split) {
+                HIPCHK(hipMemcpyAsync(C->d_hi + pb, h.d_hi, h.pool_size * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
+                HIPCHK(hipMemcpyAsync(C->d_lo + pb, h.d_lo, h.pool_size * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
+            }
+            HIPCHK(hipMemcpyAsync(C->d_diag + cb, h.d_diag, h.n_coeff * sizeof(double), hipMemcpyDeviceToDevice, s));
+            pb += h.pool_size;
+            cb += h.n_coeff;
+        }
+        build_plan(*C, s);
+        *out = C;
+        return DMRG_OK;
+    } catch (const Error& e) {
+        dmrg_status st = fail(e);
+        dmrg_hop_free(C);
+        return st;
+    } catch (const std::bad_alloc&) {
+        dmrg_hop_free(C);
+        g_err = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
+extern "C" dmrg_status dmrg_hop_parts(const dmrg_hop* H, int32_t* n_parts, int64_t* first_coeff) {
+    g_err.clear();
+    if (!H) { g_err = "hop is NULL"; return DMRG_ERR_ARG; }
+    if (n_parts) *n_parts = H->n_parts;
+    if (first_coeff) for (size_t k = 0; k < H->part_coeff.size(); ++k) first_coeff[k] = H->part_coeff[k];
+    return DMRG_OK;
+}
+
+// Autotuner: times the H.psi launch plan for candidate (widest tile, work items, launch order)
+// settings on the device and keeps the fastest.
+extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t reps, void* stream,
+                                         int32_t* chosen, double* best_ms) {
+    g_err.clear();
+    void* xy = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    try {
+        if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (reps < 1) reps = 3;
+        HIPCHK(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)stream;
+        HIPCHK(hipMalloc(&xy, 2 * H->n_coeff * sizeof(double)));
+        double* x = (double*)xy;
+        double* y = x + H->n_coeff;
+        HIPCHK(hipMemsetAsync(x, 0, H->n_coeff * sizeof(double), s));
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        const int tq_c[] = {2, 4, 8};
+        const int items_c[] = {8192, 32768, 65536};
+        const int order_c[] = {0, 2};
+        double best = INFINITY;
+        int bt = H->tune_max_tq, bi = H->tune_items, bo = H->tune_order;
+        for (int tq : tq_c)
+            for (int it : items_c)
+                for (int od : order_c) {
+                    H->tune_max_tq = tq;
+                    H->tune_items = it;
+                    H->tune_order = od;
+                    build_plan(*H, s);
+                    dmrg_status st = dmrg_hpsi(H, x, y, 1, precision, stream);
+                    if (st != DMRG_OK) throw Error(st, g_err);
+                    HIPCHK(hipEventRecord(e0, s));
+                    for (int r = 0; r < reps; ++r) {
+                        st = dmrg_hpsi(H, x, y, 1, precision, stream);
+                        if (st != DMRG_OK) throw Error(st, g_err);
+                    }
+                    HIPCHK(hipEventRecord(e1, s));
+                    HIPCHK(hipEventSynchronize(e1));
+                    float ms = 0.f;
+                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                    const double avg = ms / reps;
+                    if (avg < best) { best = avg; bt = tq; bi = it; bo = od; }
+                }
+        H->tune_max_tq = bt;
+        H->tune_items = bi;
+        H->tune_order = bo;
+        build_plan(*H, s);
+        if (chosen) { chosen[0] = bt; chosen[1] = bi; chosen[2] = bo; }
+        if (best_ms) *best_ms = best;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        (void)hipFree(xy);
+        return DMRG_OK;
+    } catch (const Error& e) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (xy) (void)hipFree(xy);
         return fail(e);
     }
 }

@@ -1,0 +1,84 @@
+"""GPU tests of batching (one launch sequence for many H.psi problems) and of the plan autotuner.
+
+A merged handle must give, for every part, the H.psi of that part's own handle: identical up to the
+order in which task contributions are summed (the work items are cut differently), bar 1e-12
+relative to max|y| in FP64 and in split precision (the split rounding happens inside a task, which
+is the same in both). One part is also checked against the FP64 oracle.
+"""
+import numpy as np
+import pytest
+
+from dmrg_inputs import random_vector
+from oracle.hpsi import OracleHop
+from helpers import rel_err, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+lib_mod = pytest.importorskip("paper_2001_04890_amd")
+Hop, PREC_FP64, PREC_SPLIT2 = lib_mod.Hop, lib_mod.PREC_FP64, lib_mod.PREC_SPLIT2
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def batch():
+    rng = np.random.default_rng(42)
+    probs, hops = [], []
+    for k in range(6):
+        L = int(rng.integers(10, 15))
+        M = int(rng.integers(30, 120))
+        p = synth(L, M, 1.0 + 0.2 * k, 100 + k)
+        print(f"[batch] part {k}: L={L} M={M}", flush=True)
+        probs.append(p)
+        h, eri, left, right, na, nb, site = p
+        hops.append(Hop(h, eri, left, right, na, nb, site, device=0, want_split=True))
+    comb = Hop.combine(hops)
+    return probs, hops, comb
+
+
+def _run(hop, x, prec):
+    xd = torch.as_tensor(x, device=DEV)
+    yd = torch.empty_like(xd)
+    hop.hpsi(xd, yd, prec)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def test_combined_layout(batch):
+    probs, hops, comb = batch
+    assert comb.n_coeff == sum(h.n_coeff for h in hops)
+    assert list(comb.part_coeff) == list(np.cumsum([0] + [h.n_coeff for h in hops]))
+    assert comb.stats()["n_tasks"] == sum(h.stats()["n_tasks"] for h in hops)
+
+
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_SPLIT2])
+def test_combined_equals_parts(batch, prec):
+    probs, hops, comb = batch
+    xs = [random_vector(h.n_coeff, 7 + k) for k, h in enumerate(hops)]
+    ycomb = _run(comb, np.concatenate(xs), prec)
+    for k, h in enumerate(hops):
+        a, b = comb.part_coeff[k], comb.part_coeff[k + 1]
+        assert rel_err(ycomb[a:b], _run(h, xs[k], prec)) < 1e-12, k
+
+
+def test_combined_part_matches_oracle(batch):
+    probs, hops, comb = batch
+    k = 3
+    h, eri, left, right, na, nb, site = probs[k]
+    xs = [random_vector(hh.n_coeff, 50 + i) for i, hh in enumerate(hops)]
+    y = _run(comb, np.concatenate(xs), PREC_FP64)
+    ref = OracleHop(h, eri, left, right, na, nb, site).apply(xs[k])
+    assert rel_err(y[comb.part_coeff[k]:comb.part_coeff[k + 1]], ref) < 1e-12
+
+
+def test_autotune_keeps_results(batch):
+    probs, hops, comb = batch
+    x = random_vector(comb.n_coeff, 3)
+    before = _run(comb, x, PREC_SPLIT2)
+    tq, items, order, ms = comb.autotune(PREC_SPLIT2, reps=2)
+    print(f"[autotune] tile width {tq} items {items} order {order}: {ms:.3f} ms")
+    assert tq in (2, 4, 8) and items in (8192, 32768, 65536) and order in (0, 2) and ms > 0
+    assert rel_err(_run(comb, x, PREC_SPLIT2), before) < 1e-12
