@@ -155,7 +155,9 @@ dmrg_status dmrg_hop_diagonal(dmrg_hop* hop, double* d, void* stream);
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs once the split
- * residual stalls (or falls below split_tol), and finishes at tol. */
+ * residual stalls (or falls below split_tol), and finishes at tol. The correction vector comes from
+ * the diagonal preconditioner or from a learned network (precond, mlp). */
+typedef struct dmrg_mlp dmrg_mlp;   /* opaque: learned preconditioner (weights, Adam state, datasets) */
 typedef struct {
     double  tol;             /* ||r||_2 convergence threshold on the normalized Ritz vector */
     int32_t max_iter;        /* iterations (matvecs beyond the first) */
@@ -164,7 +166,12 @@ typedef struct {
     int32_t fp64_polish;     /* see above */
     double  split_tol;       /* residual at which split precision hands over to FP64 (e.g. 1e-5) */
     int32_t use_graph;       /* reserved, must be 0 */
+    int32_t precond;         /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP */
+    const struct dmrg_mlp* mlp;   /* network for DMRG_PRECOND_MLP (same device as the handle) */
 } dmrg_dav_opts;
+
+#define DMRG_PRECOND_DIAG 0  /* t = r / (theta - D), D = diag(H), |theta - D| floored at 1e-8 */
+#define DMRG_PRECOND_MLP  1  /* t = r / (theta - D) * (1 + m), m from the learned network below */
 
 typedef struct {
     double  energy;          /* lowest Ritz value */
@@ -210,6 +217,89 @@ dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, vo
  * Matrix id -1 is the identity. Pass NULL arrays to query the counts. */
 dmrg_status dmrg_hop_export_tasks(const dmrg_hop* hop, int64_t* n_tasks, int32_t* quads, double* f,
                                   int64_t* n_terms, int32_t* term_int, double* term_coeff);
+
+/* ---------------------------------------------------------------------------------------------
+ * Learned Davidson preconditioner (an addition to the method of the paper, which uses Davidson's
+ * diagonal preconditioner). One MLP is shared by all psi coefficients:
+ *     x_i (16 features) -> relu(256) -> relu(256) -> m_i,   t_i = r_i / (theta - D_i) * (1 + m_i),
+ * so a network whose output layer is zero is exactly the diagonal preconditioner. Features of
+ * coefficient i of psi block (a, b, c, d), with s_x = sqrt(n) / ||x|| (0 for x = 0):
+ *     asinh(r_i s_r), asinh(t_i s_t), asinh(u_i s_u), asinh((D_i - theta) s_D), one-hot b (4),
+ *     one-hot c (4), asinh(rms_block(r) s_r), asinh(rms_block(u) s_u), ln(m_a)/8, ln(m_d)/8
+ * (r residual, u Ritz vector, t = r / (theta - D) the diagonal correction, D = diag(H)).
+ * Parameters (FP32, DMRG_MLP_PARAMS floats): W1 (16 x 256, row = input), b1 (256), W2 (256 x 256,
+ * row = input), b2 (256), w3 (256), b3 (1). Inference and training run hand-written kernels: the
+ * forward on the matrix cores with BF16 copies of W1, W2 and FP32 accumulation; set_fp32 selects an
+ * FP32 debug mode on the vector units.
+ * Training pairs come from converged solves (dmrg_mlp_collect). For each iteration, with V the
+ * subspace that the correction t is about to be orthogonalized against and psi the solve's final
+ * eigenvector, the ideal correction is P psi = psi - V V^T psi (appending it makes the subspace
+ * contain psi). Davidson only uses the direction of t, so per sampled coefficient the pair is t and
+ * P psi at unit RMS, P psi turned to point along t:
+ *     a = t_i sqrt(n) / ||t||,  b = sign(<t, P psi>) (P psi)_i sqrt(n) / ||P psi||,
+ * and the loss of a minibatch of B rows is (1/B) sum w (a (1 + m) - b)^2 with weight w = 1 (for
+ * m = 0 its mean over one iteration is 2 (1 - cos(t, P psi))). Iterations with ||P psi|| < 1e-7
+ * give no rows.
+ * ------------------------------------------------------------------------------------------- */
+#define DMRG_MLP_IN      16
+#define DMRG_MLP_HIDDEN  256
+#define DMRG_MLP_PARAMS  (16 * 256 + 256 + 256 * 256 + 256 + 256 + 1)
+
+/* New network on `device`: W1, W2 uniform in +-sqrt(6 / fan_in) from a splitmix64 stream of `seed`,
+ * biases, w3 and b3 zero (so it starts as the diagonal preconditioner). */
+dmrg_status dmrg_mlp_create(int32_t device, uint64_t seed, dmrg_mlp** out);
+void dmrg_mlp_free(dmrg_mlp* mlp);
+
+/* Copy the FP32 parameters out to `get` and/or in from `set` (host arrays of DMRG_MLP_PARAMS floats,
+ * either may be NULL; get happens first). Setting parameters resets the Adam state. */
+dmrg_status dmrg_mlp_params(dmrg_mlp* mlp, float* get, const float* set);
+
+/* 1: FP32 debug mode (forward, backward and inference from the FP32 parameters on the vector
+ * units); 0 (default): BF16 weights on the matrix cores, FP32 accumulation. */
+dmrg_status dmrg_mlp_set_fp32(dmrg_mlp* mlp, int32_t fp32);
+
+/* Features of every coefficient for residual r, Ritz vector u and Ritz value theta of handle `hop`
+ * (device pointers, n_coeff doubles each): feat (device, n_coeff x 16 FP32, row-major) and the
+ * diagonal correction t (device, n_coeff doubles). */
+dmrg_status dmrg_mlp_features(dmrg_hop* hop, const double* r, const double* u, double theta, float* feat,
+                              double* t, void* stream);
+
+/* m (device, n FP32) = network output for n feature rows (device, n x 16 FP32). */
+dmrg_status dmrg_mlp_forward(const dmrg_mlp* mlp, const float* feat, int64_t n, float* m, void* stream);
+
+/* Loss and gradient of a minibatch (device arrays): feat n x 16, pairs n x 3 (a, b, w). grad
+ * (device, DMRG_MLP_PARAMS FP32) and loss (device, 1 FP32). With lr > 0 one Adam step (beta1 0.9,
+ * beta2 0.999, eps 1e-8, bias-corrected) is then taken with learning rate lr. 1 <= n <= 2^20. */
+dmrg_status dmrg_mlp_grad(dmrg_mlp* mlp, const float* feat, const float* pairs, int64_t n, float lr, float* grad,
+                          float* loss, void* stream);
+
+/* Run dmrg_davidson on `hop` from psi (device, in: start vector, out: eigenvector) with `opts`
+ * (its precond and mlp fields are honoured) twice: once to find psi, then again from the same start
+ * vector (the solver is deterministic) recording the training pairs of every iteration into dataset
+ * `slot` (0 = training, 1 = validation) of `mlp`: rows_per_iter coefficients sampled uniformly with
+ * replacement (splitmix64 stream of `seed`), or all coefficients when rows_per_iter >= n_coeff.
+ * Rows are appended to what the slot already holds; n_rows (may be NULL) receives the slot's new
+ * size. Nothing is recorded when the first solve does not converge. Returns the Davidson status,
+ * result describes the second solve. */
+dmrg_status dmrg_mlp_collect(dmrg_mlp* mlp, dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts, int32_t slot,
+                             int32_t rows_per_iter, uint64_t seed, dmrg_dav_result* result, int64_t* n_rows,
+                             void* stream);
+
+/* Dataset slot contents: total_rows (may be NULL) receives the slot's size; rows [row0, row0+rows)
+ * are copied into feat (rows x 16) and pairs (rows x 3 as a, b, w), caller-owned host or device
+ * buffers (either may be NULL). Synchronizes `stream`. */
+dmrg_status dmrg_mlp_dataset(const dmrg_mlp* mlp, int32_t slot, int64_t row0, int64_t rows, float* feat,
+                             float* pairs, int64_t* total_rows, void* stream);
+
+/* `steps` Adam steps on minibatches of `batch` rows drawn uniformly with replacement from slot 0
+ * (splitmix64 stream of `seed`); losses (host, `steps` floats, may be NULL) receives each step's
+ * minibatch loss. Synchronizes `stream`. */
+dmrg_status dmrg_mlp_train(dmrg_mlp* mlp, int32_t steps, int32_t batch, float lr, uint64_t seed, float* losses,
+                           void* stream);
+
+/* Mean loss of the current network over every row of dataset `slot` (no update), and the loss of
+ * the diagonal preconditioner (m = 0) on the same rows; either output may be NULL. */
+dmrg_status dmrg_mlp_eval(dmrg_mlp* mlp, int32_t slot, double* loss, double* loss_diag, void* stream);
 
 #ifdef __cplusplus
 }

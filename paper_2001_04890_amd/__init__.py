@@ -4,8 +4,8 @@ The binding only marshals arguments: every step of H.psi, Davidson and the opera
 runs inside the HIP library (``csrc/``). PyTorch supplies device memory and streams. There is no
 CPU fallback: importing the package fails loudly when ``libdmrg.so`` is missing.
 """
-from .binding import (DMRG_OK, DMRG_NOT_CONVERGED, PREC_FP64, PREC_SPLIT2, DmrgError, Hop, lib,
-                      lib_path, version)
+from .binding import (DMRG_OK, DMRG_NOT_CONVERGED, MLP_IN, MLP_PARAMS, PREC_FP64, PREC_SPLIT2, DmrgError,
+                      Hop, Mlp, lib, lib_path, version)
 
-__all__ = ["Hop", "DmrgError", "PREC_FP64", "PREC_SPLIT2", "DMRG_OK", "DMRG_NOT_CONVERGED", "lib",
-           "lib_path", "version"]
+__all__ = ["Hop", "Mlp", "DmrgError", "PREC_FP64", "PREC_SPLIT2", "DMRG_OK", "DMRG_NOT_CONVERGED", "MLP_IN",
+           "MLP_PARAMS", "lib", "lib_path", "version"]

@@ -52,7 +52,8 @@ class BuildOpts(C.Structure):
 
 class DavOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32),
-                ("fp64_polish", C.c_int32), ("split_tol", C.c_double), ("use_graph", C.c_int32)]
+                ("fp64_polish", C.c_int32), ("split_tol", C.c_double), ("use_graph", C.c_int32),
+                ("precond", C.c_int32), ("mlp", C.c_void_p)]
 
 
 class DavResult(C.Structure):
@@ -85,6 +86,38 @@ lib.dmrg_hop_parts.argtypes = [C.c_void_p, i32p, i64p]
 lib.dmrg_hop_parts.restype = C.c_int32
 lib.dmrg_hop_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, i32p, f64p]
 lib.dmrg_hop_autotune.restype = C.c_int32
+lib.dmrg_mlp_create.argtypes = [C.c_int32, C.c_uint64, C.POINTER(C.c_void_p)]
+lib.dmrg_mlp_create.restype = C.c_int32
+lib.dmrg_mlp_free.argtypes = [C.c_void_p]
+lib.dmrg_mlp_free.restype = None
+lib.dmrg_mlp_params.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+lib.dmrg_mlp_params.restype = C.c_int32
+lib.dmrg_mlp_set_fp32.argtypes = [C.c_void_p, C.c_int32]
+lib.dmrg_mlp_set_fp32.restype = C.c_int32
+lib.dmrg_mlp_features.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p,
+                                  C.c_void_p]
+lib.dmrg_mlp_features.restype = C.c_int32
+lib.dmrg_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]
+lib.dmrg_mlp_forward.restype = C.c_int32
+lib.dmrg_mlp_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, C.c_void_p, C.c_void_p,
+                              C.c_void_p]
+lib.dmrg_mlp_grad.restype = C.c_int32
+lib.dmrg_mlp_collect.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.c_int32, C.c_int32,
+                                 C.c_uint64, C.POINTER(DavResult), i64p, C.c_void_p]
+lib.dmrg_mlp_collect.restype = C.c_int32
+lib.dmrg_mlp_dataset.argtypes = [C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p, i64p,
+                                 C.c_void_p]
+lib.dmrg_mlp_dataset.restype = C.c_int32
+lib.dmrg_mlp_train.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_float, C.c_uint64, C.c_void_p, C.c_void_p]
+lib.dmrg_mlp_train.restype = C.c_int32
+lib.dmrg_mlp_eval.argtypes = [C.c_void_p, C.c_int32, f64p, f64p, C.c_void_p]
+lib.dmrg_mlp_eval.restype = C.c_int32
+
+PRECOND_DIAG = 0
+PRECOND_MLP = 1
+MLP_IN = 16
+MLP_HIDDEN = 256
+MLP_PARAMS = 16 * 256 + 256 + 256 * 256 + 256 + 256 + 1
 
 
 def version():
@@ -220,16 +253,15 @@ class Hop:
         _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
 
     def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
-                 split_tol=1e-5, stream=None):
-        """In-place Davidson on the device vector psi; returns a dict of the result fields."""
+                 split_tol=1e-5, mlp=None, stream=None):
+        """In-place Davidson on the device vector psi; returns a dict of the result fields.
+        ``mlp``: a Mlp network to use as the preconditioner (default: the diagonal one)."""
         assert psi.numel() == self.n_coeff and psi.is_contiguous()
-        o = DavOpts(tol, max_iter, max_sub, precision, 1 if fp64_polish else 0, split_tol, 0)
+        o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp)
         r = DavResult()
         st = _check(lib.dmrg_davidson(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),
                                       _stream_ptr(stream)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
-        return dict(energy=r.energy, resid=r.resid, iters=r.iters, matvecs=r.matvecs,
-                    matvecs_split=r.matvecs_split, t_total=r.t_total, t_hpsi=r.t_hpsi,
-                    converged=st == DMRG_OK)
+        return _dav_result(r, st)
 
     def export_tasks(self):
         """Host-side task list and matrix definitions (introspection of the term generator)."""
@@ -242,3 +274,100 @@ class Hop:
         _check(lib.dmrg_hop_export_tasks(self._h, None, _ptr(quads, C.c_int32), _ptr(f, C.c_double), None,
                                          _ptr(ti, C.c_int32), _ptr(tc, C.c_double)))
         return quads.reshape(-1, 4), f, ti.reshape(-1, 4), tc
+
+
+def _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp):
+    return DavOpts(tol, max_iter, max_sub, precision, 1 if fp64_polish else 0, split_tol, 0,
+                   PRECOND_MLP if mlp is not None else PRECOND_DIAG, mlp._h.value if mlp is not None else None)
+
+
+def _dav_result(r, st):
+    return dict(energy=r.energy, resid=r.resid, iters=r.iters, matvecs=r.matvecs, matvecs_split=r.matvecs_split,
+                t_total=r.t_total, t_hpsi=r.t_hpsi, converged=st == DMRG_OK)
+
+
+class Mlp:
+    """Learned Davidson preconditioner (dmrg_mlp_*): network, Adam state and two datasets."""
+
+    def __init__(self, device=0, seed=0):
+        handle = C.c_void_p()
+        _check(lib.dmrg_mlp_create(device, seed, C.byref(handle)))
+        self._h = handle
+        self.device = device
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.dmrg_mlp_free(h)
+            self._h = None
+
+    def get_params(self):
+        p = np.zeros(MLP_PARAMS, dtype=np.float32)
+        _check(lib.dmrg_mlp_params(self._h, p.ctypes.data, None))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        assert p.size == MLP_PARAMS
+        _check(lib.dmrg_mlp_params(self._h, None, p.ctypes.data))
+
+    def set_fp32(self, on):
+        _check(lib.dmrg_mlp_set_fp32(self._h, 1 if on else 0))
+
+    @staticmethod
+    def features(hop, r, u, theta, feat, t, stream=None):
+        """Features (n x 16 float32) and diagonal correction t of (r, u, theta) on hop's layout."""
+        assert feat.numel() == hop.n_coeff * MLP_IN and t.numel() == hop.n_coeff
+        _check(lib.dmrg_mlp_features(hop._h, C.c_void_p(r.data_ptr()), C.c_void_p(u.data_ptr()), float(theta),
+                                     C.c_void_p(feat.data_ptr()), C.c_void_p(t.data_ptr()), _stream_ptr(stream)))
+
+    def forward(self, feat, out, stream=None):
+        n = feat.numel() // MLP_IN
+        assert out.numel() == n and feat.is_contiguous() and out.is_contiguous()
+        _check(lib.dmrg_mlp_forward(self._h, C.c_void_p(feat.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                    _stream_ptr(stream)))
+
+    def grad(self, feat, pairs, grad, loss, lr=0.0, stream=None):
+        """Loss and parameter gradient of a minibatch; with lr > 0 also one Adam step."""
+        n = feat.numel() // MLP_IN
+        assert pairs.numel() == 3 * n and grad.numel() == MLP_PARAMS and loss.numel() >= 1
+        _check(lib.dmrg_mlp_grad(self._h, C.c_void_p(feat.data_ptr()), C.c_void_p(pairs.data_ptr()), n, lr,
+                                 C.c_void_p(grad.data_ptr()), C.c_void_p(loss.data_ptr()), _stream_ptr(stream)))
+
+    def collect(self, hop, psi, slot=0, rows_per_iter=4096, seed=0, tol=1e-10, max_iter=300, max_sub=24,
+                precision=PREC_FP64, fp64_polish=False, split_tol=1e-5, use_mlp=False, stream=None):
+        """Davidson on hop from psi, recording training pairs into dataset ``slot``."""
+        o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, self if use_mlp else None)
+        r = DavResult()
+        rows = C.c_int64()
+        st = _check(lib.dmrg_mlp_collect(self._h, hop._h, C.c_void_p(psi.data_ptr()), C.byref(o), slot,
+                                         rows_per_iter, seed, C.byref(r), C.byref(rows), _stream_ptr(stream)),
+                    allow=(DMRG_OK, DMRG_NOT_CONVERGED))
+        out = _dav_result(r, st)
+        out["rows"] = rows.value
+        return out
+
+    def dataset_rows(self, slot=0):
+        rows = C.c_int64()
+        _check(lib.dmrg_mlp_dataset(self._h, slot, 0, 0, None, None, C.byref(rows), None))
+        return rows.value
+
+    def dataset(self, slot=0, row0=0, rows=None):
+        """Copy of dataset rows as numpy arrays (features n x 16, pairs n x 3)."""
+        total = self.dataset_rows(slot)
+        rows = total - row0 if rows is None else rows
+        feat = np.zeros((rows, MLP_IN), dtype=np.float32)
+        pairs = np.zeros((rows, 3), dtype=np.float32)
+        _check(lib.dmrg_mlp_dataset(self._h, slot, row0, rows, feat.ctypes.data, pairs.ctypes.data, None, None))
+        return feat, pairs
+
+    def train(self, steps, batch=4096, lr=1e-3, seed=0, stream=None):
+        losses = np.zeros(max(steps, 1), dtype=np.float32)
+        _check(lib.dmrg_mlp_train(self._h, steps, batch, lr, seed, losses.ctypes.data, _stream_ptr(stream)))
+        return losses[:steps]
+
+    def eval(self, slot=1, stream=None):
+        """(mean loss of the network, mean loss of the diagonal preconditioner) over dataset ``slot``."""
+        a, b = C.c_double(), C.c_double()
+        _check(lib.dmrg_mlp_eval(self._h, slot, C.byref(a), C.byref(b), _stream_ptr(stream)))
+        return a.value, b.value

@@ -23,29 +23,22 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <unordered_map>
 #include <vector>
 
 #include "../../include/dmrg.h"
+#include "host_common.h"
 #include "internal.h"
+#include "mlp.h"
 
 namespace {
 
 thread_local std::string g_err;
 
-struct Error : std::runtime_error {
-    dmrg_status code;
-    Error(dmrg_status c, const std::string& m) : std::runtime_error(m), code(c) {}
-};
-
-#define HIPCHK(x)                                                                            \
-    do {                                                                                     \
-        hipError_t e_ = (x);                                                                 \
-        if (e_ != hipSuccess)                                                                \
-            throw Error(DMRG_ERR_DEVICE, std::string(#x) + ": " + hipGetErrorString(e_));   \
-    } while (0)
+using dmrg::Error;
 
 using M16 = std::array<double, 256>;   // two-site operator, index (b'*4+c') * 16 + (b*4+c)
 
@@ -990,6 +983,12 @@ dmrg_status fail(const Error& e) { g_err = e.what(); return e.code; }
 
 }  // namespace
 
+namespace dmrg {
+dmrg_status record_error(const Error& e) { return fail(e); }
+void clear_error() { g_err.clear(); }
+double now_seconds() { return now(); }
+}  // namespace dmrg
+
 // ====================================================================== C-ABI
 
 extern "C" const char* dmrg_last_error(void) { return g_err.c_str(); }
@@ -1368,8 +1367,29 @@ struct DavWork {
 
 }  // namespace
 
+dmrg::MlpProblem dmrg::mlp_problem_of(const dmrg_hop* H) {
+    if (H->device < 0 || !H->d_diag) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+    HIPCHK(hipSetDevice(H->device));
+    MlpProblem p;
+    p.n = H->n_coeff;
+    p.diag = H->d_diag;
+    for (size_t k = 0; k < H->blk.size(); ++k) {
+        p.off.push_back(H->blk_off[k]);
+        p.m_a.push_back(H->blk_ma[k]);
+        p.m_d.push_back(H->blk_md[k]);
+        p.b.push_back(H->blk[k][1]);
+        p.c.push_back(H->blk[k][2]);
+    }
+    return p;
+}
+
 extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res,
                                      void* stream) {
+    return dmrg::davidson_run(H, psi, o, res, stream, nullptr);
+}
+
+dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res, void* stream,
+                               MlpRecord* rec) {
     g_err.clear();
     try {
         if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
@@ -1377,10 +1397,17 @@ extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_op
         if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
         if (o->use_graph) throw Error(DMRG_ERR_UNSUPPORTED, "use_graph is reserved");
         if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+        if (o->precond != DMRG_PRECOND_DIAG && o->precond != DMRG_PRECOND_MLP) throw Error(DMRG_ERR_ARG, "unknown preconditioner");
+        if (o->precond == DMRG_PRECOND_MLP && !o->mlp) throw Error(DMRG_ERR_ARG, "learned preconditioner requested without a network");
         HIPCHK(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)stream;
         const int64_t n = H->n_coeff;
         const int K = o->max_sub;
+        std::unique_ptr<dmrg::MlpSession> sess;
+        if (o->precond == DMRG_PRECOND_MLP || rec)
+            sess.reset(new dmrg::MlpSession(o->precond == DMRG_PRECOND_MLP ? o->mlp : nullptr, rec ? rec->mlp : nullptr,
+                                            rec ? rec->slot : 0, rec ? rec->rows_per_iter : 1, rec ? rec->seed : 0,
+                                            rec ? rec->psi_star : nullptr, mlp_problem_of(H), s));
         DavWork w;
         w.V = w.get<double>((size_t)K * n);
         w.W = w.get<double>((size_t)K * n);
@@ -1531,6 +1558,7 @@ extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_op
             }
             HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             have_prev = true;
+            if (sess) sess->correction(r, u, t, theta, w.V, k);
             orth(k, t);
             double nt = normalize(t);
             if (nt < 1e-14) break;
@@ -1553,6 +1581,7 @@ extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_op
         res->matvecs_split = matvecs_split;
         res->t_total = now() - t_start;
         res->t_hpsi = t_hpsi;
+        if (rec) rec->rows_added = sess->rows_recorded();
         if (!converged) { g_err = "Davidson did not converge"; return DMRG_NOT_CONVERGED; }
         return DMRG_OK;
     } catch (const Error& e) {
