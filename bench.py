@@ -44,6 +44,9 @@ def main():
     ap.add_argument("--workload", choices=["precision", "batch"], default="precision",
                     help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems")
     ap.add_argument("--n-problems", type=int, default=128)
+    ap.add_argument("--profile-kernels", action="store_true",
+                    help="profiling run: 3 H.psi calls per precision and a plain device copy of 1 GiB "
+                         "(calibration of the traffic counters); prints per-call event timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -76,6 +79,8 @@ def main():
     x = torch.as_tensor(random_vector(n, 7), device=dev)
     y64 = torch.empty_like(x)
     ysp = torch.empty_like(x)
+    if args.profile_kernels:
+        return profile_kernels(args, hop, st, x, y64, ysp, stream)
 
     # --- kernel timing with events on the launch stream
     def time_kernel(prec):
@@ -132,6 +137,10 @@ def main():
             log(f"[bench] converge {name}: {conv[name]}")
         conv["dE"] = abs(conv["split"]["energy"] - conv["fp64"]["energy"])
 
+    # --- learned preconditioner: one application (features + MFMA inference) at this size
+    mlp_ms = mlp_apply_ms(hop, n, stream)
+    log(f"[bench] learned preconditioner application: {mlp_ms:.3f} ms")
+
     # --- roofline of the dominant kernel (split sector-GEMM kernel)
     achieved = st["flops"] / tsp / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
@@ -161,6 +170,7 @@ def main():
         "split": {"tflops": round(value, 3), "ms_per_iter": round(s_iter_sp * 1e3, 3),
                   "kernel_ms": round(tsp * 1e3, 4), "rel_matvec_err": rel_mv},
         "converge": conv,
+        "mlp_precond_ms": round(mlp_ms, 4),
         "build_seconds": round(t_build, 2),
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -232,27 +242,77 @@ def bench_batch(args):
 
 
 def cpu_baseline(h, eri, left, right, na, nb, site, n):
-    """Oracle H.psi on ~5% of the output blocks (setup untimed), single-threaded numpy."""
+    """The oracle's full H.psi of the same workload, single-threaded numpy, repeated until at least
+    10 s of CPU work (at most 3 calls); the oracle's setup (task list) is not timed."""
     from threadpoolctl import threadpool_limits
 
     from dmrg_inputs import random_vector
     from oracle.hpsi import OracleHop
     log("[bench] cpu baseline: oracle setup (untimed)")
     oh = OracleHop(h, eri, left, right, na, nb, site)
-    rng = np.random.default_rng(0)
-    nbk = len(oh.layout.blocks)
-    targets = rng.choice(nbk, max(1, nbk // 20), replace=False)
-    tasks = oh.target_tasks(targets)
+    tasks = oh.tasks()
     fl = oh.flops(tasks)
     x = random_vector(n, 7)
+    calls, dt = 0, 0.0
     with threadpool_limits(limits=1):
-        t = time.perf_counter()
-        oh.apply(x, tasks=tasks)
-        dt = time.perf_counter() - t
-    log(f"[bench] cpu baseline: {fl:.3e} flops in {dt:.1f}s")
-    return {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"H.psi restricted to {len(targets)} of {nbk} output blocks ({len(tasks)} sector tasks, "
-                      f"{fl:.3e} flops), numpy FP64, one thread; setup untimed"}
+        while calls < 3 and dt < 10.0:
+            t = time.perf_counter()
+            oh.apply(x, tasks=tasks)
+            dt += time.perf_counter() - t
+            calls += 1
+    log(f"[bench] cpu baseline: {calls} x {fl:.3e} flops in {dt:.1f}s")
+    return {"value": round(calls * fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
+            "seconds": round(dt, 2),
+            "sample": f"{calls} full H.psi call(s) of the same workload ({len(tasks)} sector tasks, {fl:.3e} flops "
+                      f"each), oracle numpy FP64 on one host thread; oracle setup untimed"}
+
+
+def mlp_apply_ms(hop, n, stream, reps=5):
+    """Device time of one learned-preconditioner application (features + MFMA inference) on |psi|."""
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_vector
+    net = dm.Mlp(device=0, seed=1)
+    r = torch.as_tensor(random_vector(n, 21), device="cuda:0")
+    u = torch.as_tensor(random_vector(n, 22), device="cuda:0")
+    feat = torch.empty((n, dm.MLP_IN), dtype=torch.float32, device="cuda:0")
+    t = torch.empty_like(r)
+    m = torch.empty(n, dtype=torch.float32, device="cuda:0")
+    ts = []
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        dm.Mlp.features(hop, r, u, -100.0, feat, t, stream=stream)
+        net.forward(feat, m, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.mean(ts[1:]))
+
+
+def profile_kernels(args, hop, st, x, y64, ysp, stream):
+    """Short run for rocprofv3: H.psi x3 per precision, then a 1 GiB device-to-device copy x3 (the
+    known-size kernel that calibrates FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    import paper_2001_04890_amd as dm
+    res = {}
+    for name, prec, out in (("split", dm.PREC_SPLIT2, ysp), ("fp64", dm.PREC_FP64, y64)):
+        ms = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            hop.hpsi(x, out, prec, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ms.append(a.elapsed_time(b))
+        res[name] = {"event_ms": [round(v, 4) for v in ms]}
+    src = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile": res, "flops_per_matvec": st["flops"], "algorithmic_bytes": st["bytes"],
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
 
 
 if __name__ == "__main__":
