@@ -211,6 +211,23 @@ struct dmrg_hop {
     dmrg::HpsiPlan plan{};
     std::vector<dmrg::HpsiLaunch> launches;
     std::vector<dmrg::HpsiPhase> phases;
+    // split path: LDS-staged kernel over tiled operands, plus the one-wave kernel (row-major hi/lo
+    // operands, plan_fb) for targets whose blocks exceed the LDS stage size
+    std::vector<dmrg::PoolBlock> pool_blocks;   // every block of the FP64 pool (for the tiled split)
+    uint16_t* d_tiled = nullptr;                // tiled hi/lo operators + identity blocks
+    int64_t tiled_size = 0;
+    int64_t ident_off[3] = {-1, -1, -1};        // tiled identity blocks of size 32, 64, 96
+    dmrg::LdsPlan lplan{};
+    dmrg::HpsiPlan plan_fb{};
+    std::vector<dmrg::HpsiLaunch> launches_fb;
+    std::vector<dmrg::HpsiPhase> phases_fb;
+    int n_fallback_targets = 0;
+    int tune_lds_items = 16384;                 // target number of LDS work items per H.psi
+    int tune_small_mode = 1;                    // 1: single-tile sources run in the task-mode kernel
+    int tune_small_nr = 2;                      // task mode: most row tiles per wavefront (1 or 2)
+    int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
+    int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
+    int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t n_alpha = 0;
     int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
@@ -610,9 +627,8 @@ double mat_bytes(const dmrg_hop& H, int m) { return m < 0 ? 0.0 : H.mats[m].byte
 //    the phase's tasks of its target block, cut into chunks of bounded MFMA cost (about
 //    tune_items items per matvec); a tile split over several chunks writes partial tiles that the
 //    phase's reduction adds in order.
-void build_plan(dmrg_hop& H, hipStream_t s) {
-    for (void* p : H.plan_allocations) (void)hipFree(p);
-    H.plan_allocations.clear();
+void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, bool split_bufs, dmrg::HpsiPlan& plan,
+                     std::vector<dmrg::HpsiLaunch>& launches_out, std::vector<dmrg::HpsiPhase>& phases_out) {
     constexpr double kCacheBudget = 96.0 * 1024 * 1024;
     // packed input layout: every psi block padded to multiples of 32 in both directions
     std::vector<dmrg::PackBlock> packs;
@@ -628,7 +644,8 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     std::map<std::pair<int, int>, int> pair_phase;
     {
         std::vector<std::pair<int, int>> pairs;
-        for (const auto& t : H.tasks) pairs.push_back({t.rm, t.lm});
+        for (const auto& t : H.tasks)
+            if (!only || (*only)[t.j]) pairs.push_back({t.rm, t.lm});
         std::sort(pairs.begin(), pairs.end());
         pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
         std::vector<double> pb(pairs.size());
@@ -642,9 +659,9 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
             pair_phase[{pairs[k].second, pairs[k].first}] = ph;
             cum += pb[k];
         }
-        H.plan.n_phases = np;
+        plan.n_phases = np;
     }
-    const int np = H.plan.n_phases;
+    const int np = plan.n_phases;
     // device tasks, grouped per target block and phase (stable: source order kept inside)
     std::vector<dmrg::Task> dtasks;
     dtasks.reserve(H.tasks.size());
@@ -685,6 +702,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     double total = 0.0, max_task = 0.0;
     const int tile_cols = 16 * H.tune_max_tq;
     for (size_t j = 0; j < H.blk.size(); ++j) {
+        if (only && !(*only)[j]) continue;
         int mj = H.blk_ma[j], nj = H.blk_md[j];
         for (int r0 = 0; r0 < mj; r0 += dmrg::kTileRows)
             for (int c0 = 0; c0 < nj; c0 += tile_cols) {
@@ -701,8 +719,8 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     const double cmax = std::max({total / std::max(1, H.tune_items), max_task, 256.0});
     std::vector<dmrg::Item> all_items;
     std::vector<dmrg::Reduce> all_red;
-    H.launches.clear();
-    H.phases.clear();
+    launches_out.clear();
+    phases_out.clear();
     int64_t part_max = 0;
     for (int ph = 0; ph < np; ++ph) {
         std::vector<dmrg::Item> items;
@@ -797,22 +815,22 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
             perm = out;
         }
         dmrg::HpsiPhase P;
-        P.launch_begin = (int)H.launches.size();
+        P.launch_begin = (int)launches_out.size();
         const int base = (int)all_items.size();
         for (size_t i = 0; i < perm.size(); ++i) {
             all_items.push_back(items[perm[i]]);
             const int cls = iclass[perm[i]];
-            if (H.launches.size() == (size_t)P.launch_begin || H.launches.back().cls != cls)
-                H.launches.push_back({cls, base + (int)i, 0});
-            H.launches.back().item_count++;
+            if (launches_out.size() == (size_t)P.launch_begin || launches_out.back().cls != cls)
+                launches_out.push_back({cls, base + (int)i, 0});
+            launches_out.back().item_count++;
         }
-        P.launch_end = (int)H.launches.size();
+        P.launch_end = (int)launches_out.size();
         P.reduce_begin = (int)all_red.size();
         for (const auto& r : reduces) all_red.push_back(r);
         P.reduce_end = (int)all_red.size();
-        H.phases.push_back(P);
+        phases_out.push_back(P);
     }
-    H.n_items = (int)all_items.size();
+    if (!only) H.n_items = (int)all_items.size();
     H.n_dev_tasks = (int64_t)dtasks.size();
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1')
@@ -827,25 +845,310 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     if (!all_red.empty())
         HIPCHK(hipMemcpyAsync(d_red, all_red.data(), all_red.size() * sizeof(all_red[0]), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_packs, packs.data(), packs.size() * sizeof(packs[0]), hipMemcpyHostToDevice, s));
-    H.d_tasks = d_tasks;
-    H.plan.items = d_items;
-    H.plan.reduces = d_red;
-    H.plan.tasks = d_tasks;
-    H.plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1) * dmrg::kPartialVecs);
-    H.plan.partial_size = part_max;
-    H.plan.launches = H.launches.data();
-    H.plan.phases = H.phases.data();
-    H.plan.packs = d_packs;
-    H.plan.n_packs = (int)packs.size();
-    H.plan.packed_size = psize;
-    H.plan.xp = plan_alloc<double>(H, (size_t)psize * dmrg::kPartialVecs);
-    if (H.has_split) {
-        H.plan.xr_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        H.plan.xr_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        H.plan.xt_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        H.plan.xt_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+    if (!only) H.d_tasks = d_tasks;
+    plan.items = d_items;
+    plan.reduces = d_red;
+    plan.tasks = d_tasks;
+    plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1) * dmrg::kPartialVecs);
+    plan.partial_size = part_max;
+    plan.launches = launches_out.data();
+    plan.phases = phases_out.data();
+    plan.packs = d_packs;
+    plan.n_packs = (int)packs.size();
+    plan.packed_size = psize;
+    plan.xp = plan_alloc<double>(H, (size_t)psize * dmrg::kPartialVecs);
+    if (split_bufs) {
+        plan.xr_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        plan.xr_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        plan.xt_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        plan.xt_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
     }
     HIPCHK(hipStreamSynchronize(s));
+}
+
+// Launch plan of the split kernels of hpsi_lds.hip. The tasks of every target block whose own and
+// sources' padded dimensions are at most 96 are divided into small tasks (source one 32 x 32 tile)
+// for the task-mode kernel and the others for the LDS-staged row-mode kernel; both lists keep the
+// source order. Row-mode items cover the whole target (all rows and columns), task-mode items a row
+// block of one or two row tiles; each list is cut into items of bounded cost, and a target row block
+// covered by several items of one kind gets partial tiles that a reduction adds in item order.
+// Targets with larger blocks are flagged in `fallback` for the one-wave kernel.
+void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
+    const size_t nb = H.blk.size();
+    fallback.assign(nb, 0);
+    std::vector<int64_t> pk_off(nb);
+    std::vector<dmrg::PackBlock> packs;
+    int64_t psize = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        int pa = dmrg::ld_of(H.blk_ma[i]), pd = dmrg::ld_of(H.blk_md[i]);
+        pk_off[i] = psize;
+        packs.push_back({H.blk_off[i], psize, H.blk_ma[i], H.blk_md[i], pa, pd});
+        psize += (int64_t)pa * pd;
+    }
+    auto ident = [&](int p) -> int64_t {
+        int k = p / 32 - 1;
+        if (k < 0 || k > 2 || H.ident_off[k] < 0) throw Error(DMRG_ERR_ARG, "internal: no tiled identity block");
+        return H.ident_off[k];
+    };
+    // one run of tasks of one kernel kind for one target row block
+    struct Run { int j, kind, cls, r0, c0, nr, tq; int32_t tb, te; };
+    std::vector<dmrg::LTask> lt;
+    lt.reserve(H.tasks.size());
+    std::vector<Run> runs;
+    auto row_cost = [](const dmrg::LTask& L, int tp, int tq, bool new_src) {
+        return 3.0 * L.pd32 * (2.0 * L.pa32 * tp + tq * tp) + 24.0 + (new_src ? 2.0 * L.pd32 * L.pa32 : 0.0);
+    };
+    auto small_cost = [](int nr, int tq) { return 3.0 * (2.0 * nr + nr * tq) + 24.0; };
+    double total = 0.0;
+    size_t k = 0;
+    for (size_t j = 0; j < nb; ++j) {
+        size_t kb = k;
+        while (k < H.tasks.size() && H.tasks[k].j == (int)j) ++k;
+        if (k == kb) continue;
+        int smax = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
+        for (size_t t = kb; t < k; ++t) {
+            const int i = H.tasks[t].i;
+            smax = std::max({smax, dmrg::ld_of(H.blk_ma[i]), dmrg::ld_of(H.blk_md[i])});
+        }
+        if (smax > 96) { fallback[j] = 1; continue; }
+        const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, tq = dmrg::rows_of(H.blk_md[j]) / 16;
+        std::vector<dmrg::LTask> big, small;
+        int big_s = 32;
+        std::vector<size_t> order;
+        for (size_t t = kb; t < k; ++t) order.push_back(t);
+        if (H.tune_lds_task_order == 1)   // operator-pair order (same across targets) instead of source order
+            std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
+                const auto &a = H.tasks[x], &b = H.tasks[y];
+                if (a.lm != b.lm) return a.lm < b.lm;
+                return a.rm < b.rm;
+            });
+        for (size_t t : order) {
+            const auto& ht = H.tasks[t];
+            const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
+            const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
+            dmrg::LTask L;
+            L.x_off = 2 * pk_off[ht.i];
+            L.a_off = ht.lm >= 0 ? 2 * H.mats[ht.lm].pool_of_in[a] : ident(pa);
+            L.b_off = ht.rm >= 0 ? 2 * H.mats[ht.rm].pool_of_in[d] : ident(pd);
+            L.f = (float)ht.f;
+            L.pa32 = (int16_t)(pa / 32);
+            L.pd32 = (int16_t)(pd / 32);
+            if (L.pa32 == 1 && L.pd32 == 1 && H.tune_small_mode) small.push_back(L);
+            else { big.push_back(L); big_s = std::max({big_s, pa, pd}); }
+        }
+        if (!big.empty()) {
+            const int S = std::max({big_s, 16 * nrt <= 64 ? 32 : 96, dmrg::ld_of(H.blk_md[j])});
+            const int Sc = S <= 32 ? 32 : S <= 64 ? 64 : 96;
+            const int tp = nrt > dmrg::kLdsWaves ? 2 : 1;
+            Run R{(int)j, 0, Sc == 32 ? 0 : Sc == 64 ? 1 : (tp == 1 ? 2 : 3), 0, 0, nrt, tq, (int32_t)lt.size(), 0};
+            int64_t px = -1;
+            for (const auto& L : big) { lt.push_back(L); total += row_cost(L, tp, tq, L.x_off != px); px = L.x_off; }
+            R.te = (int32_t)lt.size();
+            runs.push_back(R);
+        }
+        if (!small.empty()) {
+            const int tb = (int32_t)lt.size();
+            for (const auto& L : small) lt.push_back(L);
+            const int te = (int32_t)lt.size();
+            // classes (1,2) (2,2) (1,4); targets wider than 4 column tiles get column blocks
+            const int NQ = tq <= 2 && H.tune_small_nq <= 2 ? 2 : 4;
+            const int NR = NQ == 2 && nrt > 1 && H.tune_small_nr > 1 ? 2 : 1;
+            const int cls = NQ == 4 ? 2 : NR - 1;
+            for (int r = 0; r < nrt; r += NR)
+                for (int c = 0; c < tq; c += NQ) {
+                    const int nr = std::min(NR, nrt - r), nq = std::min(NQ, tq - c);
+                    runs.push_back({(int)j, 1, cls, 16 * r, 16 * c, nr, nq, tb, te});
+                    total += (te - tb) * small_cost(nr, nq);
+                }
+        }
+    }
+    H.lplan = dmrg::LdsPlan{};
+    const double cmax = std::max(total / std::max(1, H.tune_lds_items), 600.0);
+    struct It { dmrg::Item item; double cost; int kind, cls; };
+    std::vector<It> its;
+    std::vector<dmrg::Reduce> reds, reds_small;
+    int64_t part = 0;
+    for (const Run& R : runs) {
+        const int tp = R.kind == 0 && R.nr > dmrg::kLdsWaves ? 2 : 1;
+        std::vector<std::pair<int32_t, int32_t>> chunks;
+        std::vector<double> ccost;
+        int32_t b = R.tb;
+        double c = 0.0;
+        int64_t px = -1;
+        for (int32_t t = R.tb; t < R.te; ++t) {
+            const double tc = R.kind == 0 ? row_cost(lt[t], tp, R.tq, lt[t].x_off != px || t == b) : small_cost(R.nr, R.tq);
+            px = lt[t].x_off;
+            if (c + tc > cmax && t > b) { chunks.push_back({b, t}); ccost.push_back(c); b = t; c = 0.0; }
+            c += tc;
+        }
+        chunks.push_back({b, R.te});
+        ccost.push_back(c);
+        const int j = R.j;
+        const int tm = 16 * R.nr, tn = 16 * R.tq;
+        if (chunks.size() == 1) {
+            its.push_back({{H.blk_off[j], -1, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, chunks[0].first, chunks[0].second},
+                           ccost[0], R.kind, R.cls});
+        } else {
+            (R.kind == 0 ? reds : reds_small)
+                .push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, tm, tn, (int32_t)chunks.size(), 0});
+            for (size_t q = 0; q < chunks.size(); ++q) {
+                its.push_back({{H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, chunks[q].first,
+                                chunks[q].second},
+                               ccost[q], R.kind, R.cls});
+                part += (int64_t)tm * tn;
+            }
+        }
+    }
+    // launch order: row-mode classes, then task-mode classes; heaviest item first inside a class
+    std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) {
+        if (a.kind != b.kind) return a.kind < b.kind;
+        if (a.cls != b.cls) return a.cls < b.cls;
+        return a.cost > b.cost;
+    });
+    if (H.tune_lds_order == 1) {
+        // XCD-aware: workgroups are dealt to the 8 XCDs round-robin, so items at positions of one
+        // residue mod 8 share an L2. Items of targets with the same left sector (which read the same
+        // left operator blocks) are kept on one XCD; sectors are balanced over the XCDs by cost.
+        constexpr int nx = 8;
+        size_t c0 = 0;
+        std::vector<It> out;
+        out.reserve(its.size());
+        while (c0 < its.size()) {
+            size_t c1 = c0;
+            while (c1 < its.size() && its[c1].kind == its[c0].kind && its[c1].cls == its[c0].cls) ++c1;
+            std::map<int, std::vector<size_t>> grp;
+            std::map<int, double> gcost;
+            for (size_t i = c0; i < c1; ++i) {
+                const int a = H.blk[std::lower_bound(H.blk_off.begin(), H.blk_off.end(), its[i].item.y_off) -
+                                    H.blk_off.begin()][0];
+                grp[a].push_back(i);
+                gcost[a] += its[i].cost;
+            }
+            std::vector<std::pair<double, int>> gorder;
+            for (auto& kv : gcost) gorder.push_back({-kv.second, kv.first});
+            std::sort(gorder.begin(), gorder.end());
+            std::vector<double> load(nx, 0.0);
+            std::vector<std::vector<size_t>> lane(nx);
+            for (auto& og : gorder) {
+                const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                load[x] -= og.first;
+                for (size_t i : grp[og.second]) lane[x].push_back(i);
+            }
+            std::vector<size_t> pos(nx, 0);
+            for (size_t left = c1 - c0, p = 0; left > 0; ++p) {
+                int x = (int)(p % nx);
+                if (pos[x] >= lane[x].size()) {
+                    size_t rem = 0;
+                    for (int y2 = 0; y2 < nx; ++y2)
+                        if (lane[y2].size() - pos[y2] > rem) { rem = lane[y2].size() - pos[y2]; x = y2; }
+                }
+                out.push_back(its[lane[x][pos[x]++]]);
+                --left;
+            }
+            c0 = c1;
+        }
+        its.swap(out);
+    }
+    std::vector<dmrg::Item> items;
+    items.reserve(its.size());
+    int cnt_row[dmrg::kLdsClasses] = {0}, cnt_small[dmrg::kSmallClasses] = {0};
+    for (const It& x : its) {
+        items.push_back(x.item);
+        if (x.kind == 0) cnt_row[x.cls]++; else cnt_small[x.cls]++;
+    }
+    H.lplan.cls_begin[0] = 0;
+    for (int c = 0; c < dmrg::kLdsClasses; ++c) H.lplan.cls_begin[c + 1] = H.lplan.cls_begin[c] + cnt_row[c];
+    H.lplan.small_begin[0] = H.lplan.cls_begin[dmrg::kLdsClasses];
+    for (int c = 0; c < dmrg::kSmallClasses; ++c) H.lplan.small_begin[c + 1] = H.lplan.small_begin[c] + cnt_small[c];
+    H.n_fallback_targets = 0;
+    for (char f : fallback) H.n_fallback_targets += f;
+    if (items.empty()) return;
+    const int n_red_row = (int)reds.size();
+    reds.insert(reds.end(), reds_small.begin(), reds_small.end());
+    dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
+    dmrg::LTask* d_lt = plan_alloc<dmrg::LTask>(H, lt.size());
+    dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
+    dmrg::PackBlock* d_packs = plan_alloc<dmrg::PackBlock>(H, packs.size());
+    HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_lt, lt.data(), lt.size() * sizeof(lt[0]), hipMemcpyHostToDevice, s));
+    if (!reds.empty()) HIPCHK(hipMemcpyAsync(d_red, reds.data(), reds.size() * sizeof(reds[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_packs, packs.data(), packs.size() * sizeof(packs[0]), hipMemcpyHostToDevice, s));
+    H.lplan.items = d_items;
+    H.lplan.tasks = d_lt;
+    H.lplan.reduces = d_red;
+    H.lplan.n_reduces = (int)reds.size();
+    H.lplan.n_reduces_row = n_red_row;
+    H.lplan.partial_size = part;
+    H.lplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1) * dmrg::kPartialVecs);
+    H.lplan.packs = d_packs;
+    H.lplan.n_packs = (int)packs.size();
+    H.lplan.xt_size = 2 * psize;
+    H.lplan.xt = plan_alloc<uint16_t>(H, (size_t)2 * psize * dmrg::kPartialVecs);
+    if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
+        if (e[0] == '1') {
+            std::fprintf(stderr, "[dmrg lds plan] items %zu row classes", items.size());
+            for (int c = 0; c < dmrg::kLdsClasses; ++c) std::fprintf(stderr, " %d", cnt_row[c]);
+            std::fprintf(stderr, " small classes");
+            for (int c = 0; c < dmrg::kSmallClasses; ++c) std::fprintf(stderr, " %d", cnt_small[c]);
+            std::fprintf(stderr, " reduces %zu partial %.1f MB fallback %d\n", reds.size(), part * 8e-6,
+                         H.n_fallback_targets);
+        }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// Every launch plan of the handle: FP64 (all targets) and, with split operators, the LDS-staged
+// plan plus the one-wave split plan for the targets it does not cover.
+void build_plan(dmrg_hop& H, hipStream_t s) {
+    for (void* p : H.plan_allocations) (void)hipFree(p);
+    H.plan_allocations.clear();
+    build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
+    H.plan_fb = dmrg::HpsiPlan{};
+    H.launches_fb.clear();
+    H.phases_fb.clear();
+    H.n_fallback_targets = 0;
+    if (!H.has_split) return;
+    std::vector<char> fb;
+    build_lds_plan(H, s, fb);
+    if (H.n_fallback_targets > 0) {
+        if (!H.d_hi) throw Error(DMRG_ERR_ARG, "internal: row-major split operators missing");
+        build_plan_core(H, s, &fb, true, H.plan_fb, H.launches_fb, H.phases_fb);
+    }
+}
+
+// True when some target block (or one of its sources) has a padded dimension above the LDS stage
+// size of the LDS-staged split kernel.
+bool needs_fallback(const dmrg_hop& H) {
+    std::vector<int> smax(H.blk.size(), 0);
+    for (size_t j = 0; j < H.blk.size(); ++j) smax[j] = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
+    for (const auto& t : H.tasks)
+        smax[t.j] = std::max({smax[t.j], dmrg::ld_of(H.blk_ma[t.i]), dmrg::ld_of(H.blk_md[t.i])});
+    for (int v : smax) if (v > 96) return true;
+    return false;
+}
+
+// Tiled hi/lo copy of the whole FP64 pool (internal.h) followed by tiled identity blocks of sizes
+// 32, 64 and 96 (hi = 1 on the diagonal, lo = 0), which stand in for identity factors.
+void make_tiled_split(dmrg_hop& H, hipStream_t s) {
+    int64_t n = 2 * H.pool_size;
+    std::vector<uint16_t> id;
+    for (int k = 0; k < 3; ++k) {
+        const int p = 32 * (k + 1), r16 = p / 16, k32 = p / 32;
+        H.ident_off[k] = n + (int64_t)id.size();
+        const size_t base = id.size();
+        id.resize(base + (size_t)r16 * k32 * dmrg::kTileU16, 0);
+        for (int i = 0; i < p; ++i) {
+            const int rt = i / 16, kt = i / 32, lane = (i % 16) + 16 * ((i % 32) / 8), u = i % 8;
+            id[base + (size_t)(rt * k32 + kt) * dmrg::kTileU16 + lane * 8 + u] = 0x3F80;   // bf16 1.0
+        }
+    }
+    H.tiled_size = n + (int64_t)id.size();
+    H.d_tiled = dev_alloc<uint16_t>(H, H.tiled_size);
+    dmrg::PoolBlock* d_pb = dev_alloc<dmrg::PoolBlock>(H, H.pool_blocks.size());
+    HIPCHK(hipMemcpyAsync(d_pb, H.pool_blocks.data(), H.pool_blocks.size() * sizeof(dmrg::PoolBlock),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(H.d_tiled + n, id.data(), id.size() * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    HIPCHK(dmrg::launch_split_tiled(H.d_pool, d_pb, (int)H.pool_blocks.size(), H.d_tiled, s));
+    HIPCHK(hipStreamSynchronize(s));   // the staging vector goes out of scope
 }
 
 void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
@@ -854,8 +1157,10 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     // 1. pool layout: every stored block of both sides (padded rows), then derived matrices
     std::vector<int64_t> base_off[2];
     int64_t pool = 0;
+    H.pool_blocks.clear();
     auto reserve = [&](int rows, int cols) {
         int64_t o = pool;
+        H.pool_blocks.push_back({o, dmrg::rows_of(rows) / 16, dmrg::ld_of(cols) / 32});
         pool += (int64_t)dmrg::rows_of(rows) * dmrg::ld_of(cols);
         pool = (pool + 31) / 32 * 32;
         return o;
@@ -929,11 +1234,15 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
         HIPCHK(hipMemcpyAsync(d_pt, pterms.data(), pterms.size() * sizeof(pterms[0]), hipMemcpyHostToDevice, s));
         HIPCHK(dmrg::launch_presum(d_pb, (int)pblocks.size(), d_pt, H.d_pool, s));
     }
-    // 4. split copies
+    // 4. split copies: tiled hi/lo for the LDS-staged kernel; row-major hi/lo only when some target
+    //    needs the one-wave kernel
     if (H.has_split) {
-        H.d_hi = dev_alloc<uint16_t>(H, pool);
-        H.d_lo = dev_alloc<uint16_t>(H, pool);
-        HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
+        make_tiled_split(H, s);
+        if (needs_fallback(H)) {
+            H.d_hi = dev_alloc<uint16_t>(H, pool);
+            H.d_lo = dev_alloc<uint16_t>(H, pool);
+            HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
+        }
     }
     // 5. packed input layout, work items and launch plan
     build_plan(H, s);
@@ -1026,6 +1335,12 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_ITEMS")) H->tune_items = std::max(256, std::atoi(e));
         if (const char* e = std::getenv("DMRG_ORDER")) H->tune_order = std::max(0, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_PHASES")) H->tune_phases = std::max(0, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_LDS_ITEMS")) H->tune_lds_items = std::max(64, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_SMALL_MODE")) H->tune_small_mode = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_SMALL_NR")) H->tune_small_nr = std::max(1, std::min(2, std::atoi(e)));
+        if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
+        if (const char* e = std::getenv("DMRG_LDS_TASK_ORDER")) H->tune_lds_task_order = std::atoi(e) == 1 ? 1 : 0;
+        if (const char* e = std::getenv("DMRG_SMALL_NQ")) H->tune_small_nq = std::max(2, std::min(6, std::atoi(e))) / 2 * 2;
         H->has_split = opts && opts->want_split;
         if (dev >= 0) {
             int ndev = 0;
@@ -1134,10 +1449,13 @@ extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_
             const int nv = std::min(step, nvec - v0);
             const double* xv = x + (int64_t)v0 * H->n_coeff;
             double* yv = y + (int64_t)v0 * H->n_coeff;
-            if (precision == DMRG_PREC_FP64)
+            if (precision == DMRG_PREC_FP64) {
                 HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
-            else
-                HIPCHK(dmrg::launch_hpsi_split(H->plan, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
+            } else {
+                HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
+                if (H->n_fallback_targets > 0)
+                    HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
+            }
         }
         return DMRG_OK;
     } catch (const Error& e) {
@@ -1202,6 +1520,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
             for (const auto& t : h.tasks)
                 C->tasks.push_back({t.i + blk_base, t.j + blk_base, t.lm >= 0 ? t.lm + mat_base : -1,
                                     t.rm >= 0 ? t.rm + mat_base : -1, t.f});
+            for (const auto& pb : h.pool_blocks) C->pool_blocks.push_back({pb.off + pool_base, pb.r16, pb.k32});
             C->n_coeff += h.n_coeff;
             C->pool_size += h.pool_size;
             C->flops += h.flops;
@@ -1210,22 +1529,22 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
             C->part_coeff.push_back(C->n_coeff);
         }
         C->d_pool = dev_alloc<double>(*C, C->pool_size);
-        if (C->has_split) {
-            C->d_hi = dev_alloc<uint16_t>(*C, C->pool_size);
-            C->d_lo = dev_alloc<uint16_t>(*C, C->pool_size);
-        }
         C->d_diag = dev_alloc<double>(*C, C->n_coeff);
         int64_t pb = 0, cb = 0;
         for (int k = 0; k < n; ++k) {
             const dmrg_hop& h = *hops[k];
             HIPCHK(hipMemcpyAsync(C->d_pool + pb, h.d_pool, h.pool_size * sizeof(double), hipMemcpyDeviceToDevice, s));
-            if (C->has_split) {
-                HIPCHK(hipMemcpyAsync(C->d_hi + pb, h.d_hi, h.pool_size * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
-                HIPCHK(hipMemcpyAsync(C->d_lo + pb, h.d_lo, h.pool_size * sizeof(uint16_t), hipMemcpyDeviceToDevice, s));
-            }
             HIPCHK(hipMemcpyAsync(C->d_diag + cb, h.d_diag, h.n_coeff * sizeof(double), hipMemcpyDeviceToDevice, s));
             pb += h.pool_size;
             cb += h.n_coeff;
+        }
+        if (C->has_split) {
+            make_tiled_split(*C, s);
+            if (needs_fallback(*C)) {
+                C->d_hi = dev_alloc<uint16_t>(*C, C->pool_size);
+                C->d_lo = dev_alloc<uint16_t>(*C, C->pool_size);
+                HIPCHK(dmrg::launch_split(C->d_pool, C->pool_size, C->d_hi, C->d_lo, s));
+            }
         }
         build_plan(*C, s);
         *out = C;

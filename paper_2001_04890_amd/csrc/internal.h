@@ -55,6 +55,28 @@ struct Reduce {
     int32_t pad;
 };
 
+// ---------------------------------------------------------------- tiled split-BF16 operands
+// Split-BF16 operands of the LDS-staged sector-GEMM kernel are stored pre-tiled in MFMA fragment
+// order: a matrix with R rows (padded to 16) and K columns (padded to 32) is cut into 16 x 32 tiles,
+// tile (rt, kt) at ((rt * K/32) + kt) * kTileU16 elements, row-major over tiles. Inside a tile the
+// 64 lanes' 8-element fragments are contiguous (hi: lane * 8 + u, lo: 512 + lane * 8 + u) with lane
+// l = (row % 16) + 16 * ((col % 32) / 8), u = col % 8 -- the operand layout of
+// v_mfma_f32_16x16x32_bf16. A pool block of rows_of(R) x ld_of(K) doubles at pool offset o occupies
+// exactly the u16 range [2 o, 2 o + 2 rows_of(R) ld_of(K)) of the tiled array.
+constexpr int kTileU16 = 1024;
+struct PoolBlock { int64_t off; int32_t r16, k32; };
+
+// Task of the LDS-staged split kernel: Y_tile += f * A . X . B^T with every factor present (identity
+// factors point at tiled identity blocks). Offsets are u16 offsets into the tiled arrays.
+struct LTask {
+    int64_t x_off;   // tiled X^T of the source block (see k_pack_xt)
+    int64_t a_off;   // tiled A block (rows = target rows, K = source rows)
+    int64_t b_off;   // tiled B block (rows = target cols, K = source cols)
+    float   f;
+    int16_t pa32;    // source rows padded to 32, in units of 32
+    int16_t pd32;    // source cols padded to 32, in units of 32
+};
+
 // Packing of one psi block into the padded input layout.
 struct PackBlock {
     int64_t src_off;         // offset in the caller's x (m_a x m_d, row-major)
@@ -118,6 +140,32 @@ struct HpsiPlan {
     uint16_t* xt_lo;
 };
 
+// Launch plan of the LDS-staged split kernel (hpsi_lds.hip). Items (internal.h Item) cover whole
+// target row blocks; launch class = (S, TP): S = largest padded dimension (32, 64 or 96) sizing the
+// LDS stages, TP = row tiles per wave; each class is one launch of kLdsWaves-wave workgroups.
+// Tasks whose source is a single 32 x 32 tile run in the task-mode kernel (one wavefront per target
+// block of NR row tiles and at most NQ column tiles), classes (NR, NQ) = (1,2) (2,2) (1,4), launched
+// after the row-mode classes; items[small_begin[c] .. small_begin[c+1]).
+constexpr int kLdsWaves = 4;
+constexpr int kLdsClasses = 4;          // (32,1) (64,1) (96,1) (96,2)
+constexpr int kSmallClasses = 3;
+struct LdsPlan {
+    const Item* items = nullptr;        // device
+    const LTask* tasks = nullptr;       // device
+    const Reduce* reduces = nullptr;    // device: row-mode records first, then task-mode records
+    int n_reduces = 0;                  // all records
+    int n_reduces_row = 0;              // records of row-mode runs (reduced in a launch of their own:
+                                        // a target may have records of both kinds)
+    int cls_begin[kLdsClasses + 1] = {0, 0, 0, 0, 0};   // item ranges per class
+    int small_begin[kSmallClasses + 1] = {0, 0, 0, 0};
+    double* partial = nullptr;          // device, partial_size * kPartialVecs doubles
+    int64_t partial_size = 0;
+    const PackBlock* packs = nullptr;   // device (same packing geometry as HpsiPlan)
+    int n_packs = 0;
+    int64_t xt_size = 0;                // u16 elements of one tiled X^T vector (2 * packed_size)
+    uint16_t* xt = nullptr;             // device, xt_size * kPartialVecs
+};
+
 // Launchers (kernels.hip). All asynchronous on `s`.
 hipError_t launch_presum(const PresumBlock* blocks, int n_blocks, const PresumTerm* terms,
                          double* pool, hipStream_t s);
@@ -139,5 +187,13 @@ hipError_t launch_precond(const double* r, const double* d, double theta, double
                           hipStream_t s);
 hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t s);
 int multidot_parts(int64_t n);
+// Tiled split-BF16 kernels (hpsi_lds.hip).
+hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
+// y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).
+hipError_t launch_hpsi_lds(const LdsPlan& plan, const uint16_t* pool_t, const double* x, double* y, int64_t n_coeff,
+                           int nvec, bool zero_y, hipStream_t s);
+// Old-kernel split path over a plan without clearing y first.
+hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
+                                 double* y, int64_t n_coeff, int nvec, hipStream_t s);
 }  // namespace dmrg
 #endif

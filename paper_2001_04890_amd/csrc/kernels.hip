@@ -287,10 +287,11 @@ static hipError_t launch_pack(const HpsiPlan& plan, const double* x, int64_t n_c
 
 // y = 0, then phase by phase: the item launches of every tile class, then the phase's reductions
 template <class F>
-static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, int nvec, hipStream_t s, F&& launch_one) {
+static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, int nvec, hipStream_t s, F&& launch_one,
+                             bool zero_y = true) {
     int64_t n = n_coeff * nvec, blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
+    if (zero_y) hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
     for (int ph = 0; ph < plan.n_phases; ++ph) {
         const HpsiPhase& P = plan.phases[ph];
         for (int l = P.launch_begin; l < P.launch_end; ++l) {
@@ -492,15 +493,26 @@ __global__ __launch_bounds__(64, min_waves_split(TP, TQ)) void k_hpsi_split(cons
     store_tile<TP, TQ>(I, y, part, acc, li, g, false);
 }
 
-hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x, double* y,
-                             int64_t n_coeff, int nvec, hipStream_t s) {
+static hipError_t hpsi_split_impl(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
+                                  double* y, int64_t n_coeff, int nvec, hipStream_t s, bool zero_y) {
     hipError_t e = launch_pack(plan, x, n_coeff, nvec, 1, s);
     if (e != hipSuccess) return e;
     const int64_t ss = plan.partial_size;
     return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
         DMRG_CLASS_SWITCH(k_hpsi_split, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, hi, lo, plan.xp,
                           plan.xr_hi, plan.xr_lo, plan.xt_hi, plan.xt_lo, y, plan.partial, n_coeff, plan.packed_size, ss)
-    });
+    }, zero_y);
+}
+
+hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x, double* y,
+                             int64_t n_coeff, int nvec, hipStream_t s) {
+    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, true);
+}
+
+hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
+                                 double* y, int64_t n_coeff, int nvec, hipStream_t s) {
+    if (plan.n_phases == 0) return hipSuccess;
+    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, false);
 }
 
 // ------------------------------------------------------------------ diag(H)

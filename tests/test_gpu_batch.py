@@ -1,9 +1,11 @@
 """GPU tests of batching (one launch sequence for many H.psi problems) and of the plan autotuner.
 
 A merged handle must give, for every part, the H.psi of that part's own handle: identical up to the
-order in which task contributions are summed (the work items are cut differently), bar 1e-12
-relative to max|y| in FP64 and in split precision (the split rounding happens inside a task, which
-is the same in both). One part is also checked against the FP64 oracle.
+order in which task contributions are summed (the work items are cut differently). FP64: bar 1e-12
+relative to max|y|. Split precision: the per-task BF16 rounding is identical, but task results are
+summed in FP32 over runs of at most 8 tasks before the FP64 update, and the runs start at item
+boundaries, which differ between the two plans; each FP32 addition rounds at 2^-24 relative to the
+running sum, so the bar is 2e-6 (measured 2.3e-7). One part is also checked against the FP64 oracle.
 """
 import numpy as np
 import pytest
@@ -54,6 +56,9 @@ def test_combined_layout(batch):
     assert comb.stats()["n_tasks"] == sum(h.stats()["n_tasks"] for h in hops)
 
 
+BAR = {PREC_FP64: 1e-12, PREC_SPLIT2: 2e-6}
+
+
 @pytest.mark.parametrize("prec", [PREC_FP64, PREC_SPLIT2])
 def test_combined_equals_parts(batch, prec):
     probs, hops, comb = batch
@@ -61,7 +66,7 @@ def test_combined_equals_parts(batch, prec):
     ycomb = _run(comb, np.concatenate(xs), prec)
     for k, h in enumerate(hops):
         a, b = comb.part_coeff[k], comb.part_coeff[k + 1]
-        assert rel_err(ycomb[a:b], _run(h, xs[k], prec)) < 1e-12, k
+        assert rel_err(ycomb[a:b], _run(h, xs[k], prec)) < BAR[prec], k
 
 
 def test_combined_part_matches_oracle(batch):
@@ -81,4 +86,4 @@ def test_autotune_keeps_results(batch):
     tq, items, order, ms = comb.autotune(PREC_SPLIT2, reps=2)
     print(f"[autotune] tile width {tq} items {items} order {order}: {ms:.3f} ms")
     assert tq in (2, 4, 8) and items in (8192, 32768, 65536) and order in (0, 2) and ms > 0
-    assert rel_err(_run(comb, x, PREC_SPLIT2), before) < 1e-12
+    assert rel_err(_run(comb, x, PREC_SPLIT2), before) < BAR[PREC_SPLIT2]

@@ -73,7 +73,7 @@ def test_split_matches_oracle(case):
     x = random_vector(hop.n_coeff, 12)
     y = gpu_hpsi(hop, x, PREC_SPLIT2)
     err = rel_err(y, oh.apply(x))
-    print(f"[{name}] split rel err {err:.2e}")
+    print(f"[{name}] split rel err {err:.2e}", flush=True)
     assert err < SPLIT_TOL, name
 
 
