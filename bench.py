@@ -141,11 +141,13 @@ def main():
     mlp_ms = mlp_apply_ms(hop, n, stream)
     log(f"[bench] learned preconditioner application: {mlp_ms:.3f} ms")
 
-    # --- roofline of the dominant kernel (split sector-GEMM kernel)
+    # --- roofline of the dominant kernel: the split H.psi launch sequence (k_pack_xt, the LDS-staged
+    #     k_hpsi_lds classes, the task-mode k_hpsi_small classes and the two k_reduce_lds launches)
     achieved = st["flops"] / tsp / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["bf16"], 5), "traffic": None,
-                "kernel": "k_hpsi_split", "mfma_products_per_flop": 3,
+                "kernel": "split H.psi sequence (k_hpsi_lds + k_hpsi_small + k_reduce_lds)",
+                "mfma_products_per_flop": 3,
                 "fp64_kernel": {"achieved": round(st["flops"] / t64 / 1e12, 3), "peak": PEAK["fp64"],
                                 "frac": round(st["flops"] / t64 / 1e12 / PEAK["fp64"], 4)},
                 "algorithmic_bytes": st["bytes"],

@@ -149,6 +149,16 @@ dmrg_status dmrg_hop_stats(const dmrg_hop* hop, double* flops, double* bytes, in
 dmrg_status dmrg_hpsi(dmrg_hop* hop, const double* x, double* y, int32_t nvec, int32_t precision,
                       void* stream);
 
+/* Same result as dmrg_hpsi, through a hipGraph of the whole launch sequence: the first call for a
+ * given (x, y, nvec, precision) captures the sequence (on a private stream of default priority)
+ * and instantiates it, then launches it on `stream`; later calls with the same
+ * arguments replay it on `stream` with one launch. The handle keeps at most one graph per argument
+ * tuple until it is freed or its launch plan is rebuilt (dmrg_hop_autotune). Buffers x and y must
+ * stay allocated while their graph may be replayed. Callers for whom launch overhead matters (many
+ * small H.psi, the Davidson loop with use_graph = 1) use this form. */
+dmrg_status dmrg_hpsi_graph(dmrg_hop* hop, const double* x, double* y, int32_t nvec, int32_t precision,
+                            void* stream);
+
 /* diag(H) (FP64) into a device buffer of n_coeff doubles. */
 dmrg_status dmrg_hop_diagonal(dmrg_hop* hop, double* d, void* stream);
 
@@ -165,7 +175,7 @@ typedef struct {
     int32_t precision;       /* DMRG_PREC_* for the matvec */
     int32_t fp64_polish;     /* see above */
     double  split_tol;       /* residual at which split precision hands over to FP64 (e.g. 1e-5) */
-    int32_t use_graph;       /* reserved, must be 0 */
+    int32_t use_graph;       /* 1: matvecs through dmrg_hpsi_graph (one graph per basis slot), 0: dmrg_hpsi */
     int32_t precond;         /* DMRG_PRECOND_DIAG or DMRG_PRECOND_MLP */
     const struct dmrg_mlp* mlp;   /* network for DMRG_PRECOND_MLP (same device as the handle) */
 } dmrg_dav_opts;
@@ -202,10 +212,12 @@ dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmr
  * n_coeff). A handle from dmrg_build_blocks has one part. */
 dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first_coeff);
 
-/* Autotuner of the H.psi launch plan: times candidate settings of the widest output tile
- * (2, 4, 8 MFMA tiles of 16 columns), the number of work items (8k, 32k, 64k) and the launch order
- * (heaviest first / cache-aware) on the device for `precision`, `reps` timed calls each, and keeps
- * the fastest. chosen (3 ints: tile width, items, order) and best_ms (milliseconds) may be NULL.
+/* Autotuner of the H.psi launch plan for `precision`: times candidate settings on the device, `reps`
+ * timed calls each, and keeps the fastest. FP64 (one-wavefront kernel): widest output tile (2, 4, 8
+ * MFMA tiles of 16 columns) x work items (8k, 32k, 64k) x launch order (heaviest first / cache-aware).
+ * Split (LDS-staged and task-mode kernels): work items (4k, 8k, 16k, 32k) x launch order (heaviest
+ * first / XCD-aware by left sector); its tile width is reported as 0. chosen (3 ints: tile width,
+ * items, order) and best_ms (milliseconds) may be NULL. Drops the handle's cached graphs.
  * Synchronizes `stream`. */
 dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, void* stream,
                               int32_t* chosen, double* best_ms);

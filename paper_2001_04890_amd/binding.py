@@ -74,6 +74,8 @@ lib.dmrg_hop_stats.argtypes = [C.c_void_p, f64p, f64p, i64p, i64p]
 lib.dmrg_hop_stats.restype = C.c_int32
 lib.dmrg_hpsi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
 lib.dmrg_hpsi.restype = C.c_int32
+lib.dmrg_hpsi_graph.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+lib.dmrg_hpsi_graph.restype = C.c_int32
 lib.dmrg_hop_diagonal.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 lib.dmrg_hop_diagonal.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
@@ -248,16 +250,25 @@ class Hop:
         _check(lib.dmrg_hpsi(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nvec, precision,
                              _stream_ptr(stream)))
 
+    def hpsi_graph(self, x, y, precision=PREC_FP64, stream=None):
+        """Same as hpsi, replaying a cached hipGraph of the launch sequence for these buffers."""
+        nvec = 1 if x.dim() == 1 else x.shape[0]
+        assert x.dtype == y.dtype and x.is_contiguous() and y.is_contiguous()
+        assert x.numel() == nvec * self.n_coeff and y.numel() == x.numel()
+        _check(lib.dmrg_hpsi_graph(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nvec, precision,
+                                   _stream_ptr(stream)))
+
     def diagonal(self, d, stream=None):
         assert d.numel() == self.n_coeff and d.is_contiguous()
         _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
 
     def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
-                 split_tol=1e-5, mlp=None, stream=None):
+                 split_tol=1e-5, mlp=None, stream=None, use_graph=False):
         """In-place Davidson on the device vector psi; returns a dict of the result fields.
-        ``mlp``: a Mlp network to use as the preconditioner (default: the diagonal one)."""
+        ``mlp``: a Mlp network to use as the preconditioner (default: the diagonal one).
+        ``use_graph``: run the matvecs through cached hipGraphs (dmrg_hpsi_graph)."""
         assert psi.numel() == self.n_coeff and psi.is_contiguous()
-        o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp)
+        o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp, use_graph)
         r = DavResult()
         st = _check(lib.dmrg_davidson(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),
                                       _stream_ptr(stream)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
@@ -276,8 +287,8 @@ class Hop:
         return quads.reshape(-1, 4), f, ti.reshape(-1, 4), tc
 
 
-def _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp):
-    return DavOpts(tol, max_iter, max_sub, precision, 1 if fp64_polish else 0, split_tol, 0,
+def _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp, use_graph=False):
+    return DavOpts(tol, max_iter, max_sub, precision, 1 if fp64_polish else 0, split_tol, 1 if use_graph else 0,
                    PRECOND_MLP if mlp is not None else PRECOND_DIAG, mlp._h.value if mlp is not None else None)
 
 

@@ -225,6 +225,10 @@ struct dmrg_hop {
     int tune_lds_items = 16384;                 // target number of LDS work items per H.psi
     int tune_small_mode = 1;                    // 1: single-tile sources run in the task-mode kernel
     int tune_small_nr = 2;                      // task mode: most row tiles per wavefront (1 or 2)
+    // hipGraphs of the H.psi launch sequence, one per (x, y, nvec, precision); dropped when a plan is rebuilt
+    struct GraphEntry { const double* x; double* y; int nvec, prec; hipGraph_t graph; hipGraphExec_t exec; };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;           // capture stream (default priority)
     int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
@@ -1098,7 +1102,16 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
 
 // Every launch plan of the handle: FP64 (all targets) and, with split operators, the LDS-staged
 // plan plus the one-wave split plan for the targets it does not cover.
+void drop_graphs(dmrg_hop& H) {
+    for (auto& g : H.graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    H.graphs.clear();
+}
+
 void build_plan(dmrg_hop& H, hipStream_t s) {
+    drop_graphs(H);
     for (void* p : H.plan_allocations) (void)hipFree(p);
     H.plan_allocations.clear();
     build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
@@ -1373,6 +1386,8 @@ extern "C" void dmrg_hop_free(dmrg_hop* H) {
     if (!H) return;
     if (H->device >= 0) {
         (void)hipSetDevice(H->device);
+        drop_graphs(*H);
+        if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
         for (void* p : H->allocations) (void)hipFree(p);
         for (void* p : H->plan_allocations) (void)hipFree(p);
     }
@@ -1430,33 +1445,84 @@ extern "C" dmrg_status dmrg_hop_export_tasks(const dmrg_hop* H, int64_t* n_tasks
     return DMRG_OK;
 }
 
+namespace {
+
+void check_hpsi_args(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision) {
+    if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
+    if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+    if (!x || !y || nvec < 1) throw Error(DMRG_ERR_ARG, "bad x/y/nvec");
+    int64_t n = H->n_coeff * nvec;
+    if (!(x + n <= y || y + n <= x)) throw Error(DMRG_ERR_ALIAS, "x and y overlap");
+    if (precision != DMRG_PREC_FP64 && precision != DMRG_PREC_SPLIT2) throw Error(DMRG_ERR_ARG, "unknown precision");
+    if (precision == DMRG_PREC_SPLIT2 && !H->has_split)
+        throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+}
+
+// The launch sequence of one H.psi (no host synchronization, so it can be captured).
+void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s) {
+    const int step = dmrg::kPartialVecs;   // packed-input and partial buffers hold this many vectors
+    for (int v0 = 0; v0 < nvec; v0 += step) {
+        const int nv = std::min(step, nvec - v0);
+        const double* xv = x + (int64_t)v0 * H->n_coeff;
+        double* yv = y + (int64_t)v0 * H->n_coeff;
+        if (precision == DMRG_PREC_FP64) {
+            HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
+        } else {
+            HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
+            if (H->n_fallback_targets > 0)
+                HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
+        }
+    }
+}
+
+// Replay (capturing on first use) the hipGraph of the launch sequence for (x, y, nvec, precision).
+void launch_hpsi_graph(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s) {
+    for (const auto& g : H->graphs)
+        if (g.x == x && g.y == y && g.nvec == nvec && g.prec == precision) {
+            HIPCHK(hipGraphLaunch(g.exec, s));
+            return;
+        }
+    // capture only records the launches (nothing runs on the capture stream); the graph is then
+    // launched on s, after the work already queued there
+    if (!H->cap_stream) HIPCHK(hipStreamCreateWithFlags(&H->cap_stream, hipStreamNonBlocking));
+    dmrg_hop::GraphEntry g{x, y, nvec, precision, nullptr, nullptr};
+    HIPCHK(hipStreamBeginCapture(H->cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+        enqueue_hpsi(H, x, y, nvec, precision, H->cap_stream);
+    } catch (...) {
+        hipGraph_t junk = nullptr;
+        (void)hipStreamEndCapture(H->cap_stream, &junk);
+        if (junk) (void)hipGraphDestroy(junk);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(H->cap_stream, &g.graph));
+    HIPCHK(hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0));
+    H->graphs.push_back(g);
+    HIPCHK(hipGraphLaunch(g.exec, s));
+}
+
+}  // namespace
+
 extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision,
                                  void* stream) {
     g_err.clear();
     try {
-        if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
-        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
-        if (!x || !y || nvec < 1) throw Error(DMRG_ERR_ARG, "bad x/y/nvec");
-        int64_t n = H->n_coeff * nvec;
-        if (!(x + n <= y || y + n <= x)) throw Error(DMRG_ERR_ALIAS, "x and y overlap");
+        check_hpsi_args(H, x, y, nvec, precision);
         HIPCHK(hipSetDevice(H->device));
-        hipStream_t s = (hipStream_t)stream;
-        if (precision != DMRG_PREC_FP64 && precision != DMRG_PREC_SPLIT2) throw Error(DMRG_ERR_ARG, "unknown precision");
-        if (precision == DMRG_PREC_SPLIT2 && !H->has_split)
-            throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
-        const int step = dmrg::kPartialVecs;   // packed-input and partial buffers hold this many vectors
-        for (int v0 = 0; v0 < nvec; v0 += step) {
-            const int nv = std::min(step, nvec - v0);
-            const double* xv = x + (int64_t)v0 * H->n_coeff;
-            double* yv = y + (int64_t)v0 * H->n_coeff;
-            if (precision == DMRG_PREC_FP64) {
-                HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
-            } else {
-                HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
-                if (H->n_fallback_targets > 0)
-                    HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
-            }
-        }
+        enqueue_hpsi(H, x, y, nvec, precision, (hipStream_t)stream);
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+extern "C" dmrg_status dmrg_hpsi_graph(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision,
+                                       void* stream) {
+    g_err.clear();
+    try {
+        check_hpsi_args(H, x, y, nvec, precision);
+        HIPCHK(hipSetDevice(H->device));
+        launch_hpsi_graph(H, x, y, nvec, precision, (hipStream_t)stream);
         return DMRG_OK;
     } catch (const Error& e) {
         return fail(e);
@@ -1587,17 +1653,20 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
         HIPCHK(hipMemsetAsync(x, 0, H->n_coeff * sizeof(double), s));
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        const int tq_c[] = {2, 4, 8};
-        const int items_c[] = {8192, 32768, 65536};
-        const int order_c[] = {0, 2};
+        // FP64: widest output tile, work items and launch order of the one-wave kernel. Split: work
+        // items and launch order of the LDS-staged plan (first number reported as 0).
+        const bool split = precision == DMRG_PREC_SPLIT2;
+        std::vector<int> tq_c = split ? std::vector<int>{0} : std::vector<int>{2, 4, 8};
+        std::vector<int> items_c = split ? std::vector<int>{4096, 8192, 16384, 32768} : std::vector<int>{8192, 32768, 65536};
+        std::vector<int> order_c = split ? std::vector<int>{0, 1} : std::vector<int>{0, 2};
         double best = INFINITY;
-        int bt = H->tune_max_tq, bi = H->tune_items, bo = H->tune_order;
+        int bt = split ? 0 : H->tune_max_tq, bi = split ? H->tune_lds_items : H->tune_items;
+        int bo = split ? H->tune_lds_order : H->tune_order;
         for (int tq : tq_c)
             for (int it : items_c)
                 for (int od : order_c) {
-                    H->tune_max_tq = tq;
-                    H->tune_items = it;
-                    H->tune_order = od;
+                    if (split) { H->tune_lds_items = it; H->tune_lds_order = od; }
+                    else { H->tune_max_tq = tq; H->tune_items = it; H->tune_order = od; }
                     build_plan(*H, s);
                     dmrg_status st = dmrg_hpsi(H, x, y, 1, precision, stream);
                     if (st != DMRG_OK) throw Error(st, g_err);
@@ -1613,9 +1682,8 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
                     const double avg = ms / reps;
                     if (avg < best) { best = avg; bt = tq; bi = it; bo = od; }
                 }
-        H->tune_max_tq = bt;
-        H->tune_items = bi;
-        H->tune_order = bo;
+        if (split) { H->tune_lds_items = bi; H->tune_lds_order = bo; }
+        else { H->tune_max_tq = bt; H->tune_items = bi; H->tune_order = bo; }
         build_plan(*H, s);
         if (chosen) { chosen[0] = bt; chosen[1] = bi; chosen[2] = bo; }
         if (best_ms) *best_ms = best;
@@ -1714,7 +1782,7 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
         if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
         if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
-        if (o->use_graph) throw Error(DMRG_ERR_UNSUPPORTED, "use_graph is reserved");
+        if (o->use_graph != 0 && o->use_graph != 1) throw Error(DMRG_ERR_ARG, "use_graph must be 0 or 1");
         if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
         if (o->precond != DMRG_PRECOND_DIAG && o->precond != DMRG_PRECOND_MLP) throw Error(DMRG_ERR_ARG, "unknown preconditioner");
         if (o->precond == DMRG_PRECOND_MLP && !o->mlp) throw Error(DMRG_ERR_ARG, "learned preconditioner requested without a network");
@@ -1747,7 +1815,7 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         int matvecs = 0, matvecs_split = 0;
         auto matvec = [&](const double* x, double* y) {
             HIPCHK(hipEventRecord(e0, s));
-            dmrg_status st = dmrg_hpsi(H, x, y, 1, prec, s);
+            dmrg_status st = o->use_graph ? dmrg_hpsi_graph(H, x, y, 1, prec, s) : dmrg_hpsi(H, x, y, 1, prec, s);
             if (st != DMRG_OK) throw Error(st, g_err);
             HIPCHK(hipEventRecord(e1, s));
             HIPCHK(hipEventSynchronize(e1));
