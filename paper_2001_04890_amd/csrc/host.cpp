@@ -231,6 +231,7 @@ struct dmrg_hop {
     hipStream_t cap_stream = nullptr;           // capture stream (default priority)
     int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
+    int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t n_alpha = 0;
@@ -940,15 +941,22 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
             if (L.pa32 == 1 && L.pd32 == 1 && H.tune_small_mode) small.push_back(L);
             else { big.push_back(L); big_s = std::max({big_s, pa, pd}); }
         }
+        (void)big_s;
         if (!big.empty()) {
-            const int S = std::max({big_s, 16 * nrt <= 64 ? 32 : 96, dmrg::ld_of(H.blk_md[j])});
-            const int Sc = S <= 32 ? 32 : S <= 64 ? 64 : 96;
+            // tasks that fit 64-wide stages (source and target columns <= 64) -> S = 64 run, rest -> S = 96
             const int tp = nrt > dmrg::kLdsWaves ? 2 : 1;
-            Run R{(int)j, 0, Sc == 32 ? 0 : Sc == 64 ? 1 : (tp == 1 ? 2 : 3), 0, 0, nrt, tq, (int32_t)lt.size(), 0};
-            int64_t px = -1;
-            for (const auto& L : big) { lt.push_back(L); total += row_cost(L, tp, tq, L.x_off != px); px = L.x_off; }
-            R.te = (int32_t)lt.size();
-            runs.push_back(R);
+            std::vector<dmrg::LTask> b64, b96;
+            for (const auto& L : big)
+                (L.pa32 <= 2 && L.pd32 <= 2 && tq <= 4 && H.tune_lds_split64 ? b64 : b96).push_back(L);
+            for (int S : {64, 96}) {
+                const auto& v = S == 64 ? b64 : b96;
+                if (v.empty()) continue;
+                Run R{(int)j, S == 64 ? 0 : 1, (S == 64 ? 0 : 2) + (tp - 1), 0, 0, nrt, tq, (int32_t)lt.size(), 0};
+                int64_t px = -1;
+                for (const auto& L : v) { lt.push_back(L); total += row_cost(L, tp, tq, L.x_off != px); px = L.x_off; }
+                R.te = (int32_t)lt.size();
+                runs.push_back(R);
+            }
         }
         if (!small.empty()) {
             const int tb = (int32_t)lt.size();
@@ -961,7 +969,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
             for (int r = 0; r < nrt; r += NR)
                 for (int c = 0; c < tq; c += NQ) {
                     const int nr = std::min(NR, nrt - r), nq = std::min(NQ, tq - c);
-                    runs.push_back({(int)j, 1, cls, 16 * r, 16 * c, nr, nq, tb, te});
+                    runs.push_back({(int)j, 2, cls, 16 * r, 16 * c, nr, nq, tb, te});
                     total += (te - tb) * small_cost(nr, nq);
                 }
         }
@@ -970,17 +978,17 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     const double cmax = std::max(total / std::max(1, H.tune_lds_items), 600.0);
     struct It { dmrg::Item item; double cost; int kind, cls; };
     std::vector<It> its;
-    std::vector<dmrg::Reduce> reds, reds_small;
+    std::vector<dmrg::Reduce> reds_k[dmrg::kReduceKinds];
     int64_t part = 0;
     for (const Run& R : runs) {
-        const int tp = R.kind == 0 && R.nr > dmrg::kLdsWaves ? 2 : 1;
+        const int tp = R.kind < 2 && R.nr > dmrg::kLdsWaves ? 2 : 1;
         std::vector<std::pair<int32_t, int32_t>> chunks;
         std::vector<double> ccost;
         int32_t b = R.tb;
         double c = 0.0;
         int64_t px = -1;
         for (int32_t t = R.tb; t < R.te; ++t) {
-            const double tc = R.kind == 0 ? row_cost(lt[t], tp, R.tq, lt[t].x_off != px || t == b) : small_cost(R.nr, R.tq);
+            const double tc = R.kind < 2 ? row_cost(lt[t], tp, R.tq, lt[t].x_off != px || t == b) : small_cost(R.nr, R.tq);
             px = lt[t].x_off;
             if (c + tc > cmax && t > b) { chunks.push_back({b, t}); ccost.push_back(c); b = t; c = 0.0; }
             c += tc;
@@ -993,8 +1001,8 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
             its.push_back({{H.blk_off[j], -1, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, chunks[0].first, chunks[0].second},
                            ccost[0], R.kind, R.cls});
         } else {
-            (R.kind == 0 ? reds : reds_small)
-                .push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, tm, tn, (int32_t)chunks.size(), 0});
+            reds_k[R.kind].push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, tm, tn,
+                                      (int32_t)chunks.size(), 0});
             for (size_t q = 0; q < chunks.size(); ++q) {
                 its.push_back({{H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], R.r0, R.c0, chunks[q].first,
                                 chunks[q].second},
@@ -1004,6 +1012,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
         }
     }
     // launch order: row-mode classes, then task-mode classes; heaviest item first inside a class
+    for (It& x : its) x.kind = x.kind < 2 ? 0 : 1;
     std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) {
         if (a.kind != b.kind) return a.kind < b.kind;
         if (a.cls != b.cls) return a.cls < b.cls;
@@ -1067,8 +1076,15 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     H.n_fallback_targets = 0;
     for (char f : fallback) H.n_fallback_targets += f;
     if (items.empty()) return;
-    const int n_red_row = (int)reds.size();
-    reds.insert(reds.end(), reds_small.begin(), reds_small.end());
+    std::vector<dmrg::Reduce> reds;
+    H.lplan.red_begin[0] = 0;
+    for (int kk = 0; kk < dmrg::kReduceKinds; ++kk) {
+        int mx = 1;
+        for (const auto& r : reds_k[kk]) mx = std::max(mx, r.tm * r.tn);
+        H.lplan.red_chunks[kk] = (mx + 255) / 256;
+        reds.insert(reds.end(), reds_k[kk].begin(), reds_k[kk].end());
+        H.lplan.red_begin[kk + 1] = (int)reds.size();
+    }
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::LTask* d_lt = plan_alloc<dmrg::LTask>(H, lt.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -1080,8 +1096,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     H.lplan.items = d_items;
     H.lplan.tasks = d_lt;
     H.lplan.reduces = d_red;
-    H.lplan.n_reduces = (int)reds.size();
-    H.lplan.n_reduces_row = n_red_row;
+
     H.lplan.partial_size = part;
     H.lplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1) * dmrg::kPartialVecs);
     H.lplan.packs = d_packs;
@@ -1352,6 +1367,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_SMALL_MODE")) H->tune_small_mode = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_SMALL_NR")) H->tune_small_nr = std::max(1, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
+        if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS_TASK_ORDER")) H->tune_lds_task_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_SMALL_NQ")) H->tune_small_nq = std::max(2, std::min(6, std::atoi(e))) / 2 * 2;
         H->has_split = opts && opts->want_split;

@@ -495,21 +495,21 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
     }
 }
 
-// y_tile += sum of its partial tiles, in item order
+// y_tile += sum of its partial tiles, in item order; block (record, 256-element chunk), one element
+// per thread
 __global__ void k_reduce_lds(const Reduce* __restrict__ red, const double* __restrict__ partall,
                              double* __restrict__ yall, int64_t n_coeff, int64_t part_stride) {
     const Reduce R = red[blockIdx.x];
-    const double* __restrict__ part = partall + (int64_t)blockIdx.y * part_stride + R.part_off;
-    double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
     const int n = R.tm * R.tn;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int rr = e / R.tn, cc = e - (e / R.tn) * R.tn;
-        const int row = R.r0 + rr, col = R.c0 + cc;
-        if (row >= R.m_ap || col >= R.m_dp) continue;
-        double s = 0.0;
-        for (int k = 0; k < R.n_parts; ++k) s += part[(int64_t)k * n + e];
-        y[R.y_off + (int64_t)row * R.m_dp + col] += s;
-    }
+    const int e = blockIdx.z * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const int rr = e / R.tn, cc = e - (e / R.tn) * R.tn;
+    const int row = R.r0 + rr, col = R.c0 + cc;
+    if (row >= R.m_ap || col >= R.m_dp) return;
+    const double* __restrict__ part = partall + (int64_t)blockIdx.y * part_stride + R.part_off;
+    double s = 0.0;
+    for (int k = 0; k < R.n_parts; ++k) s += part[(int64_t)k * n + e];
+    yall[(int64_t)blockIdx.y * n_coeff + R.y_off + (int64_t)row * R.m_dp + col] += s;
 }
 
 __global__ void k_zero_lds(double* __restrict__ y, int64_t n) {
@@ -532,9 +532,9 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         if (n <= 0) continue;
         const dim3 grid(n, nvec), block(kLdsWaves * 64);
         switch (c) {
-            case 0: hipLaunchKernelGGL((k_hpsi_lds<32, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
+            case 0: hipLaunchKernelGGL((k_hpsi_lds<64, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
                                        P.partial, n_coeff, P.xt_size, ss); break;
-            case 1: hipLaunchKernelGGL((k_hpsi_lds<64, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
+            case 1: hipLaunchKernelGGL((k_hpsi_lds<64, 2>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
                                        P.partial, n_coeff, P.xt_size, ss); break;
             case 2: hipLaunchKernelGGL((k_hpsi_lds<96, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
                                        P.partial, n_coeff, P.xt_size, ss); break;
@@ -555,13 +555,13 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         }
 #undef DMRG_SMALL
     }
-    // one launch per kernel kind: the records of one launch touch disjoint parts of y
-    if (P.n_reduces_row > 0)
-        hipLaunchKernelGGL(k_reduce_lds, dim3(P.n_reduces_row, nvec), dim3(256), 0, s, P.reduces, P.partial, y, n_coeff,
-                           P.partial_size);
-    if (P.n_reduces > P.n_reduces_row)
-        hipLaunchKernelGGL(k_reduce_lds, dim3(P.n_reduces - P.n_reduces_row, nvec), dim3(256), 0, s,
-                           P.reduces + P.n_reduces_row, P.partial, y, n_coeff, P.partial_size);
+    // one launch per record kind: the records of one launch touch disjoint parts of y
+    for (int k = 0; k < kReduceKinds; ++k) {
+        const int nr = P.red_begin[k + 1] - P.red_begin[k];
+        if (nr > 0)
+            hipLaunchKernelGGL(k_reduce_lds, dim3(nr, nvec, P.red_chunks[k]), dim3(256), 0, s, P.reduces + P.red_begin[k],
+                               P.partial, y, n_coeff, P.partial_size);
+    }
     return hipGetLastError();
 }
 

@@ -146,16 +146,20 @@ struct HpsiPlan {
 // Tasks whose source is a single 32 x 32 tile run in the task-mode kernel (one wavefront per target
 // block of NR row tiles and at most NQ column tiles), classes (NR, NQ) = (1,2) (2,2) (1,4), launched
 // after the row-mode classes; items[small_begin[c] .. small_begin[c+1]).
+// Row-mode classes (S, TP) = (64,1) (64,2) (96,1) (96,2): a target's tasks whose source and target
+// fit 64-wide stages run in the S = 64 classes (64 KB of LDS, several workgroups per CU), the other
+// big-source tasks in the S = 96 classes.
 constexpr int kLdsWaves = 4;
-constexpr int kLdsClasses = 4;          // (32,1) (64,1) (96,1) (96,2)
+constexpr int kLdsClasses = 4;
 constexpr int kSmallClasses = 3;
+constexpr int kReduceKinds = 3;         // partial tiles of S = 64 runs, S = 96 runs, task-mode runs
 struct LdsPlan {
     const Item* items = nullptr;        // device
     const LTask* tasks = nullptr;       // device
-    const Reduce* reduces = nullptr;    // device: row-mode records first, then task-mode records
-    int n_reduces = 0;                  // all records
-    int n_reduces_row = 0;              // records of row-mode runs (reduced in a launch of their own:
-                                        // a target may have records of both kinds)
+    const Reduce* reduces = nullptr;    // device, grouped by kind; one reduction launch per kind
+                                        // (records of one kind cover disjoint parts of y)
+    int red_begin[kReduceKinds + 1] = {0, 0, 0, 0};
+    int red_chunks[kReduceKinds] = {1, 1, 1};   // 256-element chunks of the largest tile per kind
     int cls_begin[kLdsClasses + 1] = {0, 0, 0, 0, 0};   // item ranges per class
     int small_begin[kSmallClasses + 1] = {0, 0, 0, 0};
     double* partial = nullptr;          // device, partial_size * kPartialVecs doubles
