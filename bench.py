@@ -41,8 +41,11 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
-    ap.add_argument("--workload", choices=["precision", "batch"], default="precision",
-                    help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems")
+    ap.add_argument("--workload", choices=["precision", "batch", "large"], default="precision",
+                    help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems; "
+                         "large: L=76 (57,56) M=6000, one GPU's share of the operator pairs")
+    ap.add_argument("--pairs", type=int, default=100,
+                    help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
     ap.add_argument("--profile-kernels", action="store_true",
                     help="profiling run: 3 H.psi calls per precision and a plain device copy of 1 GiB "
@@ -61,6 +64,8 @@ def main():
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "large":
+        return bench_large(args)
     dev = torch.device("cuda:0")
     L, M = args.L, args.M
     na = nb = L // 2
@@ -240,6 +245,64 @@ def bench_batch(args):
                                    f"M~U{{64..768}}, synthetic block operators sigma=1.5",
                        "n_coeff": comb.n_coeff, "flops_per_matvec": flops, "autotune": tune},
             "split": out["split"], "fp64": out["fp64"]}
+    print(json.dumps(line), flush=True)
+
+
+def bench_large(args):
+    """Large shape: L = 76, N = 113 (57, 56), M = 6000 per block at the middle bond, synthetic block
+    operators (sigma 1.5, sectors up to 420 states) restricted to one GPU's share of the operator
+    combinations (block Hamiltonians + the first --pairs B/Q and A/P pairs). Split vs FP64 H.psi."""
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_integrals, random_vector
+    from dmrg_inputs.synthetic import share_ops, synthetic_block
+    L, na, nb, M, sigma, seed = 76, 57, 56, 6000, 1.5, 4
+    site = L // 2 - 1
+    t0 = time.time()
+    h, eri = random_integrals(L, seed)
+    left = synthetic_block("left", L, na, nb, site, M, sigma, seed + 1000, ops=share_ops("left", L, site, args.pairs))
+    right = synthetic_block("right", L, na, nb, site, M, sigma, seed + 2000, ops=share_ops("right", L, site, args.pairs))
+    log(f"[bench] large: blocks generated in {time.time() - t0:.1f}s (max sector {int(left.dim.max())})")
+    stream = torch.cuda.current_stream()
+    t0 = time.time()
+    hop = dm.Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, stream=stream, share=True)
+    t_build = time.time() - t0
+    del left, right
+    st = hop.stats()
+    n = hop.n_coeff
+    log(f"[bench] large: build {t_build:.1f}s |psi|={n} alphas={st['n_alpha']} tasks={st['n_tasks']} "
+        f"flops/matvec={st['flops']:.3e}")
+    x = torch.as_tensor(random_vector(n, 7), device="cuda:0")
+    ys = {p: torch.empty_like(x) for p in (dm.PREC_FP64, dm.PREC_SPLIT2)}
+    res = {}
+    for name, prec in (("split", dm.PREC_SPLIT2), ("fp64", dm.PREC_FP64)):
+        hop.hpsi(x, ys[prec], prec, stream=stream)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.kernel_reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            hop.hpsi(x, ys[prec], prec, stream=stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        ms = float(np.mean(ts))
+        res[name] = {"ms": round(ms, 3), "tflops": round(st["flops"] / ms / 1e9, 3)}
+        log(f"[bench] large {name}: {res[name]}")
+    y64, ysp = ys[dm.PREC_FP64], ys[dm.PREC_SPLIT2]
+    rel = float(torch.linalg.norm(ysp - y64) / torch.linalg.norm(y64))
+    line = {"metric": "H·ψ TFLOP/s, split-FP32 vs FP64 (large shape, one GPU's share)",
+            "value": res["split"]["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": args.kernel_reps,
+            "warmup": 1, "ms_per_step": res["split"]["ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "bf16", "accumulate": "fp32", "data": "synthetic",
+            "config": {"workload": f"two-site H.psi, L={L} N={na + nb} ({na},{nb}) M={M} middle bond, synthetic "
+                                   f"block operators sigma={sigma}, share: H + {args.pairs} B/Q + {args.pairs} A/P pairs",
+                       "n_coeff": n, "n_alpha": st["n_alpha"], "n_tasks": st["n_tasks"], "flops_per_matvec": st["flops"],
+                       "operator_bytes_fp64": st["bytes"]},
+            "split": res["split"], "fp64": res["fp64"], "rel_matvec_err": rel, "build_seconds": round(t_build, 1),
+            "roofline": {"bound": "mfma", "achieved": res["split"]["tflops"], "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                         "frac": round(res["split"]["tflops"] / PEAK["bf16"], 5), "traffic": None,
+                         "fp64_frac": round(res["fp64"]["tflops"] / PEAK["fp64"], 4)}}
     print(json.dumps(line), flush=True)
 
 

@@ -31,7 +31,7 @@ def sector_dims(k, n_alpha, n_beta, L, M, sigma):
         for nb in range(k + 1):
             qn.append((na, nb))
             w.append(np.exp(-((na - ca) ** 2 + (nb - cb) ** 2) / (2.0 * sigma ** 2)))
-            cap.append(comb(k, na) * comb(k, nb))
+            cap.append(min(comb(k, na) * comb(k, nb), M))   # a sector never exceeds M states
     w = np.array(w)
     cap = np.array(cap, dtype=np.int64)
     total = min(M, int(cap.sum()))
@@ -123,6 +123,18 @@ def synthetic_block(side, L, n_alpha, n_beta, site, M, sigma, seed, g=0.2, h_spr
                 blocks[(so, si)] = m
         out.append(Op(kind, i0, i1, blocks))
     return Block(side=side, orbitals=orbitals, qn=np.array(qn, dtype=np.int32).reshape(-1, 2), dim=dims, ops=out)
+
+
+def share_ops(side, L, site, n_pairs):
+    """Operator list of one device's share of the operator combinations: the block Hamiltonian and
+    the first ``n_pairs`` (X <= Y) normal/complementary pairs B_XY / Q_XY and (P < Q) A_PQ / P_PQ over
+    the left-block spin-orbitals, in index order (the largest families of the sum)."""
+    left = [2 * p + s for p in range(site) for s in (0, 1)]
+    bq = [(X, Y) for i, X in enumerate(left) for Y in left[i:]][:n_pairs]
+    ap = [(P, Q) for i, P in enumerate(left) for Q in left[i + 1:]][:n_pairs]
+    if side == "left":
+        return [("H", -1, -1)] + [("B", X, Y) for X, Y in bq] + [("A", P, Q) for P, Q in ap]
+    return [("H", -1, -1)] + [("Q", X, Y) for X, Y in bq] + [("P", P, Q) for P, Q in ap]
 
 
 def synthetic_problem(L, n_alpha, n_beta, M, sigma, seed, site=None, **kw):

@@ -116,6 +116,12 @@ typedef struct {
     int32_t want_split;      /* 1: also prepare BF16 hi/lo operator copies (DMRG_PREC_SPLIT2) */
     int64_t mem_budget_bytes;/* 0 = no limit; exceeding it returns DMRG_ERR_NOMEM */
     void*   stream;          /* hipStream_t for the build; 0 = legacy default stream */
+    int32_t share;           /* 0: every operator of the sets below must be supplied (missing ->
+                                DMRG_ERR_ARG). 1: one device's share of the sum over operator
+                                combinations (the paper's distribution of the combinations over
+                                processes, Section 2.2.1): combinations that need an operator the
+                                blocks do not supply, directly or inside a pre-summed operator, are
+                                left out, and H.psi is the sum over the remaining ones */
 } dmrg_build_opts;
 
 /* Build the H.psi operator of one bond, once per bond and before Davidson starts (the pre-generated

@@ -47,7 +47,7 @@ class BlockDesc(C.Structure):
 
 class BuildOpts(C.Structure):
     _fields_ = [("device", C.c_int32), ("want_split", C.c_int32), ("mem_budget_bytes", C.c_int64),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("share", C.c_int32)]
 
 
 class DavOpts(C.Structure):
@@ -188,12 +188,12 @@ class Hop:
         return self
 
     def __init__(self, h, eri, left, right, n_alpha, n_beta, site, device=0, want_split=False,
-                 mem_budget_bytes=0, stream=None):
+                 mem_budget_bytes=0, stream=None, share=False):
         h = np.ascontiguousarray(h, dtype=np.float64)
         eri = np.ascontiguousarray(eri, dtype=np.float64)
         prob = Problem(h.shape[0], n_alpha, n_beta, site, _ptr(h, C.c_double), _ptr(eri, C.c_double))
         lm, rm = _BlockMarshal(left), _BlockMarshal(right)
-        opts = BuildOpts(device, 1 if want_split else 0, mem_budget_bytes, _stream_ptr(stream))
+        opts = BuildOpts(device, 1 if want_split else 0, mem_budget_bytes, _stream_ptr(stream), 1 if share else 0)
         handle = C.c_void_p()
         _check(lib.dmrg_build_blocks(C.byref(prob), C.byref(lm.desc), C.byref(rm.desc), C.byref(opts),
                                      C.byref(handle)))

@@ -229,6 +229,7 @@ struct dmrg_hop {
     struct GraphEntry { const double* x; double* y; int nvec, prec; hipGraph_t graph; hipGraphExec_t exec; };
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;           // capture stream (default priority)
+    bool share = false;                         // build only the combinations whose operators are supplied
     int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
@@ -281,6 +282,7 @@ struct Builder {
             k = B.find(kind, i1, i0);
             if (k >= 0) return {k, true};
         }
+        if (H.share) return {-1, false};   // share mode: the combinations using it are left out
         char buf[160];
         std::snprintf(buf, sizeof buf, "%s block lacks operator %s(%d,%d)", s == 0 ? "left" : "right",
                       kind_name(kind), i0, i1);
@@ -288,6 +290,7 @@ struct Builder {
     }
 
     int mat(int s, std::pair<int, bool> o) {
+        if (o.first < 0) return -2;            // absent operator (share mode)
         auto key = std::make_tuple(s, o.first, o.second);
         auto it = H.mat_cache.find(key);
         if (it != H.mat_cache.end()) return it->second;
@@ -303,6 +306,7 @@ struct Builder {
         std::vector<Term> nz;
         for (const Term& t : terms) if (t.c != 0.0) nz.push_back(t);
         if (nz.empty()) return -2;   // identically zero
+        for (const Term& t : nz) if (t.op < 0) return -2;   // a summand is absent (share mode)
         if (nz.size() == 1 && nz[0].c == 1.0) return mat(s, {nz[0].op, nz[0].tr});
         MatDef m;
         m.side = s;
@@ -1353,6 +1357,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         for (double v : H->eri) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite two-electron integral");
         H->left = import_block(left, "left");
         H->right = import_block(right, "right");
+        H->share = opts && opts->share != 0;
         build_layout(*H);
         Builder(*H).generate();
         build_tasks(*H);

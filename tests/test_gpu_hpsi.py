@@ -42,6 +42,8 @@ CASES = {
     "trunc_L10_M50": (exact_problem, (10, 2, 5, 5, 50)),
     "synth_L12_M70": (synth, (12, 70, 0.9, 3)),
     "synth_L14_M160_big_sectors": (synth, (14, 160, 0.7, 4)),
+    # sectors up to 139 states: targets above the 96-wide LDS stages take the one-wavefront kernel
+    "synth_L14_M300_sectors_above_96": (synth, (14, 300, 0.6, 5)),
 }
 
 
