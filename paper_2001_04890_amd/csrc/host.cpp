@@ -216,7 +216,7 @@ struct dmrg_hop {
     std::vector<dmrg::PoolBlock> pool_blocks;   // every block of the FP64 pool (for the tiled split)
     uint16_t* d_tiled = nullptr;                // tiled hi/lo operators + identity blocks
     int64_t tiled_size = 0;
-    int64_t ident_off[3] = {-1, -1, -1};        // tiled identity blocks of size 32, 64, 96
+    std::vector<int64_t> ident_off;             // tiled identity block of size 32 (k + 1), k = 0, 1, ...
     dmrg::LdsPlan lplan{};
     dmrg::HpsiPlan plan_fb{};
     std::vector<dmrg::HpsiLaunch> launches_fb;
@@ -233,6 +233,11 @@ struct dmrg_hop {
     int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
+    int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
+    int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
+    dmrg::BigPlan bplan{};
+    std::vector<dmrg::BigChunk> big_chunks;
+    std::vector<std::pair<int32_t, int32_t>> big_t2_range;
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t n_alpha = 0;
@@ -896,7 +901,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     }
     auto ident = [&](int p) -> int64_t {
         int k = p / 32 - 1;
-        if (k < 0 || k > 2 || H.ident_off[k] < 0) throw Error(DMRG_ERR_ARG, "internal: no tiled identity block");
+        if (k < 0 || k >= (int)H.ident_off.size()) throw Error(DMRG_ERR_ARG, "internal: no tiled identity block");
         return H.ident_off[k];
     };
     // one run of tasks of one kernel kind for one target row block
@@ -1079,7 +1084,6 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     for (int c = 0; c < dmrg::kSmallClasses; ++c) H.lplan.small_begin[c + 1] = H.lplan.small_begin[c] + cnt_small[c];
     H.n_fallback_targets = 0;
     for (char f : fallback) H.n_fallback_targets += f;
-    if (items.empty()) return;
     std::vector<dmrg::Reduce> reds;
     H.lplan.red_begin[0] = 0;
     for (int kk = 0; kk < dmrg::kReduceKinds; ++kk) {
@@ -1093,8 +1097,9 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     dmrg::LTask* d_lt = plan_alloc<dmrg::LTask>(H, lt.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
     dmrg::PackBlock* d_packs = plan_alloc<dmrg::PackBlock>(H, packs.size());
-    HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(d_lt, lt.data(), lt.size() * sizeof(lt[0]), hipMemcpyHostToDevice, s));
+    if (!items.empty())
+        HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
+    if (!lt.empty()) HIPCHK(hipMemcpyAsync(d_lt, lt.data(), lt.size() * sizeof(lt[0]), hipMemcpyHostToDevice, s));
     if (!reds.empty()) HIPCHK(hipMemcpyAsync(d_red, reds.data(), reds.size() * sizeof(reds[0]), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_packs, packs.data(), packs.size() * sizeof(packs[0]), hipMemcpyHostToDevice, s));
     H.lplan.items = d_items;
@@ -1116,6 +1121,153 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
             std::fprintf(stderr, " reduces %zu partial %.1f MB fallback %d\n", reds.size(), part * 8e-6,
                          H.n_fallback_targets);
         }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+// Launch plan of the large-block split path (hpsi_big.hip) for the targets flagged in `big`: targets
+// are grouped into chunks whose T buffers (one per task: target rows x source columns, tiled hi/lo)
+// stay below kBigTBudget elements; per chunk, pass 1 has one workgroup per (task, 8 row tiles,
+// 4 column chunks) and pass 2 one item per (target, 8 row tiles, 8 column tiles, task range), the
+// task lists cut into items of bounded cost whose partial tiles a reduction adds in order.
+void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
+    constexpr int64_t kBigTBudget = 96ll << 20;   // u16 elements of T per chunk (192 MB)
+    H.bplan = dmrg::BigPlan{};
+    H.big_chunks.clear();
+    const size_t nb = H.blk.size();
+    std::vector<int64_t> pk_off(nb);
+    {
+        int64_t ps = 0;
+        for (size_t i = 0; i < nb; ++i) { pk_off[i] = ps; ps += (int64_t)dmrg::ld_of(H.blk_ma[i]) * dmrg::ld_of(H.blk_md[i]); }
+    }
+    auto ident = [&](int p) -> int64_t {
+        const int k = p / 32 - 1;
+        if (k < 0 || k >= (int)H.ident_off.size()) return -1;
+        return H.ident_off[k];
+    };
+    std::vector<dmrg::BigT1> t1;
+    std::vector<dmrg::BigT2> t2;
+    std::vector<dmrg::Item> items;
+    std::vector<dmrg::Reduce> reds;
+    int64_t part_max = 0, tbuf_max = 0;
+    int red_max = 1;
+    // per target: its task range in H.tasks
+    std::vector<std::pair<size_t, size_t>> trange(nb, {0, 0});
+    for (size_t k = 0; k < H.tasks.size();) {
+        size_t e = k;
+        while (e < H.tasks.size() && H.tasks[e].j == H.tasks[k].j) ++e;
+        trange[H.tasks[k].j] = {k, e};
+        k = e;
+    }
+    dmrg::BigChunk cur{0, 0, 0, 0, 0, 0};
+    int64_t tsize = 0, part = 0;
+    std::vector<int> chunk_targets;
+    auto close_chunk = [&]() {
+        if (chunk_targets.empty()) return;
+        // pass-2 items of the chunk's targets
+        double total = 0.0;
+        for (int j : chunk_targets)
+            for (size_t k = trange[j].first; k < trange[j].second; ++k)
+                total += dmrg::ld_of(H.blk_md[H.tasks[k].i]) / 32;
+        (void)total;
+        cur.t1_end = (int)t1.size();
+        cur.item_begin = (int)items.size();
+        cur.red_begin = (int)reds.size();
+        part = 0;
+        for (int j : chunk_targets) {
+            const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, nq = dmrg::rows_of(H.blk_md[j]) / 16;
+            const int32_t tb = t2.size() ? 0 : 0;
+            (void)tb;
+            for (int rb = 0; rb < nrt; rb += 8)
+                for (int qb = 0; qb < nq; qb += 8) {
+                    const int tm = 16 * std::min(8, nrt - rb), tn = 16 * std::min(8, nq - qb);
+                    // task list of this target in t2: [first, last) stored when the target was added
+                    const int32_t b0 = H.big_t2_range[j].first, b1 = H.big_t2_range[j].second;
+                    std::vector<std::pair<int32_t, int32_t>> cuts;
+                    int32_t b = b0;
+                    int c = 0;
+                    for (int32_t t = b0; t < b1; ++t) {
+                        if (c >= H.tune_big_stages && t > b) { cuts.push_back({b, t}); b = t; c = 0; }
+                        c += t2[t].pd32;
+                    }
+                    cuts.push_back({b, b1});
+                    if (cuts.size() == 1) {
+                        items.push_back({H.blk_off[j], -1, H.blk_ma[j], H.blk_md[j], 16 * rb, 16 * qb, cuts[0].first,
+                                         cuts[0].second});
+                    } else {
+                        reds.push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], 16 * rb, 16 * qb, 128, tn,
+                                        (int32_t)cuts.size(), 0});
+                        red_max = std::max(red_max, 128 * tn);
+                        for (auto& cp : cuts) {
+                            items.push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], 16 * rb, 16 * qb, cp.first,
+                                             cp.second});
+                            part += (int64_t)128 * tn;
+                        }
+                    }
+                    (void)tm;
+                }
+        }
+        cur.item_end = (int)items.size();
+        cur.red_end = (int)reds.size();
+        part_max = std::max(part_max, part);
+        tbuf_max = std::max(tbuf_max, tsize);
+        H.big_chunks.push_back(cur);
+        cur = dmrg::BigChunk{(int)t1.size(), (int)t1.size(), 0, 0, 0, 0};
+        chunk_targets.clear();
+        tsize = 0;
+    };
+    H.big_t2_range.assign(nb, {0, 0});
+    for (size_t j = 0; j < nb; ++j) {
+        if (!big[j]) continue;
+        const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16;
+        int64_t need = 0;
+        for (size_t k = trange[j].first; k < trange[j].second; ++k)
+            need += (int64_t)nrt * (dmrg::ld_of(H.blk_md[H.tasks[k].i]) / 32) * dmrg::kTileU16;
+        if (tsize > 0 && tsize + need > kBigTBudget) close_chunk();
+        const int32_t b0 = (int32_t)t2.size();
+        for (size_t k = trange[j].first; k < trange[j].second; ++k) {
+            const auto& ht = H.tasks[k];
+            const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
+            const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
+            const int64_t a_off = ht.lm >= 0 ? 2 * H.mats[ht.lm].pool_of_in[a] : ident(pa);
+            const int64_t b_off = ht.rm >= 0 ? 2 * H.mats[ht.rm].pool_of_in[d] : ident(pd);
+            if (a_off < 0 || b_off < 0)
+                throw Error(DMRG_ERR_UNSUPPORTED, "identity factor wider than 96 in the large-block path");
+            const int64_t t_off = tsize;
+            tsize += (int64_t)nrt * (pd / 32) * dmrg::kTileU16;
+            for (int rb = 0; rb < nrt; rb += 8)
+                for (int jb = 0; jb < pd / 32; jb += 4)
+                    t1.push_back({2 * pk_off[ht.i], a_off, t_off, (float)ht.f, (int16_t)(pa / 32), (int16_t)(pd / 32),
+                                  (int16_t)nrt, (int16_t)rb, (int16_t)jb, 0});
+            t2.push_back({t_off, b_off, pd / 32, 0});
+        }
+        H.big_t2_range[j] = {b0, (int32_t)t2.size()};
+        chunk_targets.push_back((int)j);
+    }
+    close_chunk();
+    if (t1.empty()) return;
+    dmrg::BigT1* d_t1 = plan_alloc<dmrg::BigT1>(H, t1.size());
+    dmrg::BigT2* d_t2 = plan_alloc<dmrg::BigT2>(H, t2.size());
+    dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
+    dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
+    HIPCHK(hipMemcpyAsync(d_t1, t1.data(), t1.size() * sizeof(t1[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_t2, t2.data(), t2.size() * sizeof(t2[0]), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
+    if (!reds.empty()) HIPCHK(hipMemcpyAsync(d_red, reds.data(), reds.size() * sizeof(reds[0]), hipMemcpyHostToDevice, s));
+    H.bplan.t1 = d_t1;
+    H.bplan.t2 = d_t2;
+    H.bplan.items = d_items;
+    H.bplan.reduces = d_red;
+    H.bplan.chunks = H.big_chunks.data();
+    H.bplan.n_chunks = (int)H.big_chunks.size();
+    H.bplan.red_chunks = (red_max + 255) / 256;
+    H.bplan.tbuf = plan_alloc<uint16_t>(H, (size_t)std::max<int64_t>(tbuf_max, 1));
+    H.bplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1));
+    H.bplan.partial_size = part_max;
+    if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
+        if (e[0] == '1')
+            std::fprintf(stderr, "[dmrg big plan] chunks %zu pass-1 groups %zu pass-2 items %zu reduces %zu T %.1f MB "
+                         "partial %.1f MB\n", H.big_chunks.size(), t1.size(), items.size(), reds.size(),
+                         tbuf_max * 2e-6, part_max * 8e-6);
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -1141,9 +1293,15 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     if (!H.has_split) return;
     std::vector<char> fb;
     build_lds_plan(H, s, fb);
+    H.bplan = dmrg::BigPlan{};
     if (H.n_fallback_targets > 0) {
-        if (!H.d_hi) throw Error(DMRG_ERR_ARG, "internal: row-major split operators missing");
-        build_plan_core(H, s, &fb, true, H.plan_fb, H.launches_fb, H.phases_fb);
+        if (H.tune_big) {
+            build_big_plan(H, s, fb);
+            H.n_fallback_targets = 0;
+        } else {
+            if (!H.d_hi) throw Error(DMRG_ERR_ARG, "internal: row-major split operators missing");
+            build_plan_core(H, s, &fb, true, H.plan_fb, H.launches_fb, H.phases_fb);
+        }
     }
 }
 
@@ -1159,11 +1317,16 @@ bool needs_fallback(const dmrg_hop& H) {
 }
 
 // Tiled hi/lo copy of the whole FP64 pool (internal.h) followed by tiled identity blocks of sizes
-// 32, 64 and 96 (hi = 1 on the diagonal, lo = 0), which stand in for identity factors.
+// 32, 64, ... up to the widest padded block (hi = 1 on the diagonal, lo = 0), which stand in for
+// identity factors.
 void make_tiled_split(dmrg_hop& H, hipStream_t s) {
     int64_t n = 2 * H.pool_size;
+    int pmax = 96;
+    for (size_t i = 0; i < H.blk.size(); ++i)
+        pmax = std::max({pmax, dmrg::ld_of(H.blk_ma[i]), dmrg::ld_of(H.blk_md[i])});
     std::vector<uint16_t> id;
-    for (int k = 0; k < 3; ++k) {
+    H.ident_off.assign(pmax / 32, -1);
+    for (int k = 0; k < pmax / 32; ++k) {
         const int p = 32 * (k + 1), r16 = p / 16, k32 = p / 32;
         H.ident_off[k] = n + (int64_t)id.size();
         const size_t base = id.size();
@@ -1270,7 +1433,7 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     //    needs the one-wave kernel
     if (H.has_split) {
         make_tiled_split(H, s);
-        if (needs_fallback(H)) {
+        if (!H.tune_big && needs_fallback(H)) {
             H.d_hi = dev_alloc<uint16_t>(H, pool);
             H.d_lo = dev_alloc<uint16_t>(H, pool);
             HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
@@ -1373,6 +1536,8 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_SMALL_NR")) H->tune_small_nr = std::max(1, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_LDS_TASK_ORDER")) H->tune_lds_task_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_SMALL_NQ")) H->tune_small_nq = std::max(2, std::min(6, std::atoi(e))) / 2 * 2;
         H->has_split = opts && opts->want_split;
@@ -1490,6 +1655,9 @@ void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t
             HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
         } else {
             HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
+            for (int v = 0; v < nv && H->bplan.n_chunks > 0; ++v)
+                HIPCHK(dmrg::launch_hpsi_big(H->bplan, H->d_tiled, H->lplan.xt + (int64_t)v * H->lplan.xt_size,
+                                             yv + (int64_t)v * H->n_coeff, s));
             if (H->n_fallback_targets > 0)
                 HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
         }
@@ -1626,8 +1794,9 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
             cb += h.n_coeff;
         }
         if (C->has_split) {
+            C->tune_big = hops[0]->tune_big;
             make_tiled_split(*C, s);
-            if (needs_fallback(*C)) {
+            if (!C->tune_big && needs_fallback(*C)) {
                 C->d_hi = dev_alloc<uint16_t>(*C, C->pool_size);
                 C->d_lo = dev_alloc<uint16_t>(*C, C->pool_size);
                 HIPCHK(dmrg::launch_split(C->d_pool, C->pool_size, C->d_hi, C->d_lo, s));

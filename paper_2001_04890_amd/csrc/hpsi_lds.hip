@@ -524,7 +524,7 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_zero_lds, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
     }
-    if (P.n_packs == 0 || P.small_begin[kSmallClasses] == 0) return hipGetLastError();
+    if (P.n_packs == 0) return hipGetLastError();
     hipLaunchKernelGGL(k_pack_xt, dim3(P.n_packs, nvec), dim3(256), 0, s, P.packs, x, n_coeff, P.xt_size, P.xt);
     const int64_t ss = P.partial_size;
     for (int c = 0; c < kLdsClasses; ++c) {

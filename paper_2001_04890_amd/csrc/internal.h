@@ -170,6 +170,38 @@ struct LdsPlan {
     uint16_t* xt = nullptr;             // device, xt_size * kPartialVecs
 };
 
+// ---------------------------------------------------------------- large blocks (hpsi_big.hip)
+// Targets whose blocks (or sources) exceed the 96-wide LDS stages take two passes per chunk of
+// targets: pass 1 writes T = f A X of every task into a tiled hi/lo buffer (tile (rt, jc) of the
+// task's T at t_off + (rt * pd32 + jc) * kTileU16, in the A-operand fragment layout of pass 2),
+// pass 2 accumulates Y += sum_tasks T B^T per 128 x 128 output tile.
+struct BigT1 {             // pass-1 workgroup: one task, rows [16 rb, 16 rb + 128), T^T rows [32 jb, 32 jb + 128)
+    int64_t xt, a, t;      // tiled X^T of the source, tiled A, output T (u16 offsets)
+    float f;
+    int16_t pa32, pd32;    // source rows / cols in 32-element k tiles
+    int16_t nrt;           // row tiles of the target block
+    int16_t rb, jb;        // first row tile, first 32-column chunk
+    int16_t pad;
+};
+struct BigT2 {             // pass-2 task: T of the task and its B block
+    int64_t t, b;
+    int32_t pd32;
+    int32_t pad;
+};
+struct BigChunk { int t1_begin, t1_end, item_begin, item_end, red_begin, red_end; };
+struct BigPlan {
+    const BigT1* t1 = nullptr;      // device
+    const BigT2* t2 = nullptr;      // device
+    const Item* items = nullptr;    // device: pass-2 items (r0 = 16 rb, c0 = 16 qb, task range in t2)
+    const Reduce* reduces = nullptr;
+    const BigChunk* chunks = nullptr;   // host
+    int n_chunks = 0;
+    int red_chunks = 1;             // 256-element chunks of the largest partial tile
+    uint16_t* tbuf = nullptr;       // device, largest chunk's T (one vector at a time)
+    double* partial = nullptr;      // device, partial tiles of the largest chunk
+    int64_t partial_size = 0;
+};
+
 // Launchers (kernels.hip). All asynchronous on `s`.
 hipError_t launch_presum(const PresumBlock* blocks, int n_blocks, const PresumTerm* terms,
                          double* pool, hipStream_t s);
@@ -196,6 +228,10 @@ hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).
 hipError_t launch_hpsi_lds(const LdsPlan& plan, const uint16_t* pool_t, const double* x, double* y, int64_t n_coeff,
                            int nvec, bool zero_y, hipStream_t s);
+// Large-block split path (hpsi_big.hip) for one vector: y += the large targets' part of H x;
+// xt = that vector's tiled X^T (packed by launch_hpsi_lds).
+hipError_t launch_hpsi_big(const BigPlan& plan, const uint16_t* pool_t, const uint16_t* xt, double* y,
+                           hipStream_t s);
 // Old-kernel split path over a plan without clearing y first.
 hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
                                  double* y, int64_t n_coeff, int nvec, hipStream_t s);
