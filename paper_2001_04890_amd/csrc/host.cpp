@@ -234,7 +234,7 @@ struct dmrg_hop {
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
-    int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
+    int tune_big_stages = 16;                   // pass-1 and pass-2 item size in 32-wide k steps
     dmrg::BigPlan bplan{};
     std::vector<dmrg::BigChunk> big_chunks;
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
@@ -1160,6 +1160,8 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     }
     dmrg::BigChunk cur{0, 0, 0, 0, 0, 0};
     int64_t tsize = 0, part = 0;
+    std::vector<int32_t> t1_ranges;
+    int32_t g_first = 0;
     std::vector<int> chunk_targets;
     auto close_chunk = [&]() {
         if (chunk_targets.empty()) return;
@@ -1169,7 +1171,19 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
             for (size_t k = trange[j].first; k < trange[j].second; ++k)
                 total += dmrg::ld_of(H.blk_md[H.tasks[k].i]) / 32;
         (void)total;
-        cur.t1_end = (int)t1.size();
+        // pass-1 workgroups: consecutive groups of the chunk with about tune_big_stages k steps each
+        cur.t1_begin = (int)t1_ranges.size();
+        {
+            int c = 0;
+            t1_ranges.push_back(g_first);
+            for (int32_t gidx = g_first; gidx < (int32_t)t1.size(); ++gidx) {
+                if (c >= H.tune_big_stages) { t1_ranges.push_back(gidx); c = 0; }
+                c += t1[gidx].pa32;
+            }
+            cur.t1_end = (int)t1_ranges.size();   // workgroups [t1_begin, t1_end); ranges has one more entry
+            t1_ranges.push_back((int32_t)t1.size());
+        }
+        g_first = (int32_t)t1.size();
         cur.item_begin = (int)items.size();
         cur.red_begin = (int)reds.size();
         part = 0;
@@ -1211,7 +1225,7 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
         part_max = std::max(part_max, part);
         tbuf_max = std::max(tbuf_max, tsize);
         H.big_chunks.push_back(cur);
-        cur = dmrg::BigChunk{(int)t1.size(), (int)t1.size(), 0, 0, 0, 0};
+        cur = dmrg::BigChunk{0, 0, 0, 0, 0, 0};
         chunk_targets.clear();
         tsize = 0;
     };
@@ -1246,6 +1260,9 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     close_chunk();
     if (t1.empty()) return;
     dmrg::BigT1* d_t1 = plan_alloc<dmrg::BigT1>(H, t1.size());
+    int32_t* d_t1r = plan_alloc<int32_t>(H, t1_ranges.size());
+    HIPCHK(hipMemcpyAsync(d_t1r, t1_ranges.data(), t1_ranges.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    H.bplan.t1_ranges = d_t1r;
     dmrg::BigT2* d_t2 = plan_alloc<dmrg::BigT2>(H, t2.size());
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -2078,8 +2095,10 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
                                     prec, theta, rnorm);
             if (!std::isfinite(rnorm) || !std::isfinite(theta)) throw Error(DMRG_ERR_NAN, "non-finite Davidson residual");
             if (prec == DMRG_PREC_SPLIT2 && o->fp64_polish) {
+                // hand over at split_tol, or when the split residual has stopped improving (no new
+                // minimum by 1% for 10 iterations: the matvec rounding floor has been reached)
                 bool hand_over = rnorm <= std::max(o->split_tol, o->tol);
-                if (rnorm < 0.7 * best_split_r) { best_split_r = rnorm; stall = 0; } else if (++stall >= 4) hand_over = true;
+                if (rnorm < 0.99 * best_split_r) { best_split_r = rnorm; stall = 0; } else if (++stall >= 10) hand_over = true;
                 if (hand_over) {
                     // restart in FP64 from the current Ritz vector
                     prec = DMRG_PREC_FP64;

@@ -70,24 +70,32 @@ __device__ __forceinline__ void copy_stage(const uint16_t* __restrict__ p_base, 
 }  // namespace
 
 // ------------------------------------------------------------------ pass 1: T = f A X per task
-__global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, const uint16_t* __restrict__ pool_t,
-                                               const uint16_t* __restrict__ xt, uint16_t* __restrict__ tbuf) {
+// One workgroup runs the groups [ranges[blockIdx.x], ranges[blockIdx.x + 1]) (each: one task's 8 row
+// tiles x 4 column chunks) as one pipeline of k steps; at the end of a group its T tiles are stored.
+__global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, const int32_t* __restrict__ ranges,
+                                               const uint16_t* __restrict__ pool_t, const uint16_t* __restrict__ xt,
+                                               uint16_t* __restrict__ tbuf) {
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kStageU16];
-    const BigT1* wp = work + blockIdx.x;
-    const int64_t x_off = uni64(wp->xt), a_off = uni64(wp->a), t_off = uni64(wp->t);
-    const float f = __builtin_bit_cast(float, uni(__builtin_bit_cast(int, wp->f)));
-    const int pa32 = uni(wp->pa32), pd32 = uni(wp->pd32), nrt = uni(wp->nrt), rb = uni(wp->rb), jb = uni(wp->jb);
+    const int g_begin = uni(ranges[blockIdx.x]), g_end = uni(ranges[blockIdx.x + 1]);
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wj = wave & 1, wr = wave >> 1;   // wave: chunks jb + 2 wj + {0,1}, row tiles rb + 4 wr + {0..3}
-
-    // stage kt: tiles 0..7 = X^T (chunk jb + i/2, half i%2, kt), tiles 8..15 = A (row tile rb + i, kt)
-    auto sources = [&](int kt, int64_t (&src)[kStageTiles]) {
+    struct G { int64_t x, a, t; float f; int pa32, pd32, nrt, rb, jb; };
+    auto load_g = [&](int i) {
+        const BigT1* wp = work + i;
+        G d;
+        d.x = uni64(wp->xt); d.a = uni64(wp->a); d.t = uni64(wp->t);
+        d.f = __builtin_bit_cast(float, uni(__builtin_bit_cast(int, wp->f)));
+        d.pa32 = uni(wp->pa32); d.pd32 = uni(wp->pd32); d.nrt = uni(wp->nrt); d.rb = uni(wp->rb); d.jb = uni(wp->jb);
+        return d;
+    };
+    // stage (group, kt): tiles 0..7 = X^T (chunk jb + i/2, half i%2, kt), tiles 8..15 = A (row tile rb + i, kt)
+    auto sources = [&](const G d, int kt, int64_t (&src)[kStageTiles]) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
-            const int jc = jb + (i >> 1), h2 = i & 1;
-            src[i] = jc < pd32 ? x_off + (int64_t)((jc * 2 + h2) * pa32 + kt) * kTileU16 : -1;
-            const int rt = rb + i;
-            src[8 + i] = rt < nrt ? a_off + (int64_t)(rt * pa32 + kt) * kTileU16 : -1;
+            const int jc = d.jb + (i >> 1), h2 = i & 1;
+            src[i] = jc < d.pd32 ? d.x + (int64_t)((jc * 2 + h2) * d.pa32 + kt) * kTileU16 : -1;
+            const int rt = d.rb + i;
+            src[8 + i] = rt < d.nrt ? d.a + (int64_t)(rt * d.pa32 + kt) * kTileU16 : -1;
         }
     };
     f32x4 acc[2][2][4];
@@ -97,18 +105,52 @@ __global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, c
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int c = 0; c < 4; ++c) acc[a][b][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    auto store = [&](const G d) {
+        int ln = lane;   // opaque copy: keep the store addresses out of the main loop
+        asm volatile("" : "+v"(ln));
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int jc = d.jb + 2 * wj + jj, rt = d.rb + 4 * wr + rr;
+                if (jc < d.pd32 && rt < d.nrt) {
+                    // acc[jj][h2][rr][v] = T'[row 16 rt + li][col 32 jc + 8 g + 4 h2 + v]
+                    u16x8 th, tl;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float v = d.f * acc[jj][u >> 2][rr][u & 3];
+                        const unsigned short hh = bf16_rne(v);
+                        th[u] = hh;
+                        tl[u] = bf16_rne(v - bf16_f32(hh));
+                    }
+                    uint16_t* dst = tbuf + d.t + (int64_t)(rt * d.pd32 + jc) * kTileU16 + ln * 8;
+                    *reinterpret_cast<u16x8*>(dst) = th;
+                    *reinterpret_cast<u16x8*>(dst + 512) = tl;
+                }
+#pragma unroll
+                for (int h2 = 0; h2 < 2; ++h2) acc[jj][h2][rr] = f32x4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+
+    int gi = g_begin, kt = 0;
+    G cur = load_g(gi);
     {
         int64_t src[kStageTiles];
-        sources(0, src);
+        sources(cur, 0, src);
         copy_stage(xt, pool_t, src, lds, wave, lane);
     }
     wait_vm();
     __syncthreads();
-    for (int kt = 0; kt < pa32; ++kt) {
-        const int st = kt & 1;
-        if (kt + 1 < pa32) {
+    int st = 0;
+    for (;;) {
+        int ngi = gi, nkt = kt + 1;
+        if (nkt == cur.pa32) { ngi = gi + 1; nkt = 0; }
+        const bool has_next = ngi < g_end;
+        G nxt = cur;
+        if (has_next) {
+            if (ngi != gi) nxt = load_g(ngi);
             int64_t src[kStageTiles];
-            sources(kt + 1, src);
+            sources(nxt, nkt, src);
             copy_stage(xt, pool_t, src, lds + (st ^ 1) * kStageU16, wave, lane);
         }
         const uint16_t* sp = lds + st * kStageU16 + lane * 8;
@@ -134,28 +176,13 @@ __global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, c
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr)
                     acc[jj][h2][rr] = mma3(ph[jj][h2], pl[jj][h2], qh[rr], ql[rr], acc[jj][h2][rr]);
+        if (ngi != gi) store(cur);        // last k step of the group
         wait_vm();
         __syncthreads();
+        if (!has_next) break;
+        gi = ngi; kt = nkt; cur = nxt;
+        st ^= 1;
     }
-    // acc[jj][h2][rr][v] = T'[row 16 rt + li][col 32 jc + 8 g + 4 h2 + v]: store T tile (rt, jc)
-#pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int jc = jb + 2 * wj + jj, rt = rb + 4 * wr + rr;
-            if (jc >= pd32 || rt >= nrt) continue;
-            u16x8 th, tl;
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const float v = f * acc[jj][u >> 2][rr][u & 3];
-                const unsigned short hh = bf16_rne(v);
-                th[u] = hh;
-                tl[u] = bf16_rne(v - bf16_f32(hh));
-            }
-            uint16_t* dst = tbuf + t_off + (int64_t)(rt * pd32 + jc) * kTileU16 + lane * 8;
-            *reinterpret_cast<u16x8*>(dst) = th;
-            *reinterpret_cast<u16x8*>(dst + 512) = tl;
-        }
 }
 
 // ------------------------------------------------------------------ pass 2: Y += sum T B^T per tile
@@ -168,7 +195,7 @@ __global__ __launch_bounds__(256) void k_big_y(const Item* __restrict__ items, c
     const int64_t y_off = uni64(ip->y_off), part_off = uni64(ip->part_off);
     const int m_ap = uni(ip->m_ap), m_dp = uni(ip->m_dp), r0 = uni(ip->r0), c0 = uni(ip->c0);
     const int t_begin = uni(ip->t_begin), t_end = uni(ip->t_end);
-    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wr = wave >> 1, wq = wave & 1;   // wave: row tiles rb + 4 wr + {0..3}, col tiles qb + 4 wq + {0..3}
     const int rb = r0 >> 4, qb = c0 >> 4;
     const int nrt = (m_ap + 15) >> 4, nq = (m_dp + 15) >> 4;
@@ -191,6 +218,11 @@ __global__ __launch_bounds__(256) void k_big_y(const Item* __restrict__ items, c
         for (int b = 0; b < 4; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     bool first_flush = true;
     auto flush = [&]() {
+        // output addresses are recomputed here from an opaque copy of the lane id: hoisted out of the
+        // main loop they would hold 64 address pairs in registers for the whole kernel
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int fli = ln & 15, fg = ln >> 4;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
@@ -199,7 +231,7 @@ __global__ __launch_bounds__(256) void k_big_y(const Item* __restrict__ items, c
                 if (rt < nrt && q < nq) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * rt + 4 * g + v, col = 16 * q + li;
+                        const int row = 16 * rt + 4 * fg + v, col = 16 * q + fli;
                         if (part_off < 0) {
                             if (row < m_ap && col < m_dp) y[y_off + (int64_t)row * m_dp + col] += (double)acc[rr][qq][v];
                         } else {
@@ -284,8 +316,8 @@ hipError_t launch_hpsi_big(const BigPlan& P, const uint16_t* pool_t, const uint1
     for (int c = 0; c < P.n_chunks; ++c) {
         const BigChunk& C = P.chunks[c];
         if (C.t1_end > C.t1_begin)
-            hipLaunchKernelGGL(k_big_t, dim3(C.t1_end - C.t1_begin), dim3(256), 0, s, P.t1 + C.t1_begin, pool_t, xt,
-                               P.tbuf);
+            hipLaunchKernelGGL(k_big_t, dim3(C.t1_end - C.t1_begin), dim3(256), 0, s, P.t1, P.t1_ranges + C.t1_begin,
+                               pool_t, xt, P.tbuf);
         if (C.item_end > C.item_begin)
             hipLaunchKernelGGL(k_big_y, dim3(C.item_end - C.item_begin), dim3(256), 0, s, P.items + C.item_begin, P.t2,
                                pool_t, P.tbuf, y, P.partial);

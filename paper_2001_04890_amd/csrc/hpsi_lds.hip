@@ -412,6 +412,10 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
         for (int q = 0; q < NQ; ++q) c32[p][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     bool first_flush = true;
     auto flush = [&]() {
+        // addresses from an opaque copy of the lane id, so they are not hoisted into the main loop
+        int ln = lane;
+        asm volatile("" : "+v"(ln));
+        const int fli = ln & 15, fg = ln >> 4;
 #pragma unroll
         for (int p = 0; p < NR; ++p)
 #pragma unroll
@@ -419,7 +423,7 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
                 if (p < nr && q < tq) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * (rt0 + p) + 4 * g + v, col = 16 * (qt0 + q) + li;
+                        const int row = 16 * (rt0 + p) + 4 * fg + v, col = 16 * (qt0 + q) + fli;
                         if (I.part_off < 0) {
                             if (row < I.m_ap && col < I.m_dp)
                                 y[I.y_off + (int64_t)row * I.m_dp + col] += (double)c32[p][q][v];

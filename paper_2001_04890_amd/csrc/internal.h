@@ -188,9 +188,12 @@ struct BigT2 {             // pass-2 task: T of the task and its B block
     int32_t pd32;
     int32_t pad;
 };
+// Chunk c: pass-1 workgroups [t1_begin, t1_end) (workgroup w runs groups t1_ranges[w] ..
+// t1_ranges[w + 1] - 1), pass-2 items [item_begin, item_end), reductions [red_begin, red_end).
 struct BigChunk { int t1_begin, t1_end, item_begin, item_end, red_begin, red_end; };
 struct BigPlan {
     const BigT1* t1 = nullptr;      // device
+    const int32_t* t1_ranges = nullptr;   // device, one entry per pass-1 workgroup plus one
     const BigT2* t2 = nullptr;      // device
     const Item* items = nullptr;    // device: pass-2 items (r0 = 16 rb, c0 = 16 qb, task range in t2)
     const Reduce* reduces = nullptr;
