@@ -234,7 +234,9 @@ struct dmrg_hop {
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
-    int tune_big_stages = 16;                   // pass-1 and pass-2 item size in 32-wide k steps
+    int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
+    int tune_big_stages1 = 16;                  // pass-1 workgroup size in 32-wide k steps
+    int tune_big_tbudget_mb = 1024;             // T buffer of one chunk of large targets (MB)
     dmrg::BigPlan bplan{};
     std::vector<dmrg::BigChunk> big_chunks;
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
@@ -1130,7 +1132,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
 // 4 column chunks) and pass 2 one item per (target, 8 row tiles, 8 column tiles, task range), the
 // task lists cut into items of bounded cost whose partial tiles a reduction adds in order.
 void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
-    constexpr int64_t kBigTBudget = 96ll << 20;   // u16 elements of T per chunk (192 MB)
+    const int64_t kBigTBudget = (int64_t)H.tune_big_tbudget_mb << 19;   // u16 elements of T per chunk
     H.bplan = dmrg::BigPlan{};
     H.big_chunks.clear();
     const size_t nb = H.blk.size();
@@ -1177,7 +1179,7 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
             int c = 0;
             t1_ranges.push_back(g_first);
             for (int32_t gidx = g_first; gidx < (int32_t)t1.size(); ++gidx) {
-                if (c >= H.tune_big_stages) { t1_ranges.push_back(gidx); c = 0; }
+                if (c >= H.tune_big_stages1) { t1_ranges.push_back(gidx); c = 0; }
                 c += t1[gidx].pa32;
             }
             cur.t1_end = (int)t1_ranges.size();   // workgroups [t1_begin, t1_end); ranges has one more entry
@@ -1555,6 +1557,8 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_BIG_TBUDGET_MB")) H->tune_big_tbudget_mb = std::max(16, std::atoi(e));
         if (const char* e = std::getenv("DMRG_LDS_TASK_ORDER")) H->tune_lds_task_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_SMALL_NQ")) H->tune_small_nq = std::max(2, std::min(6, std::atoi(e))) / 2 * 2;
         H->has_split = opts && opts->want_split;
