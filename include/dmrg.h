@@ -171,8 +171,8 @@ dmrg_status dmrg_hop_diagonal(dmrg_hop* hop, double* d, void* stream);
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs (restarting from the
- * current Ritz vector) once the split residual falls below split_tol or has made no new minimum (by
- * 1%) for 10 iterations, and finishes at tol. The correction vector comes from
+ * current Ritz vector) once the split residual falls below split_tol, or is below 30 split_tol and has
+ * made no new minimum (by 1%) for 10 iterations, and finishes at tol. The correction vector comes from
  * the diagonal preconditioner or from a learned network (precond, mlp). */
 typedef struct dmrg_mlp dmrg_mlp;   /* opaque: learned preconditioner (weights, Adam state, datasets) */
 typedef struct {

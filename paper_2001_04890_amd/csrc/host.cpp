@@ -2099,10 +2099,12 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
                                     prec, theta, rnorm);
             if (!std::isfinite(rnorm) || !std::isfinite(theta)) throw Error(DMRG_ERR_NAN, "non-finite Davidson residual");
             if (prec == DMRG_PREC_SPLIT2 && o->fp64_polish) {
-                // hand over at split_tol, or when the split residual has stopped improving (no new
-                // minimum by 1% for 10 iterations: the matvec rounding floor has been reached)
+                // hand over at split_tol, or, within 30x of it, when the split residual has stopped
+                // improving (no new minimum by 1% for 10 iterations: the matvec rounding floor has
+                // been reached; far above split_tol a plateau is ordinary Davidson progress)
                 bool hand_over = rnorm <= std::max(o->split_tol, o->tol);
-                if (rnorm < 0.99 * best_split_r) { best_split_r = rnorm; stall = 0; } else if (++stall >= 10) hand_over = true;
+                if (rnorm < 0.99 * best_split_r) { best_split_r = rnorm; stall = 0; }
+                else if (++stall >= 10 && rnorm < 30.0 * o->split_tol) hand_over = true;
                 if (hand_over) {
                     // restart in FP64 from the current Ritz vector
                     prec = DMRG_PREC_FP64;
