@@ -41,9 +41,12 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
-    ap.add_argument("--workload", choices=["precision", "batch", "large"], default="precision",
+    ap.add_argument("--workload", choices=["precision", "batch", "large", "precond"], default="precision",
                     help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems; "
-                         "large: L=76 (57,56) M=6000, one GPU's share of the operator pairs")
+                         "large: L=76 (57,56) M=6000, one GPU's share of the operator pairs; "
+                         "precond: learned vs diagonal Davidson preconditioner at L=32 M=1500")
+    ap.add_argument("--bonds", type=str, default="4,8,12,15,19,23,27",
+                    help="precond: left-site indices of the evaluated bonds")
     ap.add_argument("--pairs", type=int, default=100,
                     help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
@@ -66,6 +69,8 @@ def main():
         return bench_batch(args)
     if args.workload == "large":
         return bench_large(args)
+    if args.workload == "precond":
+        return bench_precond(args)
     dev = torch.device("cuda:0")
     L, M = args.L, args.M
     na = nb = L // 2
@@ -303,6 +308,67 @@ def bench_large(args):
             "roofline": {"bound": "mfma", "achieved": res["split"]["tflops"], "peak": PEAK["bf16"], "unit": "TFLOP/s",
                          "frac": round(res["split"]["tflops"] / PEAK["bf16"], 5), "traffic": None,
                          "fp64_frac": round(res["fp64"]["tflops"] / PEAK["fp64"], 4)}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_precond(args):
+    """Learned Davidson preconditioner vs the diagonal one. Training pairs come from converged FP64
+    solves of synthetic middle-bond problems at L = 20, 22, 24, 26, 28 (N = L, M = 512, seeds 3000+);
+    the network is trained on the GPU (Adam, 3000 steps of 4096 rows). Evaluation: L = 32, N = 32,
+    M = 1500 at the bonds --bonds (synthetic blocks of each bond, seed 3100 + bond), Davidson to
+    ||r|| <= 1e-8 from the same start vector with each preconditioner; iterations, time and |dE|."""
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_vector
+    from dmrg_inputs.synthetic import synthetic_problem
+    stream = torch.cuda.current_stream()
+    net = dm.Mlp(device=0, seed=5)
+    t0 = time.time()
+    for k, L in enumerate((20, 22, 24, 26, 28)):
+        h, eri, left, right, site = synthetic_problem(L, L // 2, L // 2, 512, 1.5, 3000 + k)
+        hop = dm.Hop(h, eri, left, right, L // 2, L // 2, site, device=0, stream=stream)
+        psi = torch.as_tensor(random_vector(hop.n_coeff, 40 + k), device="cuda:0")
+        res = net.collect(hop, psi, slot=0, rows_per_iter=4096, seed=k, tol=1e-9, max_iter=600, stream=stream)
+        log(f"[bench] precond: collected L={L}: iters {res['iters']} rows {res['rows']} converged {res['converged']}")
+        del hop
+    losses = net.train(3000, batch=4096, lr=1e-3, seed=1, stream=stream)
+    t_train = time.time() - t0
+    log(f"[bench] precond: training loss {float(losses[:50].mean()):.4f} -> {float(losses[-50:].mean()):.4f} "
+        f"({t_train:.1f}s incl. collection)")
+    L, M = 32, 1500
+    bonds = [int(b) for b in args.bonds.split(",")]
+    rows = []
+    for b in bonds:
+        h, eri, left, right, site = synthetic_problem(L, L // 2, L // 2, M, 1.5, 3100 + b, site=b)
+        hop = dm.Hop(h, eri, left, right, L // 2, L // 2, site, device=0, stream=stream)
+        row = {"site": b, "n_coeff": hop.n_coeff}
+        for name, use in (("diag", None), ("mlp", net)):
+            psi = torch.as_tensor(random_vector(hop.n_coeff, 77), device="cuda:0")
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = hop.davidson(psi, tol=1e-8, max_iter=1000, max_sub=24, mlp=use, stream=stream)
+            torch.cuda.synchronize()
+            row[name] = {"iters": r["iters"], "energy": r["energy"], "seconds": round(time.perf_counter() - t, 3),
+                         "converged": r["converged"], "fallback_iter": r["precond_fallback_iter"]}
+        row["dE"] = abs(row["mlp"]["energy"] - row["diag"]["energy"])
+        log(f"[bench] precond bond {b}: |psi|={hop.n_coeff} diag {row['diag']['iters']} it "
+            f"{row['diag']['seconds']}s, mlp {row['mlp']['iters']} it {row['mlp']['seconds']}s "
+            f"(fallback at {row['mlp']['fallback_iter']}), |dE| {row['dE']:.1e}")
+        rows.append(row)
+        del hop
+    it_d = sum(r["diag"]["iters"] for r in rows)
+    it_m = sum(r["mlp"]["iters"] for r in rows)
+    t_d = sum(r["diag"]["seconds"] for r in rows)
+    t_m = sum(r["mlp"]["seconds"] for r in rows)
+    line = {"metric": "Davidson iterations to ||r||<=1e-8, learned vs diagonal preconditioner", "value": it_m,
+            "unit": "iterations (sum over bonds)", "n_gpus": 1, "steps": len(bonds), "warmup": 0,
+            "ms_per_step": round(1e3 * t_m / len(bonds), 2), "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"Davidson at {len(bonds)} bonds of L={L} N={L} M={M} (synthetic blocks per bond); "
+                                   "network trained on L=20..28 M=512 solves",
+                       "bonds": bonds},
+            "diag_iters": it_d, "mlp_iters": it_m, "diag_seconds": round(t_d, 2), "mlp_seconds": round(t_m, 2),
+            "max_dE": max(r["dE"] for r in rows), "per_bond": rows, "train_seconds": round(t_train, 1)}
     print(json.dumps(line), flush=True)
 
 

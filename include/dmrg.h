@@ -188,7 +188,8 @@ typedef struct {
 } dmrg_dav_opts;
 
 #define DMRG_PRECOND_DIAG 0  /* t = r / (theta - D), D = diag(H), |theta - D| floored at 1e-8 */
-#define DMRG_PRECOND_MLP  1  /* t = r / (theta - D) * (1 + m), m from the learned network below */
+#define DMRG_PRECOND_MLP  1  /* t = r / (theta - D) * (1 + m), m from the learned network below, until
+                                the diagonal rule takes over (see precond_fallback_iter) */
 
 typedef struct {
     double  energy;          /* lowest Ritz value */
@@ -198,6 +199,9 @@ typedef struct {
     int32_t matvecs_split;   /* of which in split precision */
     double  t_total;         /* seconds, wall */
     double  t_hpsi;          /* seconds spent in H.psi (device time, HIP events) */
+    int32_t precond_fallback_iter; /* DMRG_PRECOND_MLP: iteration from which the diagonal correction
+                                      replaced the network (the residual made no new minimum, by 1%,
+                                      for 20 iterations); -1 if the network ran to the end */
 } dmrg_dav_result;
 
 /* psi: device pointer, n_coeff doubles: in = start vector (need not be normalized, must be

@@ -58,7 +58,8 @@ class DavOpts(C.Structure):
 
 class DavResult(C.Structure):
     _fields_ = [("energy", C.c_double), ("resid", C.c_double), ("iters", C.c_int32), ("matvecs", C.c_int32),
-                ("matvecs_split", C.c_int32), ("t_total", C.c_double), ("t_hpsi", C.c_double)]
+                ("matvecs_split", C.c_int32), ("t_total", C.c_double), ("t_hpsi", C.c_double),
+                ("precond_fallback_iter", C.c_int32)]
 
 
 lib.dmrg_last_error.restype = C.c_char_p
@@ -294,7 +295,8 @@ def _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp, us
 
 def _dav_result(r, st):
     return dict(energy=r.energy, resid=r.resid, iters=r.iters, matvecs=r.matvecs, matvecs_split=r.matvecs_split,
-                t_total=r.t_total, t_hpsi=r.t_hpsi, converged=st == DMRG_OK)
+                t_total=r.t_total, t_hpsi=r.t_hpsi, precond_fallback_iter=r.precond_fallback_iter,
+                converged=st == DMRG_OK)
 
 
 class Mlp:

@@ -2080,6 +2080,10 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         std::vector<double> evals, evecs;
         double best_split_r = INFINITY;
         int stall = 0;
+        bool mlp_on = o->precond == DMRG_PRECOND_MLP;
+        double best_mlp_r = INFINITY;
+        int mlp_stall = 0;
+        res->precond_fallback_iter = -1;
         for (it = 1; it <= o->max_iter; ++it) {
             std::vector<double> A((size_t)k * k);
             for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j)
@@ -2160,7 +2164,13 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
             }
             HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             have_prev = true;
-            if (sess) sess->correction(r, u, t, theta, w.V, k);
+            if (o->precond == DMRG_PRECOND_MLP && mlp_on) {
+                // the diagonal preconditioner judges the network: once the residual has made no new
+                // minimum (by 1%) for 20 iterations, the rest of the solve uses the diagonal correction
+                if (rnorm < 0.99 * best_mlp_r) { best_mlp_r = rnorm; mlp_stall = 0; }
+                else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
+            }
+            if (sess) sess->correction(r, u, t, theta, w.V, k, mlp_on);
             orth(k, t);
             double nt = normalize(t);
             if (nt < 1e-14) break;

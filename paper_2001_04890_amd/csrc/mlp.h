@@ -104,9 +104,10 @@ public:
     MlpSession(const MlpSession&) = delete;
     MlpSession& operator=(const MlpSession&) = delete;
     // t holds the diagonal correction of (r, theta) on entry and V (k orthonormal vectors) the
-    // subspace t is about to be orthogonalized against; records a training pair and/or applies the
-    // network to t.
-    void correction(const double* r, const double* u, double* t, double theta, const double* V, int k);
+    // subspace t is about to be orthogonalized against; records a training pair and/or (apply_net)
+    // applies the network to t.
+    void correction(const double* r, const double* u, double* t, double theta, const double* V, int k,
+                    bool apply_net = true);
     int64_t rows_recorded() const { return rows_; }
 
 private:

@@ -268,7 +268,8 @@ MlpSession::MlpSession(const dmrg_mlp* net, dmrg_mlp* rec, int slot, int rows_pe
 
 MlpSession::~MlpSession() { delete impl_; }
 
-void MlpSession::correction(const double* r, const double* u, double* t, double theta, const double* V, int k) {
+void MlpSession::correction(const double* r, const double* u, double* t, double theta, const double* V, int k,
+                            bool apply_net) {
     Impl& I = *impl_;
     const int64_t n = I.prob.n;
     I.feats.compute(r, u, t, theta, I.feat, I.s);
@@ -301,7 +302,7 @@ void MlpSession::correction(const double* r, const double* u, double* t, double 
             rows_ += nr;
         }
     }
-    if (I.net) HIPCHK(launch_mlp_forward(I.net->dev(), I.feat, n, nullptr, nullptr, nullptr, t, I.s));
+    if (I.net && apply_net) HIPCHK(launch_mlp_forward(I.net->dev(), I.feat, n, nullptr, nullptr, nullptr, t, I.s));
 }
 
 }  // namespace dmrg
