@@ -241,6 +241,14 @@ struct dmrg_hop {
     std::vector<dmrg::BigChunk> big_chunks;
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
+    // FP64 two-pass path (hpsi_big64.hip) for the same large targets
+    int tune_big64 = 1;                         // 1: large targets of the FP64 H.psi take the two-pass path
+    double* d_tiled64 = nullptr;                // FP64 tiled operators + identity blocks (made on first use)
+    int64_t tiled64_size = 0;
+    std::vector<int64_t> ident64_off;           // FP64 tiled identity block of size 32 (k + 1)
+    dmrg::BigPlan bplan64{};
+    std::vector<dmrg::BigChunk> big_chunks64;
+    double* xt64 = nullptr;                     // FP64 tiled X^T of one vector (plan allocation)
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t n_alpha = 0;
     int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
@@ -1126,15 +1134,23 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     HIPCHK(hipStreamSynchronize(s));
 }
 
-// Launch plan of the large-block split path (hpsi_big.hip) for the targets flagged in `big`: targets
-// are grouped into chunks whose T buffers (one per task: target rows x source columns, tiled hi/lo)
-// stay below kBigTBudget elements; per chunk, pass 1 has one workgroup per (task, 8 row tiles,
-// 4 column chunks) and pass 2 one item per (target, 8 row tiles, 8 column tiles, task range), the
-// task lists cut into items of bounded cost whose partial tiles a reduction adds in order.
-void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
-    const int64_t kBigTBudget = (int64_t)H.tune_big_tbudget_mb << 19;   // u16 elements of T per chunk
-    H.bplan = dmrg::BigPlan{};
-    H.big_chunks.clear();
+// Launch plan of the two-pass large-block path for the targets flagged in `big`, split (hpsi_big.hip,
+// fp64 = false: 16 x 32 hi/lo tiles, u16 offsets) or FP64 (hpsi_big64.hip: 16 x 16 tiles, offsets
+// in doubles). Targets are grouped into chunks whose T buffers (one per task: target rows x source
+// columns, tiled) stay below the T budget; per chunk, pass 1 has one group per (task, 8 row tiles,
+// 128 T columns), consecutive groups packed into workgroups of about tune_big_stages1 k steps, and
+// pass 2 one item per (target, 8 row tiles, 8 column tiles, task range), the task lists cut into
+// items of about tune_big_stages k steps whose partial tiles a reduction adds in order.
+void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bool fp64) {
+    const int unit = fp64 ? 16 : 32;                 // k-tile width
+    const int64_t esc = fp64 ? 1 : 2;                // tiled-array elements per pool element
+    const int64_t tile_el = fp64 ? 256 : dmrg::kTileU16;
+    const int64_t kBigTBudget = (int64_t)H.tune_big_tbudget_mb << (fp64 ? 18 : 19);   // T elements per chunk
+    dmrg::BigPlan& plan = fp64 ? H.bplan64 : H.bplan;
+    std::vector<dmrg::BigChunk>& chunks = fp64 ? H.big_chunks64 : H.big_chunks;
+    const std::vector<int64_t>& ident_tab = fp64 ? H.ident64_off : H.ident_off;
+    plan = dmrg::BigPlan{};
+    chunks.clear();
     const size_t nb = H.blk.size();
     std::vector<int64_t> pk_off(nb);
     {
@@ -1143,8 +1159,8 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     }
     auto ident = [&](int p) -> int64_t {
         const int k = p / 32 - 1;
-        if (k < 0 || k >= (int)H.ident_off.size()) return -1;
-        return H.ident_off[k];
+        if (k < 0 || k >= (int)ident_tab.size()) return -1;
+        return ident_tab[k];
     };
     std::vector<dmrg::BigT1> t1;
     std::vector<dmrg::BigT2> t2;
@@ -1167,13 +1183,7 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     std::vector<int> chunk_targets;
     auto close_chunk = [&]() {
         if (chunk_targets.empty()) return;
-        // pass-2 items of the chunk's targets
-        double total = 0.0;
-        for (int j : chunk_targets)
-            for (size_t k = trange[j].first; k < trange[j].second; ++k)
-                total += dmrg::ld_of(H.blk_md[H.tasks[k].i]) / 32;
-        (void)total;
-        // pass-1 workgroups: consecutive groups of the chunk with about tune_big_stages k steps each
+        // pass-1 workgroups: consecutive groups of the chunk with about tune_big_stages1 k steps each
         cur.t1_begin = (int)t1_ranges.size();
         {
             int c = 0;
@@ -1191,13 +1201,10 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
         part = 0;
         for (int j : chunk_targets) {
             const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, nq = dmrg::rows_of(H.blk_md[j]) / 16;
-            const int32_t tb = t2.size() ? 0 : 0;
-            (void)tb;
+            const int32_t b0 = H.big_t2_range[j].first, b1 = H.big_t2_range[j].second;
             for (int rb = 0; rb < nrt; rb += 8)
                 for (int qb = 0; qb < nq; qb += 8) {
-                    const int tm = 16 * std::min(8, nrt - rb), tn = 16 * std::min(8, nq - qb);
-                    // task list of this target in t2: [first, last) stored when the target was added
-                    const int32_t b0 = H.big_t2_range[j].first, b1 = H.big_t2_range[j].second;
+                    const int tn = 16 * std::min(8, nq - qb);
                     std::vector<std::pair<int32_t, int32_t>> cuts;
                     int32_t b = b0;
                     int c = 0;
@@ -1219,14 +1226,13 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
                             part += (int64_t)128 * tn;
                         }
                     }
-                    (void)tm;
                 }
         }
         cur.item_end = (int)items.size();
         cur.red_end = (int)reds.size();
         part_max = std::max(part_max, part);
         tbuf_max = std::max(tbuf_max, tsize);
-        H.big_chunks.push_back(cur);
+        chunks.push_back(cur);
         cur = dmrg::BigChunk{0, 0, 0, 0, 0, 0};
         chunk_targets.clear();
         tsize = 0;
@@ -1237,24 +1243,23 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
         const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16;
         int64_t need = 0;
         for (size_t k = trange[j].first; k < trange[j].second; ++k)
-            need += (int64_t)nrt * (dmrg::ld_of(H.blk_md[H.tasks[k].i]) / 32) * dmrg::kTileU16;
+            need += (int64_t)nrt * (dmrg::ld_of(H.blk_md[H.tasks[k].i]) / unit) * tile_el;
         if (tsize > 0 && tsize + need > kBigTBudget) close_chunk();
         const int32_t b0 = (int32_t)t2.size();
         for (size_t k = trange[j].first; k < trange[j].second; ++k) {
             const auto& ht = H.tasks[k];
             const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
             const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
-            const int64_t a_off = ht.lm >= 0 ? 2 * H.mats[ht.lm].pool_of_in[a] : ident(pa);
-            const int64_t b_off = ht.rm >= 0 ? 2 * H.mats[ht.rm].pool_of_in[d] : ident(pd);
-            if (a_off < 0 || b_off < 0)
-                throw Error(DMRG_ERR_UNSUPPORTED, "identity factor wider than 96 in the large-block path");
+            const int64_t a_off = ht.lm >= 0 ? esc * H.mats[ht.lm].pool_of_in[a] : ident(pa);
+            const int64_t b_off = ht.rm >= 0 ? esc * H.mats[ht.rm].pool_of_in[d] : ident(pd);
+            if (a_off < 0 || b_off < 0) throw Error(DMRG_ERR_ARG, "internal: no tiled identity block");
             const int64_t t_off = tsize;
-            tsize += (int64_t)nrt * (pd / 32) * dmrg::kTileU16;
+            tsize += (int64_t)nrt * (pd / unit) * tile_el;
             for (int rb = 0; rb < nrt; rb += 8)
-                for (int jb = 0; jb < pd / 32; jb += 4)
-                    t1.push_back({2 * pk_off[ht.i], a_off, t_off, (float)ht.f, (int16_t)(pa / 32), (int16_t)(pd / 32),
-                                  (int16_t)nrt, (int16_t)rb, (int16_t)jb, 0});
-            t2.push_back({t_off, b_off, pd / 32, 0});
+                for (int jb = 0; jb < pd / unit; jb += 128 / unit)
+                    t1.push_back({esc * pk_off[ht.i], a_off, t_off, ht.f, (int16_t)(pa / unit),
+                                  (int16_t)(pd / unit), (int16_t)nrt, (int16_t)rb, (int16_t)jb, 0});
+            t2.push_back({t_off, b_off, pd / unit, 0});
         }
         H.big_t2_range[j] = {b0, (int32_t)t2.size()};
         chunk_targets.push_back((int)j);
@@ -1264,7 +1269,7 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     dmrg::BigT1* d_t1 = plan_alloc<dmrg::BigT1>(H, t1.size());
     int32_t* d_t1r = plan_alloc<int32_t>(H, t1_ranges.size());
     HIPCHK(hipMemcpyAsync(d_t1r, t1_ranges.data(), t1_ranges.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    H.bplan.t1_ranges = d_t1r;
+    plan.t1_ranges = d_t1r;
     dmrg::BigT2* d_t2 = plan_alloc<dmrg::BigT2>(H, t2.size());
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -1272,21 +1277,22 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big) {
     HIPCHK(hipMemcpyAsync(d_t2, t2.data(), t2.size() * sizeof(t2[0]), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
     if (!reds.empty()) HIPCHK(hipMemcpyAsync(d_red, reds.data(), reds.size() * sizeof(reds[0]), hipMemcpyHostToDevice, s));
-    H.bplan.t1 = d_t1;
-    H.bplan.t2 = d_t2;
-    H.bplan.items = d_items;
-    H.bplan.reduces = d_red;
-    H.bplan.chunks = H.big_chunks.data();
-    H.bplan.n_chunks = (int)H.big_chunks.size();
-    H.bplan.red_chunks = (red_max + 255) / 256;
-    H.bplan.tbuf = plan_alloc<uint16_t>(H, (size_t)std::max<int64_t>(tbuf_max, 1));
-    H.bplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1));
-    H.bplan.partial_size = part_max;
+    plan.t1 = d_t1;
+    plan.t2 = d_t2;
+    plan.items = d_items;
+    plan.reduces = d_red;
+    plan.chunks = chunks.data();
+    plan.n_chunks = (int)chunks.size();
+    plan.red_chunks = (red_max + 255) / 256;
+    const size_t tbytes = (size_t)std::max<int64_t>(tbuf_max, 1) * (fp64 ? sizeof(double) : sizeof(uint16_t));
+    plan.tbuf = plan_alloc<uint16_t>(H, tbytes / sizeof(uint16_t));
+    plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1));
+    plan.partial_size = part_max;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1')
-            std::fprintf(stderr, "[dmrg big plan] chunks %zu pass-1 groups %zu pass-2 items %zu reduces %zu T %.1f MB "
-                         "partial %.1f MB\n", H.big_chunks.size(), t1.size(), items.size(), reds.size(),
-                         tbuf_max * 2e-6, part_max * 8e-6);
+            std::fprintf(stderr, "[dmrg big plan%s] chunks %zu pass-1 groups %zu pass-2 items %zu reduces %zu T %.1f MB "
+                         "partial %.1f MB\n", fp64 ? " fp64" : "", chunks.size(), t1.size(), items.size(), reds.size(),
+                         tbytes * 1e-6, part_max * 8e-6);
     HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -1300,11 +1306,74 @@ void drop_graphs(dmrg_hop& H) {
     H.graphs.clear();
 }
 
+// Targets whose own or some source's padded dimension exceeds the 96-wide LDS stages.
+std::vector<char> large_targets(const dmrg_hop& H) {
+    std::vector<int> smax(H.blk.size(), 0);
+    for (size_t j = 0; j < H.blk.size(); ++j) smax[j] = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
+    for (const auto& t : H.tasks)
+        smax[t.j] = std::max({smax[t.j], dmrg::ld_of(H.blk_ma[t.i]), dmrg::ld_of(H.blk_md[t.i])});
+    std::vector<char> big(H.blk.size(), 0);
+    for (size_t j = 0; j < H.blk.size(); ++j) big[j] = smax[j] > 96;
+    return big;
+}
+
+// FP64 tiled copy of the whole pool (16 x 16 tiles of hpsi_big64.hip, same offsets as the pool)
+// followed by FP64 tiled identity blocks of sizes 32, 64, ... up to the widest padded block, which
+// stand in for identity factors. Made once, on the first plan that routes targets to the FP64
+// large-block path.
+void make_tiled_f64(dmrg_hop& H, hipStream_t s) {
+    if (H.d_tiled64) return;
+    const int64_t n = H.pool_size;
+    int pmax = 96;
+    for (size_t i = 0; i < H.blk.size(); ++i)
+        pmax = std::max({pmax, dmrg::ld_of(H.blk_ma[i]), dmrg::ld_of(H.blk_md[i])});
+    std::vector<double> id;
+    H.ident64_off.assign(pmax / 32, -1);
+    for (int k = 0; k < pmax / 32; ++k) {
+        const int p = 32 * (k + 1), k16 = p / 16;
+        H.ident64_off[k] = n + (int64_t)id.size();
+        const size_t base = id.size();
+        id.resize(base + (size_t)p * p, 0.0);
+        for (int i = 0; i < p; ++i) {
+            // element (i, i): tile (i / 16, i / 16), lane (i % 16) + 16 ((i % 16) % 4), value (i % 16) / 4
+            const int t = i / 16, c = i % 16, lane = c + 16 * (c % 4), v = c / 4;
+            id[base + (size_t)(t * k16 + t) * 256 + lane * 4 + v] = 1.0;
+        }
+    }
+    H.tiled64_size = n + (int64_t)id.size();
+    H.d_tiled64 = dev_alloc<double>(H, H.tiled64_size);
+    dmrg::PoolBlock* d_pb = dev_alloc<dmrg::PoolBlock>(H, H.pool_blocks.size());
+    HIPCHK(hipMemcpyAsync(d_pb, H.pool_blocks.data(), H.pool_blocks.size() * sizeof(dmrg::PoolBlock),
+                          hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(H.d_tiled64 + n, id.data(), id.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(dmrg::launch_tile_f64(H.d_pool, d_pb, (int)H.pool_blocks.size(), H.d_tiled64, s));
+    HIPCHK(hipStreamSynchronize(s));   // the staging vector goes out of scope
+}
+
 void build_plan(dmrg_hop& H, hipStream_t s) {
     drop_graphs(H);
     for (void* p : H.plan_allocations) (void)hipFree(p);
     H.plan_allocations.clear();
-    build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
+    // FP64: targets above the LDS stage size take the two-pass path, the others the one-wave kernel
+    H.bplan64 = dmrg::BigPlan{};
+    H.big_chunks64.clear();
+    H.xt64 = nullptr;
+    std::vector<char> big64;
+    bool any_big = false;
+    if (H.tune_big64) {
+        big64 = large_targets(H);
+        for (char b : big64) any_big |= b != 0;
+    }
+    if (any_big) {
+        std::vector<char> rest(big64.size());
+        for (size_t j = 0; j < big64.size(); ++j) rest[j] = !big64[j];
+        build_plan_core(H, s, &rest, false, H.plan, H.launches, H.phases);
+        make_tiled_f64(H, s);
+        build_big_plan(H, s, big64, true);
+        H.xt64 = plan_alloc<double>(H, (size_t)std::max<int64_t>(H.plan.packed_size, 1));
+    } else {
+        build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
+    }
     H.plan_fb = dmrg::HpsiPlan{};
     H.launches_fb.clear();
     H.phases_fb.clear();
@@ -1315,7 +1384,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     H.bplan = dmrg::BigPlan{};
     if (H.n_fallback_targets > 0) {
         if (H.tune_big) {
-            build_big_plan(H, s, fb);
+            build_big_plan(H, s, fb, false);
             H.n_fallback_targets = 0;
         } else {
             if (!H.d_hi) throw Error(DMRG_ERR_ARG, "internal: row-major split operators missing");
@@ -1327,11 +1396,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
 // True when some target block (or one of its sources) has a padded dimension above the LDS stage
 // size of the LDS-staged split kernel.
 bool needs_fallback(const dmrg_hop& H) {
-    std::vector<int> smax(H.blk.size(), 0);
-    for (size_t j = 0; j < H.blk.size(); ++j) smax[j] = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
-    for (const auto& t : H.tasks)
-        smax[t.j] = std::max({smax[t.j], dmrg::ld_of(H.blk_ma[t.i]), dmrg::ld_of(H.blk_md[t.i])});
-    for (int v : smax) if (v > 96) return true;
+    for (char b : large_targets(H)) if (b) return true;
     return false;
 }
 
@@ -1556,6 +1621,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_TBUDGET_MB")) H->tune_big_tbudget_mb = std::max(16, std::atoi(e));
@@ -1674,6 +1740,9 @@ void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t
         double* yv = y + (int64_t)v0 * H->n_coeff;
         if (precision == DMRG_PREC_FP64) {
             HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
+            for (int v = 0; v < nv && H->bplan64.n_chunks > 0; ++v)
+                HIPCHK(dmrg::launch_hpsi_big64(H->bplan64, H->d_tiled64, H->plan.packs, H->plan.n_packs,
+                                               xv + (int64_t)v * H->n_coeff, H->xt64, yv + (int64_t)v * H->n_coeff, s));
         } else {
             HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
             for (int v = 0; v < nv && H->bplan.n_chunks > 0; ++v)
@@ -1823,6 +1892,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
                 HIPCHK(dmrg::launch_split(C->d_pool, C->pool_size, C->d_hi, C->d_lo, s));
             }
         }
+        C->tune_big64 = hops[0]->tune_big64;
         build_plan(*C, s);
         *out = C;
         return DMRG_OK;

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, c
         const BigT1* wp = work + i;
         G d;
         d.x = uni64(wp->xt); d.a = uni64(wp->a); d.t = uni64(wp->t);
-        d.f = __builtin_bit_cast(float, uni(__builtin_bit_cast(int, wp->f)));
+        d.f = (float)__builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, wp->f)));
         d.pa32 = uni(wp->pa32); d.pd32 = uni(wp->pd32); d.nrt = uni(wp->nrt); d.rb = uni(wp->rb); d.jb = uni(wp->jb);
         return d;
     };

@@ -175,9 +175,11 @@ struct LdsPlan {
 // targets: pass 1 writes T = f A X of every task into a tiled hi/lo buffer (tile (rt, jc) of the
 // task's T at t_off + (rt * pd32 + jc) * kTileU16, in the A-operand fragment layout of pass 2),
 // pass 2 accumulates Y += sum_tasks T B^T per 128 x 128 output tile.
-struct BigT1 {             // pass-1 workgroup: one task, rows [16 rb, 16 rb + 128), T^T rows [32 jb, 32 jb + 128)
+// FP64 form (hpsi_big64.hip): 16 x 16 FP64 tiles, offsets in doubles, pa32 / pd32 / jb counted in
+// 16-wide tiles.
+struct BigT1 {             // pass-1 group: one task, rows [16 rb, 16 rb + 128), T^T rows [32 jb, 32 jb + 128)
     int64_t xt, a, t;      // tiled X^T of the source, tiled A, output T (u16 offsets)
-    float f;
+    double f;
     int16_t pa32, pd32;    // source rows / cols in 32-element k tiles
     int16_t nrt;           // row tiles of the target block
     int16_t rb, jb;        // first row tile, first 32-column chunk
@@ -191,7 +193,7 @@ struct BigT2 {             // pass-2 task: T of the task and its B block
 // Chunk c: pass-1 workgroups [t1_begin, t1_end) (workgroup w runs groups t1_ranges[w] ..
 // t1_ranges[w + 1] - 1), pass-2 items [item_begin, item_end), reductions [red_begin, red_end).
 struct BigChunk { int t1_begin, t1_end, item_begin, item_end, red_begin, red_end; };
-struct BigPlan {
+struct BigPlan {                    // split or FP64 form (see BigT1)
     const BigT1* t1 = nullptr;      // device
     const int32_t* t1_ranges = nullptr;   // device, one entry per pass-1 workgroup plus one
     const BigT2* t2 = nullptr;      // device
@@ -200,7 +202,7 @@ struct BigPlan {
     const BigChunk* chunks = nullptr;   // host
     int n_chunks = 0;
     int red_chunks = 1;             // 256-element chunks of the largest partial tile
-    uint16_t* tbuf = nullptr;       // device, largest chunk's T (one vector at a time)
+    uint16_t* tbuf = nullptr;       // device, largest chunk's T (one vector at a time; doubles in the FP64 form)
     double* partial = nullptr;      // device, partial tiles of the largest chunk
     int64_t partial_size = 0;
 };
@@ -235,6 +237,11 @@ hipError_t launch_hpsi_lds(const LdsPlan& plan, const uint16_t* pool_t, const do
 // xt = that vector's tiled X^T (packed by launch_hpsi_lds).
 hipError_t launch_hpsi_big(const BigPlan& plan, const uint16_t* pool_t, const uint16_t* xt, double* y,
                            hipStream_t s);
+// FP64 large-block path (hpsi_big64.hip) for one vector: y += the large targets' part of H x, over the
+// FP64 tiled pool; packs x into xt (FP64 tiled X^T, packed_size doubles) first.
+hipError_t launch_tile_f64(const double* pool, const PoolBlock* blocks, int n_blocks, double* tiled, hipStream_t s);
+hipError_t launch_hpsi_big64(const BigPlan& plan, const double* pool_t, const PackBlock* packs, int n_packs,
+                             const double* x, double* xt, double* y, hipStream_t s);
 // Old-kernel split path over a plan without clearing y first.
 hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
                                  double* y, int64_t n_coeff, int nvec, hipStream_t s);

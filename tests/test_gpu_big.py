@@ -1,0 +1,141 @@
+"""GPU parity of the two-pass large-block path (targets whose own or source blocks exceed the 96-wide
+LDS stages) against the FP64 oracle, through the C-ABI, in both precisions.
+
+Plan variants: the default plan; a cut plan (16 MB T budget: several chunks; 4-step pass-1
+workgroups: many groups per workgroup; 4-step pass-2 items: task lists cut into partial tiles that
+ordered reductions add); and the large-block path switched off (one-wavefront kernels). Bars as for
+every H.psi: FP64 within 1e-12 of max|y|, split within 5e-4; split plans that move FP32 run
+boundaries agree within 2e-6; every plan is deterministic bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from dmrg_inputs import random_vector
+from oracle.hpsi import OracleHop
+from helpers import rel_err, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+lib_mod = pytest.importorskip("paper_2001_04890_amd")
+Hop, PREC_FP64, PREC_SPLIT2 = lib_mod.Hop, lib_mod.PREC_FP64, lib_mod.PREC_SPLIT2
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+FP64_TOL = 1e-12
+SPLIT_TOL = 5e-4
+VARIANTS = {
+    "default": {},
+    "cut": {"DMRG_BIG_STAGES": "4", "DMRG_BIG_STAGES1": "4", "DMRG_BIG_TBUDGET_MB": "16"},
+    "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0"},
+}
+
+
+def build(p, variant):
+    h, eri, left, right, na, nb, site = p
+    env = VARIANTS[variant]
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return Hop(h, eri, left, right, na, nb, site, device=0, want_split=True)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def run(hop, x, prec):
+    xd = torch.as_tensor(x, device=DEV).contiguous()
+    yd = torch.empty_like(xd)
+    hop.hpsi(xd, yd, prec)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def block_slices(oh, targets):
+    return [slice(oh.layout.blocks[j][4], oh.layout.blocks[j][4] + oh.layout.blocks[j][5] * oh.layout.blocks[j][6])
+            for j in targets]
+
+
+# ---------------------------------------------------------------- case A: every target, full oracle
+@pytest.fixture(scope="module")
+def case_a():
+    # L = 14, M = 300: sectors up to 139 states (two 128-row tiles, the second ragged)
+    p = synth(14, 300, 0.6, 5)
+    print("[big A] L=14 M=300: oracle", flush=True)
+    oh = OracleHop(*p)
+    x = random_vector(oh.layout.size, 41)
+    return p, oh, x, oh.apply(x)
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS))
+def test_case_a_matches_oracle(case_a, variant):
+    p, oh, x, ref = case_a
+    print(f"[big A] variant {variant}", flush=True)
+    hop = build(p, variant)
+    y64 = run(hop, x, PREC_FP64)
+    assert rel_err(y64, ref) < FP64_TOL, variant
+    ysp = run(hop, x, PREC_SPLIT2)
+    err = rel_err(ysp, ref)
+    print(f"[big A] {variant}: fp64 {rel_err(y64, ref):.2e} split {err:.2e}", flush=True)
+    assert err < SPLIT_TOL, variant
+    assert np.array_equal(run(hop, x, PREC_FP64), y64)
+    assert np.array_equal(run(hop, x, PREC_SPLIT2), ysp)
+
+
+def test_case_a_plans_agree(case_a):
+    p, oh, x, ref = case_a
+    a, b = build(p, "default"), build(p, "cut")
+    assert rel_err(run(b, x, PREC_FP64), run(a, x, PREC_FP64)) < 1e-13
+    assert rel_err(run(b, x, PREC_SPLIT2), run(a, x, PREC_SPLIT2)) < 2e-6
+
+
+# ---------------------------------------------------------------- case B: sampled large targets
+@pytest.fixture(scope="module")
+def case_b():
+    # L = 16, M = 1000, sigma = 0.35: 36 blocks, the largest 250 x 250 (rows 250 = 128 + 122)
+    p = synth(16, 1000, 0.35, 7)
+    print("[big B] L=16 M=1000: oracle", flush=True)
+    oh = OracleHop(*p)
+    bl = oh.layout.blocks
+    big = [j for j in range(len(bl)) if max(bl[j][5], bl[j][6]) > 96]
+    rng = np.random.default_rng(3)
+    targets = sorted(set(sorted(big, key=lambda j: -bl[j][5] * bl[j][6])[:4]) |
+                     set(rng.choice(big, size=min(3, len(big)), replace=False).tolist()))
+    x = random_vector(oh.layout.size, 43)
+    ref = oh.apply(x, targets=targets)
+    return p, oh, x, ref, targets
+
+
+@pytest.mark.parametrize("variant", ["default", "cut"])
+def test_case_b_sampled_targets(case_b, variant):
+    p, oh, x, ref, targets = case_b
+    print(f"[big B] variant {variant}, targets {targets}", flush=True)
+    hop = build(p, variant)
+    sl = block_slices(oh, targets)
+    r = np.concatenate([ref[s] for s in sl])
+    for prec, bar in ((PREC_FP64, FP64_TOL), (PREC_SPLIT2, SPLIT_TOL)):
+        y = run(hop, x, prec)
+        err = rel_err(np.concatenate([y[s] for s in sl]), r)
+        print(f"[big B] {variant} prec {prec}: {err:.2e}", flush=True)
+        assert err < bar, (variant, prec)
+
+
+def test_case_b_multivector_deterministic(case_b):
+    p, oh, x, ref, targets = case_b
+    hop = build(p, "default")
+    X = np.stack([random_vector(hop.n_coeff, 50 + k) for k in range(5)])   # more vectors than one launch holds
+    xd = torch.as_tensor(X, device=DEV).contiguous()
+    for prec in (PREC_FP64, PREC_SPLIT2):
+        y1, y2 = torch.empty_like(xd), torch.empty_like(xd)
+        hop.hpsi(xd, y1, prec)
+        hop.hpsi(xd, y2, prec)
+        torch.cuda.synchronize()
+        assert torch.equal(y1, y2)
+        for k in (0, 4):
+            assert np.array_equal(y1[k].cpu().numpy(), run(hop, X[k], prec))
