@@ -2027,7 +2027,7 @@ struct DavWork {
     double* tmp = nullptr;   // 3 x n  (u, r, t)
     double* prev = nullptr;  // n
     double* part = nullptr;  // partial dots
-    double* dots = nullptr;  // max_sub + 2
+    double* dots = nullptr;  // max_sub + 4: dot products [0, max_sub], squared norms at max_sub + 1, + 2
     std::vector<void*> allocs;
     ~DavWork() { for (void* p : allocs) (void)hipFree(p); }
     template <class T> T* get(size_t n) { void* p; if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw Error(DMRG_ERR_NOMEM, "device allocation failed (Davidson work space)"); allocs.push_back(p); return (T*)p; }
@@ -2083,7 +2083,7 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         w.prev = w.get<double>(n);
         int np = dmrg::multidot_parts(n);
         w.part = w.get<double>((size_t)np * (K + 2));
-        w.dots = w.get<double>(K + 2);
+        w.dots = w.get<double>(K + 4);
         double* restart_scratch = w.get<double>((size_t)4 * n);
         double* u = w.tmp;
         double* r = w.tmp + n;
@@ -2094,23 +2094,46 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         double t_hpsi = 0.0;
         int prec = o->precision;
         int matvecs = 0, matvecs_split = 0;
+        // every matvec is followed by a host synchronization (dots / fetch) before the next one; its
+        // event-timed duration is collected there
+        bool timing_pending = false;
+        auto collect_timing = [&]() {
+            if (!timing_pending) return;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t_hpsi += ms * 1e-3;
+            timing_pending = false;
+        };
         auto matvec = [&](const double* x, double* y) {
             HIPCHK(hipEventRecord(e0, s));
             dmrg_status st = o->use_graph ? dmrg_hpsi_graph(H, x, y, 1, prec, s) : dmrg_hpsi(H, x, y, 1, prec, s);
             if (st != DMRG_OK) throw Error(st, g_err);
             HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            t_hpsi += ms * 1e-3;
+            timing_pending = true;
             ++matvecs;
             if (prec == DMRG_PREC_SPLIT2) ++matvecs_split;
         };
-        std::vector<double> hd(K + 2);
+        std::vector<double> hd(K + 4);
+        auto fetch = [&](int count) {               // w.dots[0, count) -> hd, synchronizing the stream
+            HIPCHK(hipMemcpyAsync(hd.data(), w.dots, count * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            collect_timing();
+        };
         auto dots = [&](const double* Vs, int nv, const double* x) {
             HIPCHK(dmrg::launch_multidot(Vs, nv, n, x, w.part, np, w.dots, s));
-            HIPCHK(hipMemcpyAsync(hd.data(), w.dots, nv * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            fetch(nv);
+        };
+        // device-side classical Gram-Schmidt (twice) of x against the first k columns of V, and
+        // normalization with the squared norm left in w.dots[slot]: no host round trip
+        auto orth_dev = [&](int k, double* x) {
+            for (int pass = 0; pass < 2 && k > 0; ++pass) {
+                HIPCHK(dmrg::launch_multidot(w.V, k, n, x, w.part, np, w.dots, s));
+                HIPCHK(dmrg::launch_project_out(w.V, k, n, w.dots, x, s));
+            }
+        };
+        auto normalize_dev = [&](double* x, int slot) {
+            HIPCHK(dmrg::launch_multidot(x, 1, n, x, w.part, np, w.dots + slot, s));
+            HIPCHK(dmrg::launch_scale_dev(x, w.dots + slot, n, s));
         };
         auto combine = [&](const double* Vs, int nv, const std::vector<double>& c, double* out, double beta) {
             dmrg::Coefs cf;
@@ -2124,15 +2147,6 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
             if (nrm == 0.0) return 0.0;
             HIPCHK(dmrg::launch_scale(x, 1.0 / nrm, n, s));
             return nrm;
-        };
-        // Gram-Schmidt (classical, twice) of x against the first k columns of V
-        auto orth = [&](int k, double* x) {
-            for (int pass = 0; pass < 2 && k > 0; ++pass) {
-                dots(w.V, k, x);
-                std::vector<double> c(k);
-                for (int i = 0; i < k; ++i) c[i] = -hd[i];
-                combine(w.V, k, c, x, 1.0);
-            }
         };
         const char* tr_env = std::getenv("DMRG_DAVIDSON_TRACE");
         const bool trace = tr_env && tr_env[0] == '1';
@@ -2241,14 +2255,20 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
                 else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
             }
             if (sess) sess->correction(r, u, t, theta, w.V, k, mlp_on);
-            orth(k, t);
-            double nt = normalize(t);
-            if (nt < 1e-14) break;
-            orth(k, t);                                   // re-orthogonalize after scaling (cheap insurance)
-            normalize(t);
-            HIPCHK(hipMemcpyAsync(w.V + (size_t)k * n, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-            matvec(w.V + (size_t)k * n, w.W + (size_t)k * n);
-            dots(w.V, k + 1, w.W + (size_t)k * n);
+            // next basis vector, built in place on the device: orthogonalize, normalize, and once more
+            // after scaling (cheap insurance); its norm before scaling returns with the new column of G
+            double* vk = w.V + (size_t)k * n;
+            HIPCHK(hipMemcpyAsync(vk, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            orth_dev(k, vk);
+            normalize_dev(vk, K + 1);
+            orth_dev(k, vk);
+            normalize_dev(vk, K + 2);
+            matvec(vk, w.W + (size_t)k * n);
+            HIPCHK(dmrg::launch_multidot(w.V, k + 1, n, w.W + (size_t)k * n, w.part, np, w.dots, s));
+            fetch(K + 3);
+            const double nt = std::sqrt(hd[K + 1]);
+            if (!std::isfinite(nt) || !std::isfinite(hd[K + 2])) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
+            if (nt < 1e-14) break;                        // the correction lies in span(V): no new direction
             for (int i = 0; i <= k; ++i) { G[(size_t)i * K + k] = hd[i]; G[(size_t)k * K + i] = hd[i]; }
             ++k;
         }

@@ -228,6 +228,9 @@ hipError_t launch_precond(const double* r, const double* d, double theta, double
                           hipStream_t s);
 hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t s);
 int multidot_parts(int64_t n);
+// out -= sum_j c[j] V[j], c in device memory; x *= 1 / sqrt(*nrm2) with *nrm2 in device memory.
+hipError_t launch_project_out(const double* V, int nv, int64_t n, const double* c, double* out, hipStream_t s);
+hipError_t launch_scale_dev(double* x, const double* nrm2, int64_t n, hipStream_t s);
 // Tiled split-BF16 kernels (hpsi_lds.hip).
 hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).

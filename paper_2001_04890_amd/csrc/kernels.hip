@@ -542,11 +542,15 @@ hipError_t launch_diag(const DiagBlock* blocks, int n_blocks, const DiagTask* ta
 }
 
 // ------------------------------------------------------------------ Davidson vector kernels (FP64)
+// Dot products V[j] . w: the vector is cut into n_part chunks of kDotChunk elements; workgroup (b, g)
+// forms the partial sums of chunk b for vectors 8 g .. 8 g + 7 (w read once per element for all 8),
+// then one wavefront per vector adds the n_part partials. Fixed partition and order: deterministic.
+constexpr int kDotChunk = 1024;
+constexpr int kDotVecs = 8;
+
 int multidot_parts(int64_t n) {
-    int64_t p = (n + 8191) / 8192;
-    if (p < 1) p = 1;
-    if (p > 1024) p = 1024;
-    return (int)p;
+    int64_t p = (n + kDotChunk - 1) / kDotChunk;
+    return (int)(p < 1 ? 1 : p);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -554,37 +558,88 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// partial[j * n_part + block] = sum over the block's chunk of V[j] . w   (fixed order)
-__global__ void k_multidot(const double* __restrict__ V, int nv, int64_t n, const double* __restrict__ w,
-                           double* __restrict__ partial, int n_part) {
-    __shared__ double red[4];
-    const int64_t chunk = (n + n_part - 1) / n_part;
-    const int64_t lo = blockIdx.x * chunk;
-    const int64_t hi = lo + chunk < n ? lo + chunk : n;
-    for (int j = 0; j < nv; ++j) {
-        const double* __restrict__ v = V + (int64_t)j * n;
-        double s = 0.0;
-        for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += v[i] * w[i];
-        s = wave_sum(s);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) partial[(int64_t)j * n_part + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-        __syncthreads();
+// partial[j * n_part + b] = sum over chunk b of V[j] . w
+__global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, int nv, int64_t n,
+                                                  const double* __restrict__ w, double* __restrict__ partial,
+                                                  int n_part) {
+    __shared__ double red[4][kDotVecs];
+    const int64_t lo = (int64_t)blockIdx.x * kDotChunk;
+    const int64_t hi = lo + kDotChunk < n ? lo + kDotChunk : n;
+    const int j0 = blockIdx.y * kDotVecs;
+    const int nj = nv - j0 < kDotVecs ? nv - j0 : kDotVecs;
+    double acc[kDotVecs];
+#pragma unroll
+    for (int j = 0; j < kDotVecs; ++j) acc[j] = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < kDotVecs; ++j)
+            if (j < nj) acc[j] += V[(int64_t)(j0 + j) * n + i] * wi;
     }
+#pragma unroll
+    for (int j = 0; j < kDotVecs; ++j) {
+        const double v = wave_sum(acc[j]);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nj)
+        partial[(int64_t)(j0 + threadIdx.x) * n_part + blockIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-__global__ void k_multidot_finish(const double* __restrict__ partial, int n_part, int nv, double* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nv) return;
+// out[j] = sum_b partial[j * n_part + b]; one wavefront per vector
+__global__ void k_multidot_finish(const double* __restrict__ partial, int n_part, double* __restrict__ out) {
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < n_part; ++b) s += partial[(int64_t)j * n_part + b];
-    out[j] = s;
+    for (int b = threadIdx.x; b < n_part; b += 64) s += partial[(int64_t)j * n_part + b];
+    s = wave_sum(s);
+    if (threadIdx.x == 0) out[j] = s;
 }
 
 hipError_t launch_multidot(const double* V, int nv, int64_t n, const double* w, double* partial, int n_part,
                            double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_multidot, dim3(n_part), dim3(256), 0, s, V, nv, n, w, partial, n_part);
-    hipLaunchKernelGGL(k_multidot_finish, dim3((nv + 63) / 64), dim3(64), 0, s, partial, n_part, nv, out);
+    if (nv <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_multidot, dim3(n_part, (nv + kDotVecs - 1) / kDotVecs), dim3(256), 0, s, V, nv, n, w,
+                       partial, n_part);
+    hipLaunchKernelGGL(k_multidot_finish, dim3(nv), dim3(64), 0, s, partial, n_part, out);
+    return hipGetLastError();
+}
+
+// out -= sum_j c[j] V[j] with the coefficients in device memory (Gram-Schmidt step)
+__global__ void k_project_out(const double* __restrict__ V, int nv, int64_t n, const double* __restrict__ c,
+                              double* __restrict__ out) {
+    __shared__ double cs[kMaxCombine];
+    for (int j = threadIdx.x; j < nv; j += blockDim.x) cs[j] = c[j];
+    __syncthreads();
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int j = 0; j < nv; ++j) s += cs[j] * V[(int64_t)j * n + i];
+        out[i] -= s;
+    }
+}
+
+hipError_t launch_project_out(const double* V, int nv, int64_t n, const double* c, double* out, hipStream_t s) {
+    if (nv > kMaxCombine) return hipErrorInvalidValue;
+    if (nv <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_project_out, dim3((unsigned)blocks), dim3(256), 0, s, V, nv, n, c, out);
+    return hipGetLastError();
+}
+
+// x *= 1 / sqrt(*nrm2) (left unchanged when *nrm2 is not positive)
+__global__ void k_scale_dev(double* __restrict__ x, const double* __restrict__ nrm2, int64_t n) {
+    const double q = *nrm2;
+    if (!(q > 0.0)) return;
+    const double a = 1.0 / sqrt(q);
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] *= a;
+}
+
+hipError_t launch_scale_dev(double* x, const double* nrm2, int64_t n, hipStream_t s) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_scale_dev, dim3((unsigned)blocks), dim3(256), 0, s, x, nrm2, n);
     return hipGetLastError();
 }
 

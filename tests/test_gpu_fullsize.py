@@ -1,0 +1,65 @@
+"""Full-size GPU parity: the benchmark's H.psi workload (L = 24, N = 24 (12, 12), M = 1024 middle
+bond, synthetic block operators sigma = 1.5, seed 1; 844 psi blocks, 3366 combinations), built and
+launched exactly as bench.py times it (eager dmrg_hpsi on the caller's stream, and the captured
+graph), checked on sampled output blocks that the oracle computes target by target.
+
+Sample: the three largest blocks, the smallest, and four seeded random blocks. Bars: FP64 within
+1e-12 of the sample's max|y|, split within 5e-4; graph replays equal the eager launch bit for bit.
+"""
+import numpy as np
+import pytest
+
+from dmrg_inputs import random_vector
+from dmrg_inputs.synthetic import synthetic_problem
+from oracle.hpsi import OracleHop
+from helpers import rel_err
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+lib_mod = pytest.importorskip("paper_2001_04890_amd")
+Hop, PREC_FP64, PREC_SPLIT2 = lib_mod.Hop, lib_mod.PREC_FP64, lib_mod.PREC_SPLIT2
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+DEV = torch.device("cuda:0")
+L, NA, NB, M, SIGMA, SEED = 24, 12, 12, 1024, 1.5, 1
+
+
+@pytest.fixture(scope="module")
+def full():
+    h, eri, left, right, site = synthetic_problem(L, NA, NB, M, SIGMA, SEED)
+    print(f"[full] L={L} M={M}: building the GPU operator", flush=True)
+    stream = torch.cuda.current_stream()
+    hop = Hop(h, eri, left, right, NA, NB, site, device=0, want_split=True, stream=stream)
+    x = random_vector(hop.n_coeff, 7)
+    print("[full] oracle set-up (pre-summed operators of every combination)", flush=True)
+    oh = OracleHop(h, eri, left, right, NA, NB, site)
+    bl = oh.layout.blocks
+    order = sorted(range(len(bl)), key=lambda j: -bl[j][5] * bl[j][6])
+    rng = np.random.default_rng(11)
+    targets = sorted(set(order[:3]) | {order[-1]} | set(rng.choice(len(bl), size=4, replace=False).tolist()))
+    print(f"[full] oracle on targets {targets}", flush=True)
+    ref = oh.apply(x, targets=targets)
+    sl = [slice(bl[j][4], bl[j][4] + bl[j][5] * bl[j][6]) for j in targets]
+    return hop, stream, x, np.concatenate([ref[s] for s in sl]), sl
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", [PREC_FP64, PREC_SPLIT2])
+def test_full_size_sampled_blocks(full, prec):
+    hop, stream, x, ref, sl = full
+    xd = torch.as_tensor(x, device=DEV)
+    y = torch.empty_like(xd)
+    hop.hpsi(xd, y, prec, stream=stream)
+    torch.cuda.synchronize()
+    yh = y.cpu().numpy()
+    err = rel_err(np.concatenate([yh[s] for s in sl]), ref)
+    print(f"[full] prec {prec}: sampled rel err {err:.2e}", flush=True)
+    assert err < (1e-12 if prec == PREC_FP64 else 5e-4)
+    yg = torch.empty_like(xd)
+    for _ in range(2):
+        yg.fill_(float("nan"))
+        hop.hpsi_graph(xd, yg, prec, stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(yg, y)
