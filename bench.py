@@ -23,6 +23,12 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                        # GB/s
+# HBM traffic of one split H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the k_pack_xt / k_zero_lds / k_hpsi_lds /
+# k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
+# (factors read off a 1 GiB device copy in the same runs); summary and commands in
+# profiles/hpsi_split_L24_M1024_kernel_trace.md. Valid for that workload and these kernels only.
+SPLIT_TRAFFIC_L24_M1024 = {"fetch_bytes": 14856.3 * 2**20, "write_bytes": 375.6 * 2**20}
 
 
 def log(*a):
@@ -154,8 +160,12 @@ def main():
     # --- roofline of the dominant kernel: the split H.psi launch sequence (k_pack_xt, the LDS-staged
     #     k_hpsi_lds classes, the task-mode k_hpsi_small classes and the two k_reduce_lds launches)
     achieved = st["flops"] / tsp / 1e12
+    default_shape = (L, M, args.sigma, args.seed) == (24, 1024, 1.5, 1)
+    traffic = (SPLIT_TRAFFIC_L24_M1024["fetch_bytes"] + SPLIT_TRAFFIC_L24_M1024["write_bytes"]) if default_shape else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["bf16"], 5), "traffic": None,
+                "frac": round(achieved / PEAK["bf16"], 5), "traffic": traffic,
+                "traffic_note": "HBM bytes per split H.psi call (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
+                                "profiles/hpsi_split_L24_M1024_kernel_trace.md)" if traffic else None,
                 "kernel": "split H.psi sequence (k_hpsi_lds + k_hpsi_small + k_reduce_lds)",
                 "mfma_products_per_flop": 3,
                 "fp64_kernel": {"achieved": round(st["flops"] / t64 / 1e12, 3), "peak": PEAK["fp64"],

@@ -93,14 +93,17 @@ def op_list(side, orbitals, L, site):
 
 
 def synthetic_block(side, L, n_alpha, n_beta, site, M, sigma, seed, g=0.2, h_spread=6.0, eps=0.05,
-                    ops=None):
-    """Random-valued block with the operator structure of ``side`` at the bond (site, site+1)."""
+                    ops=None, dim_of=None):
+    """Random-valued block with the operator structure of ``side`` at the bond (site, site+1).
+    ``dim_of``: optional function (n_alpha, n_beta) -> sector dimension replacing the model's sizes."""
     orbitals = tuple(range(0, site)) if side == "left" else tuple(range(site + 2, L))
     k = len(orbitals)
     if k == 0:
         qn, dims = [(0, 0)], np.array([1], dtype=np.int32)
     else:
         qn, dims = sector_dims(k, n_alpha, n_beta, L, M, sigma)
+    if dim_of is not None:
+        dims = np.array([int(dim_of(*q)) for q in qn], dtype=np.int32)
     index = {q: i for i, q in enumerate(qn)}
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []

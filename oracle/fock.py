@@ -104,7 +104,7 @@ def exact_block(orbitals, side, t, w, outside):
     """
     k = len(orbitals)
     F = FockSpace(k)
-    base = 2 * orbitals[0]
+    base = 2 * orbitals[0] if k else 0    # a block with no orbitals (edge bond): the vacuum only
     modes = list(range(2 * k))            # local mode m <-> global spin-orbital base + m
     g = [base + m for m in modes]
     C = [F.c(m) for m in modes]
@@ -224,7 +224,7 @@ def _block_state_bits(block, sec, pos):
     """Global determinant bits of basis state ``pos`` of sector ``sec`` of an untruncated block."""
     F = block.fock
     local = int(F.sector_states[sec][pos])
-    return local << (2 * block.orbitals[0])
+    return local << (2 * block.orbitals[0]) if len(block.orbitals) else local
 
 
 _SITE_BITS = (0, 1, 2, 3)   # site basis (0, up, down, updown) -> bit pattern (alpha = bit 0, beta = bit 1)

@@ -7,11 +7,12 @@ from oracle.fock import exact_block, random_bases, truncate
 from oracle.hamiltonian import spin_orbital_integrals
 
 
-def exact_problem(L, seed, n_alpha=None, n_beta=None, trunc=None):
-    """Integrals + exact (optionally randomly truncated) middle-bond blocks from the oracle's Fock space."""
+def exact_problem(L, seed, n_alpha=None, n_beta=None, trunc=None, site=None):
+    """Integrals + exact (optionally randomly truncated) blocks from the oracle's Fock space at the
+    middle bond, or at the bond (site, site + 1) (0-based; site 0 and L - 2 leave a block empty)."""
     h, eri = random_integrals(L, seed)
     t, w = spin_orbital_integrals(h, eri)
-    s1 = L // 2 - 1
+    s1 = L // 2 - 1 if site is None else site
     s2 = s1 + 1
     left = exact_block(list(range(0, s1)), "left", t, w, [P for P in range(2 * L) if P // 2 >= s1])
     right = exact_block(list(range(s2 + 1, L)), "right", t, w, [P for P in range(2 * L) if P // 2 <= s2])

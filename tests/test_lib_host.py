@@ -60,10 +60,17 @@ def _exec_tasks(hop, left, right, x):
     return y
 
 
-@pytest.mark.parametrize("case", ["exact8", "trunc10_odd", "synth12"])
+@pytest.mark.parametrize("case", ["exact8", "trunc10_odd", "synth12", "edge4_left_empty", "edge6_right_empty",
+                                  "edge2_both_empty"])
 def test_host_task_list_matches_oracle(case):
     if case == "exact8":
         h, eri, left, right, na, nb, site = exact_problem(8, 0)
+    elif case == "edge4_left_empty":
+        h, eri, left, right, na, nb, site = exact_problem(4, 3, site=0)
+    elif case == "edge6_right_empty":
+        h, eri, left, right, na, nb, site = exact_problem(6, 3, site=4)
+    elif case == "edge2_both_empty":
+        h, eri, left, right, na, nb, site = exact_problem(2, 3, n_alpha=1, n_beta=1, site=0)
     elif case == "trunc10_odd":
         h, eri, left, right, na, nb, site = exact_problem(10, 1, n_alpha=5, n_beta=4, trunc=40)
     else:
@@ -74,7 +81,9 @@ def test_host_task_list_matches_oracle(case):
     x = random_vector(hop.n_coeff, 3)
     assert rel_err(_exec_tasks(hop, left, right, x), oh.apply(x)) < 1e-12
     st = hop.stats()
-    assert st["n_alpha"] > 0 and st["n_tasks"] > 0 and st["flops"] > 0
+    assert st["n_alpha"] > 0 and st["n_tasks"] > 0
+    # with both blocks empty every task is a site-only scaling (identity on both sides): no GEMM flops
+    assert (st["flops"] == 0) if case == "edge2_both_empty" else (st["flops"] > 0)
 
 
 def test_host_only_handle_refuses_compute():

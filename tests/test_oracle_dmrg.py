@@ -87,6 +87,24 @@ def test_hpsi_equals_fci_exact_blocks_L10():
     assert np.abs(hop.apply(x) - yref).max() < 1e-12 * np.abs(yref).max()
 
 
+@pytest.mark.parametrize("L,s1,na,nb", [(2, 0, 1, 1), (4, 0, 2, 2), (4, 2, 2, 2), (5, 0, 3, 2), (6, 4, 3, 3)])
+def test_hpsi_equals_fci_edge_bonds(L, s1, na, nb):
+    """Edge bonds: a block with no orbitals holds only the vacuum (one sector of dimension 1), so the
+    superblock is still the whole FCI space."""
+    h, eri = random_integrals(L, 3)
+    t, w = spin_orbital_integrals(h, eri)
+    s2 = s1 + 1
+    left = exact_block(list(range(0, s1)), "left", t, w, [P for P in range(2 * L) if P // 2 >= s1])
+    right = exact_block(list(range(s2 + 1, L)), "right", t, w, [P for P in range(2 * L) if P // 2 <= s2])
+    hop = OracleHop(h, eri, left, right, na, nb, s1)
+    fci = FCI(h, eri, na, nb)
+    assert hop.layout.size == fci.dim
+    x = random_vector(hop.layout.size, 5)
+    X = embed(hop.layout, x, left, right, s1, s2, fci.dets)
+    yref = project(hop.layout, fci.matvec(X), left, right, s1, s2, fci.dets)
+    assert np.abs(hop.apply(x) - yref).max() < 1e-12 * np.abs(yref).max()
+
+
 def test_hpsi_projected_fci_truncated_blocks():
     """Truncated bases: H_sb = P^T H_FCI P with P the isometric embedding (Section 2.1, Eq. h_mat)."""
     h, eri, left, right, s1, s2 = middle_bond_blocks(8, 2, trunc=24)
