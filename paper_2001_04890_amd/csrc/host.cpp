@@ -1433,6 +1433,17 @@ void make_tiled_split(dmrg_hop& H, hipStream_t s) {
 void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
     HIPCHK(hipSetDevice(H.device));
+    // DMRG_BUILD_TRACE=1: synchronize after each phase and print its wall time
+    const char* bt = std::getenv("DMRG_BUILD_TRACE");
+    const bool btrace = bt && bt[0] == '1';
+    double bt0 = now();
+    auto phase = [&](const char* name) {
+        if (!btrace) return;
+        HIPCHK(hipStreamSynchronize(s));
+        const double t = now();
+        std::fprintf(stderr, "[dmrg build] %-28s %8.3f s\n", name, t - bt0);
+        bt0 = t;
+    };
     // 1. pool layout: every stored block of both sides (padded rows), then derived matrices
     std::vector<int64_t> base_off[2];
     int64_t pool = 0;
@@ -1491,20 +1502,72 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
         throw Error(DMRG_ERR_NOMEM, "operator pool exceeds the memory budget");
     H.d_pool = dev_alloc<double>(H, pool);
     HIPCHK(hipMemsetAsync(H.d_pool, 0, pool * sizeof(double), s));
-    // 2. stored blocks, padded, host -> device (staged per side)
-    for (int sd = 0; sd < 2; ++sd) {
-        BlockIn& B = sd == 0 ? H.left : H.right;
-        for (size_t k = 0; k < B.ops.size(); ++k)
-            for (int si = 0; si < B.n_sec; ++si) {
-                int so = B.ops[k].out_of_in[si];
-                if (so < 0) continue;
-                int rows = B.dim[so], cols = B.dim[si];
-                if (rows == 0 || cols == 0) continue;
-                HIPCHK(hipMemcpy2DAsync(H.d_pool + base_off[sd][k * B.n_sec + si], dmrg::ld_of(cols) * sizeof(double),
-                                        B.data + B.ops[k].off_of_in[si], cols * sizeof(double),
-                                        cols * sizeof(double), rows, hipMemcpyHostToDevice, s));
+    phase("pool layout + alloc");
+    // 2. stored blocks, padded, host -> device: packed on the host into the pool layout inside pinned
+    //    staging chunks (two, alternating, ~256 MB or one block if larger), one copy per chunk
+    {
+        struct Src { int64_t off; const double* src; int rows, cols; };
+        std::vector<Src> blocks;
+        for (int sd = 0; sd < 2; ++sd) {
+            BlockIn& B = sd == 0 ? H.left : H.right;
+            for (size_t k = 0; k < B.ops.size(); ++k)
+                for (int si = 0; si < B.n_sec; ++si) {
+                    int so = B.ops[k].out_of_in[si];
+                    if (so < 0) continue;
+                    int rows = B.dim[so], cols = B.dim[si];
+                    if (rows == 0 || cols == 0) continue;
+                    blocks.push_back({base_off[sd][k * B.n_sec + si], B.data + B.ops[k].off_of_in[si], rows, cols});
+                }
+        }
+        std::sort(blocks.begin(), blocks.end(), [](const Src& a, const Src& b) { return a.off < b.off; });
+        auto extent = [](const Src& b) { return (int64_t)dmrg::rows_of(b.rows) * dmrg::ld_of(b.cols); };
+        int64_t cap = (int64_t)32 << 20;                       // doubles per staging chunk
+        for (const Src& b : blocks) cap = std::max(cap, extent(b));
+        if (!blocks.empty()) cap = std::min(cap, std::max(blocks.back().off + extent(blocks.back()), (int64_t)1));
+        double* stage[2] = {nullptr, nullptr};
+        hipEvent_t done[2] = {nullptr, nullptr};
+        bool used[2] = {false, false};
+        try {
+            for (int b = 0; b < 2 && !blocks.empty(); ++b) {
+                HIPCHK(hipHostMalloc((void**)&stage[b], (size_t)cap * sizeof(double), hipHostMallocDefault));
+                HIPCHK(hipEventCreateWithFlags(&done[b], hipEventDisableTiming));
             }
+            size_t i = 0;
+            for (int slot = 0; i < blocks.size(); slot ^= 1) {
+                const int64_t c0 = blocks[i].off;
+                size_t e = i;
+                while (e < blocks.size() && blocks[e].off + extent(blocks[e]) - c0 <= cap) ++e;
+                const int64_t len = blocks[e - 1].off + extent(blocks[e - 1]) - c0;
+                if (used[slot]) HIPCHK(hipEventSynchronize(done[slot]));   // the copy out of this buffer is done
+                double* st = stage[slot];
+                std::memset(st, 0, (size_t)len * sizeof(double));
+                for (size_t q = i; q < e; ++q) {
+                    const Src& b = blocks[q];
+                    const int ld = dmrg::ld_of(b.cols);
+                    for (int r = 0; r < b.rows; ++r)
+                        std::memcpy(st + (b.off - c0) + (int64_t)r * ld, b.src + (int64_t)r * b.cols,
+                                    (size_t)b.cols * sizeof(double));
+                }
+                HIPCHK(hipMemcpyAsync(H.d_pool + c0, st, (size_t)len * sizeof(double), hipMemcpyHostToDevice, s));
+                HIPCHK(hipEventRecord(done[slot], s));
+                used[slot] = true;
+                i = e;
+            }
+            HIPCHK(hipStreamSynchronize(s));
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            for (int b = 0; b < 2; ++b) {
+                if (stage[b]) (void)hipHostFree(stage[b]);
+                if (done[b]) (void)hipEventDestroy(done[b]);
+            }
+            throw;
+        }
+        for (int b = 0; b < 2; ++b) {
+            if (stage[b]) (void)hipHostFree(stage[b]);
+            if (done[b]) (void)hipEventDestroy(done[b]);
+        }
     }
+    phase("operator upload");
     // 3. pre-summed and transposed matrices on the GPU (Section 2.2.3)
     if (!pblocks.empty()) {
         dmrg::PresumBlock* d_pb = dev_alloc<dmrg::PresumBlock>(H, pblocks.size());
@@ -1513,6 +1576,7 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
         HIPCHK(hipMemcpyAsync(d_pt, pterms.data(), pterms.size() * sizeof(pterms[0]), hipMemcpyHostToDevice, s));
         HIPCHK(dmrg::launch_presum(d_pb, (int)pblocks.size(), d_pt, H.d_pool, s));
     }
+    phase("pre-summation");
     // 4. split copies: tiled hi/lo for the LDS-staged kernel; row-major hi/lo only when some target
     //    needs the one-wave kernel
     if (H.has_split) {
@@ -1523,8 +1587,10 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
             HIPCHK(dmrg::launch_split(H.d_pool, pool, H.d_hi, H.d_lo, s));
         }
     }
+    phase("split tiling");
     // 5. packed input layout, work items and launch plan
     build_plan(H, s);
+    phase("launch plans");
     // 7. diag(H): tasks mapping a block onto itself (host staging vectors live until the final sync)
     std::vector<dmrg::DiagBlock> db;
     std::vector<dmrg::DiagTask> dt;
@@ -1565,6 +1631,7 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     }
     H.bytes = by;
     HIPCHK(hipStreamSynchronize(s));
+    phase("diag(H) + byte count");
 }
 
 dmrg_status fail(const Error& e) { g_err = e.what(); return e.code; }
