@@ -219,6 +219,15 @@ dmrg_status dmrg_davidson(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts,
  * combined handle solves the direct-sum problem (its lowest eigenpair over all parts). */
 dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out);
 
+/* Release the parts of a built handle that only its own H.psi uses — launch plans, cached graphs,
+ * the tiled split and tiled FP64 operator copies — keeping the FP64 operator pool, diag(H) and the
+ * host-side description that dmrg_hop_combine reads: for callers that merge many handles and need
+ * the memory for the merged one. Waits for all work on the device (hipDeviceSynchronize) before
+ * freeing. Afterwards the handle can be combined, queried (layout, stats, parts, diagonal) and
+ * freed; dmrg_hpsi, dmrg_hpsi_graph, dmrg_davidson and dmrg_hop_autotune return
+ * DMRG_ERR_UNSUPPORTED. Trimming a trimmed or host-only handle does nothing. */
+dmrg_status dmrg_hop_trim(dmrg_hop* hop);
+
 /* Number of merged problems and their first coefficient offsets (n_parts + 1 entries, the last is
  * n_coeff). A handle from dmrg_build_blocks has one part. */
 dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first_coeff);

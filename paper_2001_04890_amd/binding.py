@@ -85,6 +85,8 @@ lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, 
 lib.dmrg_hop_export_tasks.restype = C.c_int32
 lib.dmrg_hop_combine.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
 lib.dmrg_hop_combine.restype = C.c_int32
+lib.dmrg_hop_trim.argtypes = [C.c_void_p]
+lib.dmrg_hop_trim.restype = C.c_int32
 lib.dmrg_hop_parts.argtypes = [C.c_void_p, i32p, i64p]
 lib.dmrg_hop_parts.restype = C.c_int32
 lib.dmrg_hop_autotune.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, i32p, f64p]
@@ -222,6 +224,10 @@ class Hop:
         first = np.zeros(npart.value + 1, dtype=np.int64)
         _check(lib.dmrg_hop_parts(handle, None, _ptr(first, C.c_int64)))
         self.part_coeff = first
+
+    def trim(self):
+        """Release plans and tiled operator copies; the handle can then only be combined or queried."""
+        _check(lib.dmrg_hop_trim(self._h))
 
     def autotune(self, precision=PREC_SPLIT2, reps=3, stream=None):
         """Pick the fastest H.psi launch plan (dmrg_hop_autotune); returns (tile width, items, order, ms)."""

@@ -250,6 +250,9 @@ struct dmrg_hop {
     std::vector<dmrg::BigChunk> big_chunks64;
     double* xt64 = nullptr;                     // FP64 tiled X^T of one vector (plan allocation)
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
+    int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)
+    int vec_step = 1;                      // vectors per launch sequence (packed-input and partial buffers)
+    bool trimmed = false;                  // dmrg_hop_trim: plans and derived operator copies released
     int64_t n_alpha = 0;
     int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
     std::vector<int64_t> part_coeff;       // first coefficient of each merged problem (+ end)
@@ -628,6 +631,7 @@ T* dev_alloc(dmrg_hop& H, size_t n) {
     if (n == 0) n = 1;
     HIPCHK(hipMalloc(&p, n * sizeof(T)));
     H.allocations.push_back(p);
+    H.dev_bytes += (int64_t)(n * sizeof(T));
     return static_cast<T*>(p);
 }
 
@@ -637,6 +641,7 @@ T* plan_alloc(dmrg_hop& H, size_t n) {
     if (n == 0) n = 1;
     HIPCHK(hipMalloc(&p, n * sizeof(T)));
     H.plan_allocations.push_back(p);
+    H.plan_bytes += (int64_t)(n * sizeof(T));
     return static_cast<T*>(p);
 }
 
@@ -873,19 +878,19 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
     plan.items = d_items;
     plan.reduces = d_red;
     plan.tasks = d_tasks;
-    plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1) * dmrg::kPartialVecs);
+    plan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part_max, 1) * H.vec_step);
     plan.partial_size = part_max;
     plan.launches = launches_out.data();
     plan.phases = phases_out.data();
     plan.packs = d_packs;
     plan.n_packs = (int)packs.size();
     plan.packed_size = psize;
-    plan.xp = plan_alloc<double>(H, (size_t)psize * dmrg::kPartialVecs);
+    plan.xp = plan_alloc<double>(H, (size_t)psize * H.vec_step);
     if (split_bufs) {
-        plan.xr_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        plan.xr_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        plan.xt_hi = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
-        plan.xt_lo = plan_alloc<uint16_t>(H, (size_t)psize * dmrg::kPartialVecs);
+        plan.xr_hi = plan_alloc<uint16_t>(H, (size_t)psize * H.vec_step);
+        plan.xr_lo = plan_alloc<uint16_t>(H, (size_t)psize * H.vec_step);
+        plan.xt_hi = plan_alloc<uint16_t>(H, (size_t)psize * H.vec_step);
+        plan.xt_lo = plan_alloc<uint16_t>(H, (size_t)psize * H.vec_step);
     }
     HIPCHK(hipStreamSynchronize(s));
 }
@@ -1117,11 +1122,11 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     H.lplan.reduces = d_red;
 
     H.lplan.partial_size = part;
-    H.lplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1) * dmrg::kPartialVecs);
+    H.lplan.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1) * H.vec_step);
     H.lplan.packs = d_packs;
     H.lplan.n_packs = (int)packs.size();
     H.lplan.xt_size = 2 * psize;
-    H.lplan.xt = plan_alloc<uint16_t>(H, (size_t)2 * psize * dmrg::kPartialVecs);
+    H.lplan.xt = plan_alloc<uint16_t>(H, (size_t)2 * psize * H.vec_step);
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds plan] items %zu row classes", items.size());
@@ -1354,6 +1359,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     drop_graphs(H);
     for (void* p : H.plan_allocations) (void)hipFree(p);
     H.plan_allocations.clear();
+    H.plan_bytes = 0;
     // FP64: targets above the LDS stage size take the two-pass path, the others the one-wave kernel
     H.bplan64 = dmrg::BigPlan{};
     H.big_chunks64.clear();
@@ -1632,6 +1638,8 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
     H.bytes = by;
     HIPCHK(hipStreamSynchronize(s));
     phase("diag(H) + byte count");
+    if (btrace) std::fprintf(stderr, "[dmrg build] device memory: %.1f MB data + %.1f MB plans\n", H.dev_bytes * 1e-6,
+                             H.plan_bytes * 1e-6);
 }
 
 dmrg_status fail(const Error& e) { g_err = e.what(); return e.code; }
@@ -1689,6 +1697,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_TBUDGET_MB")) H->tune_big_tbudget_mb = std::max(16, std::atoi(e));
@@ -1790,6 +1799,7 @@ namespace {
 void check_hpsi_args(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision) {
     if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
     if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+    if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim): it can only be combined");
     if (!x || !y || nvec < 1) throw Error(DMRG_ERR_ARG, "bad x/y/nvec");
     int64_t n = H->n_coeff * nvec;
     if (!(x + n <= y || y + n <= x)) throw Error(DMRG_ERR_ALIAS, "x and y overlap");
@@ -1800,7 +1810,7 @@ void check_hpsi_args(dmrg_hop* H, const double* x, double* y, int32_t nvec, int3
 
 // The launch sequence of one H.psi (no host synchronization, so it can be captured).
 void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s) {
-    const int step = dmrg::kPartialVecs;   // packed-input and partial buffers hold this many vectors
+    const int step = H->vec_step;   // packed-input and partial buffers hold this many vectors
     for (int v0 = 0; v0 < nvec; v0 += step) {
         const int nv = std::min(step, nvec - v0);
         const double* xv = x + (int64_t)v0 * H->n_coeff;
@@ -1960,6 +1970,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
             }
         }
         C->tune_big64 = hops[0]->tune_big64;
+        C->vec_step = hops[0]->vec_step;
         build_plan(*C, s);
         *out = C;
         return DMRG_OK;
@@ -1984,6 +1995,48 @@ extern "C" dmrg_status dmrg_hop_parts(const dmrg_hop* H, int32_t* n_parts, int64
 
 // Autotuner: times the H.psi launch plan for candidate (widest tile, work items, launch order)
 // settings on the device and keeps the fastest.
+// Release everything of a handle that only H.psi needs (launch plans, graphs, tiled operator
+// copies), keeping the FP64 pool, diag(H) and the host description, which dmrg_hop_combine reads.
+extern "C" dmrg_status dmrg_hop_trim(dmrg_hop* H) {
+    g_err.clear();
+    try {
+        if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
+        if (H->device < 0 || H->trimmed) return DMRG_OK;
+        HIPCHK(hipSetDevice(H->device));
+        HIPCHK(hipDeviceSynchronize());   // no kernel of this handle may still be reading what is freed
+        drop_graphs(*H);
+        for (void* p : H->plan_allocations) (void)hipFree(p);
+        H->plan_allocations.clear();
+        H->plan_bytes = 0;
+        H->plan = dmrg::HpsiPlan{};
+        H->plan_fb = dmrg::HpsiPlan{};
+        H->lplan = dmrg::LdsPlan{};
+        H->bplan = dmrg::BigPlan{};
+        H->bplan64 = dmrg::BigPlan{};
+        H->launches.clear(); H->phases.clear(); H->launches_fb.clear(); H->phases_fb.clear();
+        H->big_chunks.clear(); H->big_chunks64.clear();
+        H->n_fallback_targets = 0;
+        H->xt64 = nullptr;
+        auto release = [&](void* p, int64_t bytes) {
+            if (!p) return;
+            auto it = std::find(H->allocations.begin(), H->allocations.end(), p);
+            if (it != H->allocations.end()) H->allocations.erase(it);
+            (void)hipFree(p);
+            H->dev_bytes -= bytes;
+        };
+        release(H->d_tiled, H->tiled_size * (int64_t)sizeof(uint16_t));
+        release(H->d_tiled64, H->tiled64_size * (int64_t)sizeof(double));
+        release(H->d_hi, H->pool_size * (int64_t)sizeof(uint16_t));
+        release(H->d_lo, H->pool_size * (int64_t)sizeof(uint16_t));
+        H->d_tiled = nullptr; H->d_tiled64 = nullptr; H->d_hi = nullptr; H->d_lo = nullptr;
+        H->tiled_size = H->tiled64_size = 0;
+        H->trimmed = true;
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
 extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t reps, void* stream,
                                          int32_t* chosen, double* best_ms) {
     g_err.clear();
@@ -1992,6 +2045,7 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
     try {
         if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
         if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
         if (reps < 1) reps = 3;
         HIPCHK(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)stream;
@@ -2129,6 +2183,7 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
     try {
         if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
         if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
         if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
         if (o->use_graph != 0 && o->use_graph != 1) throw Error(DMRG_ERR_ARG, "use_graph must be 0 or 1");
         if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");

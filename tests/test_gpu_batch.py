@@ -87,3 +87,30 @@ def test_autotune_keeps_results(batch):
     print(f"[autotune] tile width {tq} items {items} order {order}: {ms:.3f} ms")
     assert tq == 0 and items in (4096, 8192, 16384, 32768) and order in (0, 1) and ms > 0
     assert rel_err(_run(comb, x, PREC_SPLIT2), before) < BAR[PREC_SPLIT2]
+
+
+def test_trimmed_handles_combine_to_the_same_result():
+    """dmrg_hop_trim keeps what merging needs: a merge of trimmed handles equals the merge of the
+    untrimmed ones bit for bit, and a trimmed handle refuses H.psi (DMRG_ERR_UNSUPPORTED)."""
+    ps = [synth(12, 60, 1.1, 300), synth(11, 40, 0.9, 301), synth(13, 90, 1.3, 302)]
+    full = [Hop(*p, device=0, want_split=True) for p in ps]
+    ref = Hop.combine(full)
+    parts = [Hop(*p, device=0, want_split=True) for p in ps]
+    xs = [random_vector(h.n_coeff, 70 + k) for k, h in enumerate(parts)]
+    for h in parts:
+        h.trim()
+        h.trim()                                   # trimming twice does nothing
+    with pytest.raises(lib_mod.DmrgError) as e:
+        _run(parts[0], xs[0], PREC_FP64)
+    assert e.value.status == -7
+    comb = Hop.combine(parts)
+    x = np.concatenate(xs)
+    for prec in (PREC_FP64, PREC_SPLIT2):
+        assert np.array_equal(_run(comb, x, prec), _run(ref, x, prec))
+    d = torch.empty(parts[1].n_coeff, dtype=torch.float64, device=DEV)
+    parts[1].diagonal(d)                           # diag(H) survives the trim
+    torch.cuda.synchronize()
+    d_ref = torch.empty_like(d)
+    full[1].diagonal(d_ref)
+    torch.cuda.synchronize()
+    assert torch.equal(d, d_ref)
