@@ -207,19 +207,21 @@ __global__ __launch_bounds__(kLdsWaves * 64) void k_hpsi_lds(const Item* __restr
         }
 
     u16x8 ah[TP][KS], al[TP][KS];
+    // Branch-free: a fragment outside the block (k tile >= pa32, or a row tile past the target) is
+    // loaded from tile (0, 0) of the same block instead and never used for a stored result (the
+    // GEMMs skip k tiles >= pa32; rows past the target are not stored). A conditional load merged
+    // with a zero fragment would make the compiler wait for the load right away, which would
+    // serialize this prefetch of the next task with the current task's GEMMs.
     auto load_a = [&](const TD T, u16x8 (&h)[TP][KS], u16x8 (&l)[TP][KS]) {
 #pragma unroll
         for (int p = 0; p < TP; ++p)
 #pragma unroll
             for (int kt = 0; kt < KS; ++kt) {
-                if (kt < T.pa32 && rt0 + p < nrt) {
-                    const uint16_t* src = pool_t + T.a + (int64_t)((rt0 + p) * T.pa32 + kt) * kTileU16 + lane * 8;
-                    h[p][kt] = gld8(src);
-                    l[p][kt] = gld8(src + 512);
-                } else {
-                    h[p][kt] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                    l[p][kt] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                }
+                const bool in = kt < T.pa32 && rt0 + p < nrt;
+                const int64_t tile = in ? (int64_t)((rt0 + p) * T.pa32 + kt) : 0;
+                const uint16_t* src = pool_t + T.a + tile * kTileU16 + lane * 8;
+                h[p][kt] = gld8(src);
+                l[p][kt] = gld8(src + 512);
             }
     };
     auto stage = [&](const TD T, int st, int xsl, bool load_x) {
@@ -370,38 +372,29 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
     // operand fragments of one task: A rows, X^T (two halves), B rows; hi and lo
     u16x8 ah[NR], al[NR], xh[2], xl[2], bh[NQ], bl[NQ];
     u16x8 nah[NR], nal[NR], nxh[2], nxl[2], nbh[NQ], nbl[NQ];
-    auto load = [&](const TD T, bool new_x, u16x8 (&fah)[NR], u16x8 (&fal)[NR], u16x8 (&fxh)[2], u16x8 (&fxl)[2],
+    // Branch-free loads (a conditional load merged with a zero or kept fragment makes the compiler
+    // wait for it at once, serializing the prefetch of task t+1 with task t): row tiles past the
+    // target and column tiles past tq read the block's first tile instead and are never stored; the
+    // X^T fragments are re-read even when the source is unchanged (a cache hit).
+    auto load = [&](const TD T, u16x8 (&fah)[NR], u16x8 (&fal)[NR], u16x8 (&fxh)[2], u16x8 (&fxl)[2],
                     u16x8 (&fbh)[NQ], u16x8 (&fbl)[NQ]) {
-        const u16x8 z = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int p = 0; p < NR; ++p) {
-            if (p < nr) {
-                const uint16_t* src = pool_t + T.a + (int64_t)(rt0 + p) * kTileU16 + lane * 8;
-                fah[p] = gld8(src);
-                fal[p] = gld8(src + 512);
-            } else {
-                fah[p] = z;
-                fal[p] = z;
-            }
+            const uint16_t* src = pool_t + T.a + (int64_t)(p < nr ? rt0 + p : rt0) * kTileU16 + lane * 8;
+            fah[p] = gld8(src);
+            fal[p] = gld8(src + 512);
         }
-        if (new_x) {   // else the X^T fragments of the previous task (same source) are kept
 #pragma unroll
-            for (int h2 = 0; h2 < 2; ++h2) {
-                const uint16_t* src = xt + T.x + h2 * kTileU16 + lane * 8;
-                fxh[h2] = gld8(src);
-                fxl[h2] = gld8(src + 512);
-            }
+        for (int h2 = 0; h2 < 2; ++h2) {
+            const uint16_t* src = xt + T.x + h2 * kTileU16 + lane * 8;
+            fxh[h2] = gld8(src);
+            fxl[h2] = gld8(src + 512);
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            if (q < tq) {
-                const uint16_t* src = pool_t + T.b + (int64_t)(qt0 + q) * kTileU16 + lane * 8;
-                fbh[q] = gld8(src);
-                fbl[q] = gld8(src + 512);
-            } else {
-                fbh[q] = z;
-                fbl[q] = z;
-            }
+            const uint16_t* src = pool_t + T.b + (int64_t)(q < tq ? qt0 + q : qt0) * kTileU16 + lane * 8;
+            fbh[q] = gld8(src);
+            fbl[q] = gld8(src + 512);
         }
     };
 
@@ -443,19 +436,16 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
     int t = I.t_begin;
     TD T = load_td(tasks + t);
     TD Tn = t + 1 < I.t_end ? load_td(tasks + t + 1) : T;
-    load(T, true, ah, al, xh, xl, bh, bl);
+    load(T, ah, al, xh, xl, bh, bl);
+    // nothing outstanding at the loop head: the first task's fragments are complete here, and each
+    // iteration's prefetch completes at its end (the copies into the current-task registers), so the
+    // compiler's wait analysis lets this task's GEMMs run while the next task's loads are in flight
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0) expcnt(7) lgkmcnt(15)
     int since_flush = 0;
     for (;;) {
         const bool has_next = t + 1 < I.t_end;
         const TD Tnn = t + 2 < I.t_end ? load_td(tasks + t + 2) : Tn;
-        if (has_next) {
-            const bool new_x = Tn.x != T.x;
-            if (!new_x) {
-#pragma unroll
-                for (int h2 = 0; h2 < 2; ++h2) { nxh[h2] = xh[h2]; nxl[h2] = xl[h2]; }
-            }
-            load(Tn, new_x, nah, nal, nxh, nxl, nbh, nbl);
-        }
+        if (has_next) load(Tn, nah, nal, nxh, nxl, nbh, nbl);
         // GEMM1: T'^T (32 x 16 per row tile) = X^T A(rows)^T, one k step (K = 32)
         f32x4 tt[2][NR];
 #pragma unroll
