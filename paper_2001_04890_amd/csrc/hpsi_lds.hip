@@ -170,8 +170,12 @@ __global__ void k_pack_xt(const PackBlock* __restrict__ packs, const double* __r
 // ------------------------------------------------------------------ the sector-GEMM kernel
 // S: largest padded dimension of the class (LDS stage size), TP: row tiles per wave. The item's
 // column tile count tq = ceil((m_d' - c0) / 16) <= S / 16 is a runtime bound of unrolled loops.
-template <int S, int TP>
-__global__ __launch_bounds__(kLdsWaves * 64) void k_hpsi_lds(const Item* __restrict__ items,
+// PF = 1: one more wavefront per workgroup touches, during task t, the cache lines of the operands
+// of task t+2 (X^T if its source changes, B, and the workgroup's A rows) with loads into a scratch
+// LDS word that nobody reads; it never waits for them, so the LDS copies of task t+2, issued by the
+// compute waves one task later, find their lines in L2.
+template <int S, int TP, int PF>
+__global__ __launch_bounds__(kLdsWaves * 64 + PF * 64) void k_hpsi_lds(const Item* __restrict__ items,
                                                              const LTask* __restrict__ tasks,
                                                              const uint16_t* __restrict__ pool_t,
                                                              const uint16_t* __restrict__ xtall,
@@ -181,7 +185,7 @@ __global__ __launch_bounds__(kLdsWaves * 64) void k_hpsi_lds(const Item* __restr
     constexpr int QS = S / 16;          // max column tiles of the target
     constexpr int XS = KS * 2 * KS * kTileU16;
     constexpr int BS = QS * KS * kTileU16;
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * XS + 2 * BS];
+    __shared__ __attribute__((aligned(16))) uint16_t lds[2 * XS + 2 * BS + PF * 128];   // + touch target
 
     const ID I = load_item(items + blockIdx.x);
     const uint16_t* __restrict__ xt = xtall + (int64_t)blockIdx.y * xt_size;
@@ -194,6 +198,49 @@ __global__ __launch_bounds__(kLdsWaves * 64) void k_hpsi_lds(const Item* __restr
     const int qt0 = I.c0 >> 4;
     const int tq = min(QS, ((I.m_dp - I.c0) + 15) >> 4);
     const bool active = rt0 < nrt;
+
+    if constexpr (PF == 1) {
+        if (wave == kLdsWaves) {
+            const int rtw0 = I.r0 >> 4;
+            const int nrow = min(kLdsWaves * TP, nrt - rtw0);     // row tiles of the workgroup
+            auto touch = [&](const TD P, bool with_x) {
+                const int nxl = with_x ? P.pd32 * P.pa32 * 32 : 0;                 // 128-byte lines
+                const int nbl = tq * P.pd32 * 16;
+                const int n = nxl + nbl + nrow * P.pa32 * 16;
+                const uint16_t* xb = xt + P.x;
+                const uint16_t* bb = pool_t + P.b + (int64_t)qt0 * P.pd32 * kTileU16;
+                const uint16_t* ab = pool_t + P.a + (int64_t)rtw0 * P.pa32 * kTileU16;
+                for (int l0 = 0; l0 < n; l0 += 64) {
+                    const int l = min(l0 + lane, n - 1);
+                    const uint16_t* src = l < nxl ? xb + (int64_t)l * 64
+                                        : l < nxl + nbl ? bb + (int64_t)(l - nxl) * 64
+                                                        : ab + (int64_t)(l - nxl - nbl) * 64;
+                    __builtin_amdgcn_global_load_lds((const void*)src, (lds_ptr_t)(lds + 2 * XS + 2 * BS), 4, 0, 0);
+                }
+            };
+            // one barrier before the loop and one per task, as the compute waves
+            int t = I.t_begin;
+            TD Pp = load_td(tasks + t);
+            if (t + 1 < I.t_end) {
+                const TD P1 = load_td(tasks + t + 1);
+                touch(P1, P1.x != Pp.x);
+                Pp = P1;
+            }
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            for (; t < I.t_end; ++t) {
+                if (t + 2 < I.t_end) {
+                    const TD P2 = load_td(tasks + t + 2);
+                    touch(P2, P2.x != Pp.x);
+                    Pp = P2;
+                }
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_barrier();
+            }
+            wait_vm();   // the touches land in LDS: all of them before the wave ends
+            return;
+        }
+    }
 
     f32x4 c32[TP][QS];
     double acc[TP][QS][4];
@@ -524,16 +571,31 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
     for (int c = 0; c < kLdsClasses; ++c) {
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
         if (n <= 0) continue;
-        const dim3 grid(n, nvec), block(kLdsWaves * 64);
+        const dim3 grid(n, nvec), block(kLdsWaves * 64), block_pf(kLdsWaves * 64 + 64);
+        const bool pf = (P.prefetch_mask >> c) & 1;
         switch (c) {
-            case 0: hipLaunchKernelGGL((k_hpsi_lds<64, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
-                                       P.partial, n_coeff, P.xt_size, ss); break;
-            case 1: hipLaunchKernelGGL((k_hpsi_lds<64, 2>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
-                                       P.partial, n_coeff, P.xt_size, ss); break;
-            case 2: hipLaunchKernelGGL((k_hpsi_lds<96, 1>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
-                                       P.partial, n_coeff, P.xt_size, ss); break;
-            default: hipLaunchKernelGGL((k_hpsi_lds<96, 2>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
-                                        P.partial, n_coeff, P.xt_size, ss); break;
+            case 0:
+                if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else hipLaunchKernelGGL((k_hpsi_lds<64, 1, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
+                                        y, P.partial, n_coeff, P.xt_size, ss);
+                break;
+            case 1:
+                if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 2, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else hipLaunchKernelGGL((k_hpsi_lds<64, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
+                                        y, P.partial, n_coeff, P.xt_size, ss);
+                break;
+            case 2:
+                if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else hipLaunchKernelGGL((k_hpsi_lds<96, 1, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
+                                        y, P.partial, n_coeff, P.xt_size, ss);
+                break;
+            default:   // no prefetch variant: with a fifth wavefront its registers would spill
+                hipLaunchKernelGGL((k_hpsi_lds<96, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
+                                   P.partial, n_coeff, P.xt_size, ss);
+                break;
         }
     }
     for (int c = 0; c < kSmallClasses; ++c) {

@@ -168,6 +168,10 @@ struct LdsPlan {
     int n_packs = 0;
     int64_t xt_size = 0;                // u16 elements of one tiled X^T vector (2 * packed_size)
     uint16_t* xt = nullptr;             // device, xt_size * kPartialVecs
+    int prefetch_mask = 0x4;            // row-mode classes (bit c) whose workgroups get a cache-line
+                                        // prefetch wavefront: (96,1) (one workgroup per CU anyway);
+                                        // the S = 64 classes would lose their second workgroup per
+                                        // CU (measured slower), (96,2) would spill
 };
 
 // ---------------------------------------------------------------- large blocks (hpsi_big.hip)
