@@ -52,9 +52,10 @@ typedef __attribute__((address_space(3))) void* lds_ptr_t;
 
 // Copy n16 16-byte chunks (a multiple of 64) from global src to LDS dst, spread over the workgroup's
 // waves; each wave instruction moves 64 consecutive chunks (lane i -> dst + 16 i).
+template <int NW = kLdsWaves>
 __device__ __forceinline__ void copy_to_lds(const uint16_t* __restrict__ src, uint16_t* dst, int n16, int wave,
                                             int lane) {
-    for (int c = wave * 64; c < n16; c += kLdsWaves * 64)
+    for (int c = wave * 64; c < n16; c += NW * 64)
         __builtin_amdgcn_global_load_lds((const void*)(src + (int64_t)(c + lane) * 8), (lds_ptr_t)(dst + c * 8), 16,
                                          0, 0);
 }
@@ -174,8 +175,10 @@ __global__ void k_pack_xt(const PackBlock* __restrict__ packs, const double* __r
 // of task t+2 (X^T if its source changes, B, and the workgroup's A rows) with loads into a scratch
 // LDS word that nobody reads; it never waits for them, so the LDS copies of task t+2, issued by the
 // compute waves one task later, find their lines in L2.
-template <int S, int TP, int PF>
-__global__ __launch_bounds__(kLdsWaves * 64 + PF * 64) void k_hpsi_lds(const Item* __restrict__ items,
+// NW compute wavefronts (16 TP rows each): kLdsWaves, or 3 for the (96, 2) class with a prefetch
+// wavefront, whose targets have at most 96 rows, so the workgroup stays at four wavefronts.
+template <int S, int TP, int PF, int NW = kLdsWaves>
+__global__ __launch_bounds__(NW * 64 + PF * 64) void k_hpsi_lds(const Item* __restrict__ items,
                                                              const LTask* __restrict__ tasks,
                                                              const uint16_t* __restrict__ pool_t,
                                                              const uint16_t* __restrict__ xtall,
@@ -200,9 +203,9 @@ __global__ __launch_bounds__(kLdsWaves * 64 + PF * 64) void k_hpsi_lds(const Ite
     const bool active = rt0 < nrt;
 
     if constexpr (PF == 1) {
-        if (wave == kLdsWaves) {
+        if (wave == NW) {
             const int rtw0 = I.r0 >> 4;
-            const int nrow = min(kLdsWaves * TP, nrt - rtw0);     // row tiles of the workgroup
+            const int nrow = min(NW * TP, nrt - rtw0);            // row tiles of the workgroup
             auto touch = [&](const TD P, bool with_x) {
                 const int nxl = with_x ? P.pd32 * P.pa32 * 32 : 0;                 // 128-byte lines
                 const int nbl = tq * P.pd32 * 16;
@@ -272,8 +275,8 @@ __global__ __launch_bounds__(kLdsWaves * 64 + PF * 64) void k_hpsi_lds(const Ite
             }
     };
     auto stage = [&](const TD T, int st, int xsl, bool load_x) {
-        if (load_x) copy_to_lds(xt + T.x, lds + xsl * XS, T.pd32 * T.pa32 * 256, wave, lane);
-        copy_to_lds(pool_t + T.b + (int64_t)qt0 * T.pd32 * kTileU16, lds + 2 * XS + st * BS, tq * T.pd32 * 128,
+        if (load_x) copy_to_lds<NW>(xt + T.x, lds + xsl * XS, T.pd32 * T.pa32 * 256, wave, lane);
+        copy_to_lds<NW>(pool_t + T.b + (int64_t)qt0 * T.pd32 * kTileU16, lds + 2 * XS + st * BS, tq * T.pd32 * 128,
                     wave, lane);
     };
 
@@ -592,9 +595,11 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
                 else hipLaunchKernelGGL((k_hpsi_lds<96, 1, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
                                         y, P.partial, n_coeff, P.xt_size, ss);
                 break;
-            default:   // no prefetch variant: with a fifth wavefront its registers would spill
-                hipLaunchKernelGGL((k_hpsi_lds<96, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt, y,
-                                   P.partial, n_coeff, P.xt_size, ss);
+            default:   // with prefetch: 3 compute wavefronts (targets of at most 96 rows) + the prefetch one
+                if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 2, 1, 3>), grid, block, 0, s, P.items + b, P.tasks, pool_t,
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else hipLaunchKernelGGL((k_hpsi_lds<96, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
+                                        y, P.partial, n_coeff, P.xt_size, ss);
                 break;
         }
     }

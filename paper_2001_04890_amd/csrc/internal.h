@@ -171,7 +171,7 @@ struct LdsPlan {
     int prefetch_mask = 0x4;            // row-mode classes (bit c) whose workgroups get a cache-line
                                         // prefetch wavefront: (96,1) (one workgroup per CU anyway);
                                         // the S = 64 classes would lose their second workgroup per
-                                        // CU (measured slower), (96,2) would spill
+                                        // CU (measured slower); (96,2) runs 3 compute wavefronts then
 };
 
 // ---------------------------------------------------------------- large blocks (hpsi_big.hip)
