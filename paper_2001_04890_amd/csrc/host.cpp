@@ -234,6 +234,7 @@ struct dmrg_hop {
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_lds_pf = 0x4;                      // row-mode classes with a prefetch wavefront (bit mask)
+    int tune_lds_w6 = 0x8;                      // (S, 2) row-mode classes run as six one-row-tile wavefronts
     int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
     int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
     int tune_big_stages1 = 16;                  // pass-1 workgroup size in 32-wide k steps
@@ -1129,6 +1130,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
     H.lplan.xt_size = 2 * psize;
     H.lplan.xt = plan_alloc<uint16_t>(H, (size_t)2 * psize * H.vec_step);
     H.lplan.prefetch_mask = H.tune_lds_pf;
+    H.lplan.six_wave_mask = H.tune_lds_w6;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds plan] items %zu row classes", items.size());
@@ -1697,7 +1699,8 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_SMALL_NR")) H->tune_small_nr = std::max(1, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
-        if (const char* e = std::getenv("DMRG_LDS_PF")) H->tune_lds_pf = std::atoi(e) & 0x7;
+        if (const char* e = std::getenv("DMRG_LDS_PF")) H->tune_lds_pf = std::atoi(e) & 0xF;
+        if (const char* e = std::getenv("DMRG_LDS_W6")) H->tune_lds_w6 = std::atoi(e) & 0xA;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
@@ -1975,6 +1978,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_big64 = hops[0]->tune_big64;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
+        C->tune_lds_w6 = hops[0]->tune_lds_w6;
         build_plan(*C, s);
         *out = C;
         return DMRG_OK;

@@ -576,6 +576,8 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         if (n <= 0) continue;
         const dim3 grid(n, nvec), block(kLdsWaves * 64), block_pf(kLdsWaves * 64 + 64);
         const bool pf = (P.prefetch_mask >> c) & 1;
+        const bool w6 = (P.six_wave_mask >> c) & 1;      // (S, 2) classes as six one-row-tile wavefronts
+        const dim3 block6(6 * 64), block6_pf(7 * 64);
         switch (c) {
             case 0:
                 if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
@@ -584,8 +586,10 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
                                         y, P.partial, n_coeff, P.xt_size, ss);
                 break;
             case 1:
-                if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 2, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
+                if (w6) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 0, 6>), grid, block6, 0, s, P.items + b, P.tasks, pool_t,
                                            P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 2, 1>), grid, block_pf, 0, s, P.items + b, P.tasks,
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
                 else hipLaunchKernelGGL((k_hpsi_lds<64, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
                                         y, P.partial, n_coeff, P.xt_size, ss);
                 break;
@@ -596,8 +600,12 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
                                         y, P.partial, n_coeff, P.xt_size, ss);
                 break;
             default:   // with prefetch: 3 compute wavefronts (targets of at most 96 rows) + the prefetch one
-                if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 2, 1, 3>), grid, block, 0, s, P.items + b, P.tasks, pool_t,
-                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                if (w6 && pf) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 1, 6>), grid, block6_pf, 0, s, P.items + b,
+                                                 P.tasks, pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else if (w6) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 0, 6>), grid, block6, 0, s, P.items + b, P.tasks,
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                else if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 2, 1, 3>), grid, block, 0, s, P.items + b, P.tasks,
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
                 else hipLaunchKernelGGL((k_hpsi_lds<96, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
                                         y, P.partial, n_coeff, P.xt_size, ss);
                 break;

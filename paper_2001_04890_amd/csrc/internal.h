@@ -172,6 +172,10 @@ struct LdsPlan {
                                         // prefetch wavefront: (96,1) (one workgroup per CU anyway);
                                         // the S = 64 classes would lose their second workgroup per
                                         // CU (measured slower); (96,2) runs 3 compute wavefronts then
+    int six_wave_mask = 0x8;            // (S, 2) classes (bits 1, 3) run as six wavefronts of one row
+                                        // tile each (targets of 65..96 rows) instead of four of two:
+                                        // (96,2), whose one workgroup per CU then has two wavefronts on
+                                        // two of the SIMDs (measured faster; (64,2) is not)
 };
 
 // ---------------------------------------------------------------- large blocks (hpsi_big.hip)
