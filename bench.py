@@ -28,7 +28,7 @@ HBM_PEAK = 8000.0                        # GB/s
 # k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
 # (factors read off a 1 GiB device copy in the same runs); summary and commands in
 # profiles/hpsi_split_L24_M1024_kernel_trace.md. Valid for that workload and these kernels only.
-SPLIT_TRAFFIC_L24_M1024 = {"fetch_bytes": 15305.5 * 2**20, "write_bytes": 376.0 * 2**20}
+SPLIT_TRAFFIC_L24_M1024 = {"fetch_bytes": 15306.2 * 2**20, "write_bytes": 376.0 * 2**20}
 
 
 def log(*a):
