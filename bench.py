@@ -253,8 +253,7 @@ def bench_batch(args):
         hp.trim()
     comb = dm.Hop.combine(hops, stream=stream)
     tune = comb.autotune(dm.PREC_SPLIT2, reps=2, stream=stream)
-    tune64 = comb.autotune(dm.PREC_FP64, reps=2, stream=stream)
-    log(f"[bench] combined: |psi|={comb.n_coeff} flops/matvec={flops:.3e} autotune split={tune} fp64={tune64}")
+    log(f"[bench] combined: |psi|={comb.n_coeff} flops/matvec={flops:.3e} autotune={tune}")
     out = {}
     for name, prec in (("split", dm.PREC_SPLIT2), ("fp64", dm.PREC_FP64)):
         t_batch = timed(lambda: comb.hpsi(xc, yc, prec, stream=stream), 3)
@@ -270,7 +269,7 @@ def bench_batch(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
             "config": {"workload": f"{args.n_problems} independent two-site H.psi problems, L~U{{16..28}}, N=L, "
                                    f"M~U{{64..768}}, synthetic block operators sigma=1.5",
-                       "n_coeff": comb.n_coeff, "flops_per_matvec": flops, "autotune": tune, "autotune_fp64": tune64},
+                       "n_coeff": comb.n_coeff, "flops_per_matvec": flops, "autotune": tune},
             "split": out["split"], "fp64": out["fp64"]}
     print(json.dumps(line), flush=True)
 

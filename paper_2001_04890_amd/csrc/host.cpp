@@ -244,7 +244,7 @@ struct dmrg_hop {
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
     // FP64 two-pass path (hpsi_big64.hip) for the same large targets
-    int tune_big64 = 1;                         // 1: large targets of the FP64 H.psi take the two-pass path
+    int tune_big64 = 1;                         // FP64 two-pass path: 0 off, 1 where cheaper, 2 every target above 96
     double* d_tiled64 = nullptr;                // FP64 tiled operators + identity blocks (made on first use)
     int64_t tiled64_size = 0;
     std::vector<int64_t> ident64_off;           // FP64 tiled identity block of size 32 (k + 1)
@@ -1326,6 +1326,31 @@ std::vector<char> large_targets(const dmrg_hop& H) {
     return big;
 }
 
+// Targets of the FP64 H.psi that take the two-pass path. The one-wavefront kernel has no size limit,
+// so this is a cost choice: per target, the MFMA work each path executes (padded to its tiles; the
+// one-wavefront kernel recomputes A.X for every 128-column output tile) divided by the fraction of
+// the FP64 MFMA rate it sustains (measured: two-pass ~0.65 of peak on its padded work, one-wavefront
+// ~0.3). mode 2: every target above the 96-wide LDS stages (as the split path).
+std::vector<char> fp64_big_targets(const dmrg_hop& H, int mode) {
+    std::vector<char> big = large_targets(H);
+    if (mode == 2) return big;
+    auto up = [](double m, double q) { return std::ceil(m / q) * q; };
+    std::vector<double> c_big(H.blk.size(), 0.0), c_one(H.blk.size(), 0.0);
+    for (const auto& t : H.tasks) {
+        if (!big[t.j]) continue;
+        const double ma = H.blk_ma[t.i], md = H.blk_md[t.i], mj = H.blk_ma[t.j], nj = H.blk_md[t.j];
+        const double r16 = up(mj, 16), nrt = r16 / 16, nq = up(nj, 16) / 16;
+        const double pa = up(ma, 32), pd = up(md, 32);
+        // two-pass: pass 1 (8 x 8 tiles of 16 per group, pa k), pass 2 (8 x 8 tiles, pd k)
+        c_big[t.j] += (2.0 * up(nrt, 8) * 16 * up(pd / 16, 8) * 16 * pa + 2.0 * up(nrt, 8) * 16 * up(nq, 8) * 16 * pd) / 0.65;
+        // one wavefront per 32 x 128 tile: A.X per column tile, then (A.X).B^T
+        const double ncol = std::ceil(nj / 128.0);
+        c_one[t.j] += (2.0 * up(mj, 32) * up(ma, 16) * up(md, 16) * ncol + 2.0 * up(mj, 32) * up(md, 16) * up(nj, 16)) / 0.3;
+    }
+    for (size_t j = 0; j < big.size(); ++j) big[j] = big[j] && c_big[j] < c_one[j];
+    return big;
+}
+
 // FP64 tiled copy of the whole pool (16 x 16 tiles of hpsi_big64.hip, same offsets as the pool)
 // followed by FP64 tiled identity blocks of sizes 32, 64, ... up to the widest padded block, which
 // stand in for identity factors. Made once, on the first plan that routes targets to the FP64
@@ -1371,7 +1396,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     std::vector<char> big64;
     bool any_big = false;
     if (H.tune_big64) {
-        big64 = large_targets(H);
+        big64 = fp64_big_targets(H, H.tune_big64);
         for (char b : big64) any_big |= b != 0;
     }
     if (any_big) {
@@ -1702,7 +1727,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_PF")) H->tune_lds_pf = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_LDS_W6")) H->tune_lds_w6 = std::atoi(e) & 0xA;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
-        if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::max(0, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));

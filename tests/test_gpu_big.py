@@ -1,9 +1,11 @@
 """GPU parity of the two-pass large-block path (targets whose own or source blocks exceed the 96-wide
 LDS stages) against the FP64 oracle, through the C-ABI, in both precisions.
 
-Plan variants: the default plan; a cut plan (16 MB T budget: several chunks; 4-step pass-1
-workgroups: many groups per workgroup; 4-step pass-2 items: task lists cut into partial tiles that
-ordered reductions add); and the large-block path switched off (one-wavefront kernels). Bars as for
+Plan variants: every target above the LDS stages on the two-pass path in both precisions ("forced";
+by default the FP64 path takes it only where its cost model says it is cheaper); a cut plan of the
+same (16 MB T budget: several chunks; 4-step pass-1 workgroups: many groups per workgroup; 4-step
+pass-2 items: task lists cut into partial tiles that ordered reductions add); the default choice
+("auto"); and the large-block path switched off (one-wavefront kernels). Bars as for
 every H.psi: FP64 within 1e-12 of max|y|, split within 5e-4; split plans that move FP32 run
 boundaries agree within 2e-6; every plan is deterministic bit for bit.
 """
@@ -28,8 +30,9 @@ DEV = torch.device("cuda:0")
 FP64_TOL = 1e-12
 SPLIT_TOL = 5e-4
 VARIANTS = {
-    "default": {},
-    "cut": {"DMRG_BIG_STAGES": "4", "DMRG_BIG_STAGES1": "4", "DMRG_BIG_TBUDGET_MB": "16"},
+    "forced": {"DMRG_BIG64": "2"},
+    "cut": {"DMRG_BIG64": "2", "DMRG_BIG_STAGES": "4", "DMRG_BIG_STAGES1": "4", "DMRG_BIG_TBUDGET_MB": "16"},
+    "auto": {},
     "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0"},
 }
 
@@ -90,7 +93,7 @@ def test_case_a_matches_oracle(case_a, variant):
 
 def test_case_a_plans_agree(case_a):
     p, oh, x, ref = case_a
-    a, b = build(p, "default"), build(p, "cut")
+    a, b = build(p, "forced"), build(p, "cut")
     assert rel_err(run(b, x, PREC_FP64), run(a, x, PREC_FP64)) < 1e-13
     assert rel_err(run(b, x, PREC_SPLIT2), run(a, x, PREC_SPLIT2)) < 2e-6
 
@@ -112,7 +115,7 @@ def case_b():
     return p, oh, x, ref, targets
 
 
-@pytest.mark.parametrize("variant", ["default", "cut"])
+@pytest.mark.parametrize("variant", ["forced", "cut", "auto"])
 def test_case_b_sampled_targets(case_b, variant):
     p, oh, x, ref, targets = case_b
     print(f"[big B] variant {variant}, targets {targets}", flush=True)
@@ -128,7 +131,7 @@ def test_case_b_sampled_targets(case_b, variant):
 
 def test_case_b_multivector_deterministic(case_b):
     p, oh, x, ref, targets = case_b
-    hop = build(p, "default")
+    hop = build(p, "forced")
     X = np.stack([random_vector(hop.n_coeff, 50 + k) for k in range(5)])   # more vectors than one launch holds
     xd = torch.as_tensor(X, device=DEV).contiguous()
     for prec in (PREC_FP64, PREC_SPLIT2):
