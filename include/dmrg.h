@@ -236,7 +236,8 @@ dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first
  * timed calls each, and keeps the fastest. FP64 (one-wavefront kernel): widest output tile (2, 4, 8
  * MFMA tiles of 16 columns) x work items (8k, 32k, 64k) x launch order (heaviest first / cache-aware).
  * Split (LDS-staged and task-mode kernels): work items (4k, 8k, 16k, 32k) x launch order (heaviest
- * first / XCD-aware by left sector); its tile width is reported as 0. chosen (3 ints: tile width,
+ * first / XCD-aware by left sector / for a merged handle, each problem's items together); its tile
+ * width is reported as 0. chosen (3 ints: tile width,
  * items, order) and best_ms (milliseconds) may be NULL. Drops the handle's cached graphs.
  * Synchronizes `stream`. */
 dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, void* stream,

@@ -230,7 +230,8 @@ struct dmrg_hop {
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;           // capture stream (default priority)
     bool share = false;                         // build only the combinations whose operators are supplied
-    int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector
+    int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector;
+                                                // 2: merged handle, each problem's items together
     int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_lds_pf = 0x4;                      // row-mode classes with a prefetch wavefront (bit mask)
@@ -1044,6 +1045,20 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
         if (a.cls != b.cls) return a.cls < b.cls;
         return a.cost > b.cost;
     });
+    if (H.tune_lds_order == 2 && H.n_parts > 1) {
+        // merged problems: inside a class, the items of one problem stay together (heaviest first),
+        // so that the workgroups running at one time share that problem's operators in the caches
+        auto part_of = [&](int64_t y_off) {
+            return (int)(std::upper_bound(H.part_coeff.begin(), H.part_coeff.end(), y_off) - H.part_coeff.begin());
+        };
+        std::stable_sort(its.begin(), its.end(), [&](const It& a, const It& b) {
+            if (a.kind != b.kind) return a.kind < b.kind;
+            if (a.cls != b.cls) return a.cls < b.cls;
+            const int pa = part_of(a.item.y_off), pb = part_of(b.item.y_off);
+            if (pa != pb) return pa < pb;
+            return a.cost > b.cost;
+        });
+    }
     if (H.tune_lds_order == 1) {
         // XCD-aware: workgroups are dealt to the 8 XCDs round-robin, so items at positions of one
         // residue mod 8 share an L2. Items of targets with the same left sector (which read the same
@@ -1722,7 +1737,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_ITEMS")) H->tune_lds_items = std::max(64, std::atoi(e));
         if (const char* e = std::getenv("DMRG_SMALL_MODE")) H->tune_small_mode = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_SMALL_NR")) H->tune_small_nr = std::max(1, std::min(2, std::atoi(e)));
-        if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::atoi(e) == 1 ? 1 : 0;
+        if (const char* e = std::getenv("DMRG_LDS_ORDER")) H->tune_lds_order = std::max(0, std::min(2, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_LDS_SPLIT64")) H->tune_lds_split64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS_PF")) H->tune_lds_pf = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_LDS_W6")) H->tune_lds_w6 = std::atoi(e) & 0xA;
@@ -2094,6 +2109,7 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
         std::vector<int> tq_c = split ? std::vector<int>{0} : std::vector<int>{2, 4, 8};
         std::vector<int> items_c = split ? std::vector<int>{4096, 8192, 16384, 32768} : std::vector<int>{8192, 32768, 65536};
         std::vector<int> order_c = split ? std::vector<int>{0, 1} : std::vector<int>{0, 2};
+        if (split && H->n_parts > 1) order_c.push_back(2);   // merged problems: keep each problem's items together
         double best = INFINITY;
         int bt = split ? 0 : H->tune_max_tq, bi = split ? H->tune_lds_items : H->tune_items;
         int bo = split ? H->tune_lds_order : H->tune_order;
