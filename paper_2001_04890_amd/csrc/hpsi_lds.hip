@@ -413,7 +413,7 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
     const uint16_t* __restrict__ xt = xtall + (int64_t)blockIdx.y * xt_size;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
     double* __restrict__ part = partall + (int64_t)blockIdx.y * slot_stride;
-    const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    const int lane = threadIdx.x & 63;
     const int rt0 = I.r0 >> 4, qt0 = I.c0 >> 4;
     const int nr = min(NR, ((I.m_ap + 15) >> 4) - rt0);
     const int tq = min(NQ, ((I.m_dp - I.c0) + 15) >> 4);

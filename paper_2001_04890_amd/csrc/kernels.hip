@@ -582,7 +582,7 @@ __global__ __launch_bounds__(256) void k_multidot(const double* __restrict__ V, 
         if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
     }
     __syncthreads();
-    if (threadIdx.x < nj)
+    if ((int)threadIdx.x < nj)
         partial[(int64_t)(j0 + threadIdx.x) * n_part + blockIdx.x] =
             ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }

@@ -58,7 +58,6 @@ struct DevBuf {
 };
 
 constexpr int64_t kMaxBatch = int64_t(1) << 20;
-constexpr int kMaxSnapshots = 256;
 
 }  // namespace
 
