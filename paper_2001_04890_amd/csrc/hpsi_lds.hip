@@ -1,15 +1,18 @@
 // LDS-staged split-BF16 sector GEMMs of Eq. dgemm (Section 2.2.1) for gfx950.
 //
-// One workgroup of kLdsWaves wavefronts owns a whole row block of a target psi block (every column)
-// and loops over the target's tasks Y += f * A . X . B^T, sorted by source block. Wave w owns row
-// tiles [TP w, TP w + TP) of the block. Per task:
+// One workgroup of NW compute wavefronts (kLdsWaves, or six of one row tile each for targets of
+// 65..96 rows) owns a whole row block of a target psi block (every column) and loops over the
+// target's tasks Y += f * A . X . B^T, sorted by source block. Wave w owns row tiles
+// [TP w, TP w + TP) of the block; an optional extra wavefront only touches the cache lines of the
+// task after next. Per task:
 //   GEMM1  T'^T = X^T . A(rows)^T       A-operand: X^T fragments from LDS, B-operand: A rows held in
 //                                       registers (loaded straight from the tiled pool)
 //   GEMM2  Y   += T' . B^T              A-operand: T' (the MFMA result layout of GEMM1 is the
 //                                       A-operand layout of GEMM2), B-operand: B fragments from LDS
 // X^T (shared by the run of tasks with the same source) and B (per task) are copied into LDS with
 // global_load_lds_dwordx4 one task ahead (two stages), so the copy of task k+1 and the A-fragment
-// loads of task k+1 overlap the MFMAs of task k. Operands are stored pre-tiled in fragment order
+// loads of task k+1 (branch-free: the compiler must not have to wait for them before task k's
+// MFMAs) overlap the MFMAs of task k. Operands are stored pre-tiled in fragment order
 // (internal.h), which makes every copy a contiguous 1 KB per wave instruction and every LDS read a
 // conflict-free ds_read_b128 at lane * 16 bytes.
 //
