@@ -144,3 +144,25 @@ def test_electron_number_out_of_range_and_empty_sector():
     with pytest.raises(DmrgError) as e:
         Hop(h, eri, left, right, 6, 6, site, device=-1)
     assert e.value.status == -2
+
+
+@pytest.mark.parametrize("case", ["exact8", "synth12", "edge4_left_empty"])
+def test_flop_count_follows_its_definition(case):
+    """The algorithmic flop count behind every TFLOP/s figure: per exported task, 2 MACs of the cheaper
+    association of A.X.B^T (one product when a side is the identity, none when both are), summed."""
+    if case == "exact8":
+        p = exact_problem(8, 0)
+    elif case == "synth12":
+        p = synth(12, 60, 1.2, 5)
+    else:
+        p = exact_problem(4, 3, site=0)
+    hop = Hop(*p, device=-1)
+    quads, f, ti, tc = hop.export_tasks()
+    ma, md = hop.dims[:, 0].astype(np.float64), hop.dims[:, 1].astype(np.float64)
+    i, j, lm, rm = quads[:, 0], quads[:, 1], quads[:, 2], quads[:, 3]
+    a, d, mj, nj = ma[i], md[i], ma[j], md[j]
+    both = 2.0 * np.minimum(mj * a * d + mj * d * nj, a * d * nj + mj * a * nj)
+    fl = np.where((lm < 0) & (rm < 0), 0.0,
+                  np.where(lm < 0, 2.0 * a * d * nj, np.where(rm < 0, 2.0 * mj * a * d, both)))
+    assert hop.stats()["n_tasks"] == len(quads)
+    assert abs(hop.stats()["flops"] - fl.sum()) <= 1e-12 * fl.sum()
