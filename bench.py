@@ -2,8 +2,8 @@
 
 Workload (the precision configuration): L = 24 orbitals, N = 24 (N_alpha = N_beta = 12),
 bond dimension M = 1024 per block at the middle bond (site 11 | 12), random integrals (seed 1),
-synthetic block operators with the real operator structure and Gaussian sector sizes (sigma = 1.5);
-see the design doc for the recipe. One step = one Davidson iteration (H.psi in split-BF16 precision,
+synthetic block operators with the real operator structure and Gaussian sector sizes (sigma = 1.5),
+built by dmrg_inputs/synthetic.py. One step = one Davidson iteration (H.psi in split-BF16 precision,
 Gram-Schmidt, Rayleigh-Ritz, residual, diagonal preconditioner), inputs resident in HBM.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
@@ -62,8 +62,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the H.psi would shard over operator combinations with one all-reduce per matvec; "
-              "see DESIGN.md)", file=sys.stderr)
+              "(the H.psi would shard over operator combinations with one all-reduce per matvec)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -2420,7 +2420,7 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
             HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
             have_prev = true;
             if (o->precond == DMRG_PRECOND_MLP && mlp_on) {
-                // the diagonal preconditioner judges the network: once the residual has made no new
+                // the diagonal preconditioner is the network's yardstick: once the residual has made no new
                 // minimum (by 1%) for 20 iterations, the rest of the solve uses the diagonal correction
                 if (rnorm < 0.99 * best_mlp_r) { best_mlp_r = rnorm; mlp_stall = 0; }
                 else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
