@@ -17,6 +17,8 @@ Everything here is plain, slow and written for checkability against the paper
   left-block operators (Section 2.1 / 2.2.3).
 * :mod:`oracle.hpsi`        -- the sector GEMMs of Eq. dgemm, and diag(H).
 * :mod:`oracle.davidson`    -- Davidson's method for the lowest eigenpair.
+* :mod:`oracle.renorm`      -- reduced density matrices, the M-state truncation and Eq. renorm_mat
+  (the renormalization step that follows the Davidson solve; no GPU counterpart yet).
 
 Parity pins (see ``tests/test_oracle_*.py``): closed forms of tiny Hamiltonians, CAR relations,
 brute-force FCI matvecs and energies with exact blocks, Hermiticity, particle-number/Sz
