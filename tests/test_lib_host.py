@@ -61,10 +61,18 @@ def _exec_tasks(hop, left, right, x):
 
 
 @pytest.mark.parametrize("case", ["exact8", "trunc10_odd", "synth12", "edge4_left_empty", "edge6_right_empty",
-                                  "edge2_both_empty"])
+                                  "edge2_both_empty", "spin_polarized8", "off_center9", "near_full6", "one_electron6"])
 def test_host_task_list_matches_oracle(case):
     if case == "exact8":
         h, eri, left, right, na, nb, site = exact_problem(8, 0)
+    elif case == "spin_polarized8":        # N_alpha - N_beta = 4: many (a, b, c, d) combinations vanish
+        h, eri, left, right, na, nb, site = exact_problem(8, 4, n_alpha=6, n_beta=2)
+    elif case == "off_center9":            # bond (2, 3) of L = 9: 2-orbital left block, 5-orbital right block
+        h, eri, left, right, na, nb, site = exact_problem(9, 5, n_alpha=5, n_beta=3, site=2)
+    elif case == "near_full6":             # two holes: the particle-hole mirror of a 2-electron problem
+        h, eri, left, right, na, nb, site = exact_problem(6, 6, n_alpha=5, n_beta=5)
+    elif case == "one_electron6":          # one electron: no two-body term has a nonzero matrix element
+        h, eri, left, right, na, nb, site = exact_problem(6, 7, n_alpha=1, n_beta=0)
     elif case == "edge4_left_empty":
         h, eri, left, right, na, nb, site = exact_problem(4, 3, site=0)
     elif case == "edge6_right_empty":

@@ -87,10 +87,12 @@ def test_hpsi_equals_fci_exact_blocks_L10():
     assert np.abs(hop.apply(x) - yref).max() < 1e-12 * np.abs(yref).max()
 
 
-@pytest.mark.parametrize("L,s1,na,nb", [(2, 0, 1, 1), (4, 0, 2, 2), (4, 2, 2, 2), (5, 0, 3, 2), (6, 4, 3, 3)])
-def test_hpsi_equals_fci_edge_bonds(L, s1, na, nb):
+@pytest.mark.parametrize("L,s1,na,nb", [(2, 0, 1, 1), (4, 0, 2, 2), (4, 2, 2, 2), (5, 0, 3, 2), (6, 4, 3, 3),
+                                        (8, 3, 6, 2), (9, 2, 5, 3), (6, 2, 5, 5), (6, 2, 1, 0)])
+def test_hpsi_equals_fci_edge_and_uneven_bonds(L, s1, na, nb):
     """Edge bonds: a block with no orbitals holds only the vacuum (one sector of dimension 1), so the
-    superblock is still the whole FCI space."""
+    superblock is still the whole FCI space. Also, with exact blocks: strong spin imbalance (6, 2), an
+    off-centre bond of odd L, two holes (5, 5) in 6 orbitals, and a single electron."""
     h, eri = random_integrals(L, 3)
     t, w = spin_orbital_integrals(h, eri)
     s2 = s1 + 1
