@@ -19,6 +19,8 @@ Everything here is plain, slow and written for checkability against the paper
 * :mod:`oracle.davidson`    -- Davidson's method for the lowest eigenpair.
 * :mod:`oracle.renorm`      -- reduced density matrices, the M-state truncation and Eq. renorm_mat
   (the renormalization step that follows the Davidson solve; no GPU counterpart yet).
+* :mod:`oracle.blocking`    -- operators of the grown left block (block + site) from the block's
+  stored operators and the site matrices, and their renormalized block (no GPU counterpart yet).
 
 Parity pins (see ``tests/test_oracle_*.py``): closed forms of tiny Hamiltonians, CAR relations,
 brute-force FCI matvecs and energies with exact blocks, Hermiticity, particle-number/Sz
