@@ -61,7 +61,7 @@ def main():
                          "(calibration of the traffic counters); prints per-call event timings")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: libdmrg has no multi-GPU path "
               "(the H.psi would shard over operator combinations with one all-reduce per matvec)", file=sys.stderr)
         sys.exit(2)
 

@@ -174,3 +174,15 @@ def test_flop_count_follows_its_definition(case):
                   np.where(lm < 0, 2.0 * a * d * nj, np.where(rm < 0, 2.0 * mj * a * d, both)))
     assert hop.stats()["n_tasks"] == len(quads)
     assert abs(hop.stats()["flops"] - fl.sum()) <= 1e-12 * fl.sum()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU only: --gpus 2 (or a multi-rank launch) exits with status 2 and a
+    message, before any GPU work."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py")] + args, capture_output=True, text=True,
+                           env={**os.environ, **env}, timeout=120)
+        assert r.returncode == 2 and "one GPU only" in r.stderr
