@@ -10,6 +10,7 @@ What is computed, in the paper's order and notation:
 3. O^L (Eq. renorm) holds the M eigenvectors of rho^L with the largest eigenvalues, as columns; the
    truncated basis is |l_p> = sum_{l s} O_{(l s), l_p} |l>|s>.
 4. An enlarged-block operator A becomes A' = O^T A O (Eq. renorm_mat).
+5. The truncated state O^T psi is carried to the next bond's basis (``next_bond_psi``).
 
 U(1) x U(1) symmetry makes every step block diagonal. The enlarged-left quantum number
 q = qn(a) + qn(b) fixes the enlarged-right one, (N_alpha, N_beta) - q, so psi splits into one dense
@@ -169,3 +170,26 @@ def block_number_left(left, spin):
             d[st:st + m] = left.qn[a][spin]
         A[(q, q)] = np.diag(d)
     return A
+
+
+def next_bond_psi(layout_next, psi_t, right_old, n_alpha, n_beta, split_right):
+    """psi of the truncated state in the next bond's basis (the left block grown and renormalized,
+    the old right site now the left site, the old right block split into a site and a smaller block).
+
+    psi_t: q -> O_q^T Psi_q (rows: kept states of sector q in O's column order; columns: the old
+    enlarged-right basis of sector N - q). The new left block's sectors are the q of psi_t in
+    ascending order. split_right(d, r) -> (s, d_new, r_new, coef) writes old right-block state r of
+    sector d as coef |s>|r_new> (site state s of the new right site, state r_new of sector d_new).
+    """
+    rparts, _ = enlarged_right_basis(right_old)
+    sidx = {q: i for i, q in enumerate(sorted(psi_t))}
+    out = np.zeros(layout_next.size)
+    for q, T in psi_t.items():
+        qr = (n_alpha - q[0], n_beta - q[1])
+        for c, d, st, m in rparts.get(qr, []):
+            for r in range(m):
+                s, d_new, r_new, coef = split_right(d, r)
+                i = layout_next.index[(sidx[q], c, s, d_new)]
+                X = layout_next.view(out, i)
+                X[:, r_new] += coef * T[:, st + r]
+    return out

@@ -10,6 +10,10 @@
   then has the FCI ground-state energy when nothing is discarded, and for smaller M an energy
   between E_FCI (variational bound) and the energy of the truncated state O O^T psi, which that
   superblock space contains.
+* The same step for the state itself: O O^T psi written in the next bond's basis (renormalized left
+  block, the old right site as the new left site, the old exact right block split into a site and a
+  block) has, under the next bond's H.psi, exactly the energy and norm it has at the current bond;
+  at full M it is an eigenvector with the FCI energy.
 """
 import numpy as np
 import pytest
@@ -138,3 +142,32 @@ def test_renormalization_step_truncated_is_bracketed(step, M):
     e_trunc = float(x @ step["hop"].apply(x) / (x @ x))
     assert disc > 0
     assert step["e_fci"] - 1e-10 <= e <= e_trunc + 1e-10
+
+
+def _split_exact_right(old, new):
+    """Old exact right block -> its first orbital (the new right site) x the new right block."""
+    def split(d, r):
+        bits = int(old.fock.sector_states[d][r])
+        s, rest = bits & 3, bits >> 2          # site bits come first in the Jordan-Wigner order
+        return s, int(new.fock.sector_of[rest]), int(new.fock.pos_in[rest]), 1.0
+    return split
+
+
+@pytest.mark.parametrize("M", [6, 12, 24, 64])
+def test_renormalization_step_carries_the_state(step, M):
+    O, kept, disc = renorm.select(step["rho"], M)
+    grown = GrownLeft(step["left"], step["t"], step["w"], step["s1"]).renormalized_block(O)
+    nxt = OracleHop(step["h"], step["eri"], grown, step["right_next"], step["na"], step["nb"], step["s1"] + 1)
+    psi_t = renorm.transform_psi(step["P"], O)
+    split = _split_exact_right(step["right"], step["right_next"])
+    y = renorm.next_bond_psi(nxt.layout, psi_t, step["right"], step["na"], step["nb"], split)
+    # the same state at the current bond
+    Pt = {q: (O[q] @ psi_t[q] if q in O else np.zeros_like(step["P"][q])) for q in step["P"]}
+    x = _unflatten(step["hop"].layout, step["left"], step["right"], step["na"], step["nb"], Pt)
+    assert abs(y @ y - x @ x) < 1e-12 and abs(y @ y - (1.0 - disc)) < 1e-12
+    e_next = float(y @ nxt.apply(y) / (y @ y))
+    e_cur = float(x @ step["hop"].apply(x) / (x @ x))
+    assert abs(e_next - e_cur) < 1e-10
+    if M == 64:
+        assert abs(disc) < 1e-12
+        assert np.abs(nxt.apply(y) - step["e_fci"] * y).max() < 1e-9
