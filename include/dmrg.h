@@ -168,6 +168,27 @@ dmrg_status dmrg_hpsi_graph(dmrg_hop* hop, const double* x, double* y, int32_t n
 /* diag(H) (FP64) into a device buffer of n_coeff doubles. */
 dmrg_status dmrg_hop_diagonal(dmrg_hop* hop, double* d, void* stream);
 
+/* Reduced density matrix of the enlarged left block, rho^L = psi psi^T (Section 2.1, the matrix whose
+ * M leading eigenvectors form the renormalization matrix of Eq. renorm), with psi read as the matrix
+ * psi_{(l s_l), (s_r r)}. U(1) x U(1) makes rho^L block diagonal in the enlarged-left quantum number
+ * q = qn(a) + qn(s_l).
+ *
+ * dmrg_rdm_left_layout: the sectors, in ascending (n_alpha, n_beta). *n_sec receives their number;
+ * qn (2 * n_sec int32: n_alpha, n_beta), dims (n_sec) and offsets (n_sec + 1 int64, offsets of the
+ * dense blocks, offsets[n_sec] = sum of dims^2) are filled when not NULL (call once with NULL to size
+ * them). Rows of sector q: the pairs (a, s_l) with qn(a) + qn(s_l) = q in (a, s_l) order, each with
+ * the dim(a) states of left sector a, including pairs that no psi block reaches (zero rows). Works on
+ * host-only handles; a merged handle (dmrg_hop_combine) returns DMRG_ERR_UNSUPPORTED.
+ *
+ * dmrg_rdm_left: rho (device, rho_len doubles, rho_len = offsets[n_sec]) receives every sector's
+ * dim x dim block, row-major, at its offset; psi is a device vector of n_coeff doubles in the handle's
+ * layout. FP64, each element summed in a fixed order (deterministic). Synchronizes `stream` before
+ * returning (it allocates and frees small device work lists). Errors: DMRG_ERR_ARG (NULL),
+ * DMRG_ERR_SHAPE (rho_len), DMRG_ERR_UNSUPPORTED (host-only or merged handle), DMRG_ERR_DEVICE. */
+dmrg_status dmrg_rdm_left_layout(const dmrg_hop* hop, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                                 int64_t* offsets);
+dmrg_status dmrg_rdm_left(dmrg_hop* hop, const double* psi, double* rho, int64_t rho_len, void* stream);
+
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs (restarting from the

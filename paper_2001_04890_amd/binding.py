@@ -79,6 +79,10 @@ lib.dmrg_hpsi_graph.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C
 lib.dmrg_hpsi_graph.restype = C.c_int32
 lib.dmrg_hop_diagonal.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 lib.dmrg_hop_diagonal.restype = C.c_int32
+lib.dmrg_rdm_left_layout.argtypes = [C.c_void_p, i32p, i32p, i32p, i64p]
+lib.dmrg_rdm_left_layout.restype = C.c_int32
+lib.dmrg_rdm_left.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+lib.dmrg_rdm_left.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
 lib.dmrg_davidson.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
@@ -268,6 +272,23 @@ class Hop:
     def diagonal(self, d, stream=None):
         assert d.numel() == self.n_coeff and d.is_contiguous()
         _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
+
+    def rdm_left_layout(self):
+        """Sectors of rho^L: (qn (n, 2), dims (n,), offsets (n + 1,)) from dmrg_rdm_left_layout."""
+        n = C.c_int32(0)
+        _check(lib.dmrg_rdm_left_layout(self._h, C.byref(n), None, None, None))
+        qn = np.zeros(2 * n.value, dtype=np.int32)
+        dims = np.zeros(n.value, dtype=np.int32)
+        off = np.zeros(n.value + 1, dtype=np.int64)
+        _check(lib.dmrg_rdm_left_layout(self._h, C.byref(n), _ptr(qn, C.c_int32), _ptr(dims, C.c_int32),
+                                        _ptr(off, C.c_int64)))
+        return qn.reshape(-1, 2), dims, off
+
+    def rdm_left(self, psi, rho, stream=None):
+        """rho^L = psi psi^T per sector (dmrg_rdm_left) into the device buffer rho."""
+        assert psi.numel() == self.n_coeff and psi.is_contiguous() and rho.is_contiguous()
+        _check(lib.dmrg_rdm_left(self._h, C.c_void_p(psi.data_ptr()), C.c_void_p(rho.data_ptr()),
+                                 int(rho.numel()), _stream_ptr(stream)))
 
     def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
                  split_tol=1e-5, mlp=None, stream=None, use_graph=False):

@@ -1944,6 +1944,147 @@ extern "C" dmrg_status dmrg_hop_diagonal(dmrg_hop* H, double* d, void* stream) {
     }
 }
 
+// ---------------------------------------------------------------- reduced density matrix
+namespace {
+// Enlarged-left sectors q = qn(a) + qn(b) (Section 2.1: psi read as the matrix psi_{(l s_l),(s_r r)}) in
+// ascending (n_alpha, n_beta); the rows of sector q are the pairs (a, b) in (a, b) order, each with the
+// m_a states of left sector a, including pairs that no psi block reaches (zero rows).
+struct RdmLayout {
+    std::vector<std::pair<int, int>> qn;
+    std::vector<int> dim;
+    std::vector<int64_t> off;                                  // n_sec + 1: dense dim x dim blocks
+    std::vector<std::vector<std::array<int, 3>>> groups;       // per sector: (a, b, first row)
+};
+
+RdmLayout rdm_layout(const dmrg_hop& H) {
+    if (H.n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: density matrices are per problem");
+    std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> groups;
+    std::map<std::pair<int, int>, int> dims;
+    for (int a = 0; a < H.left.n_sec; ++a) {
+        if (H.left.dim[a] <= 0) continue;
+        for (int b = 0; b < 4; ++b) {
+            const std::pair<int, int> q{H.left.qa[a] + kSiteQn[b][0], H.left.qb[a] + kSiteQn[b][1]};
+            int& d = dims[q];
+            groups[q].push_back({a, b, d});
+            d += H.left.dim[a];
+        }
+    }
+    RdmLayout R;
+    R.off.push_back(0);
+    for (auto& kv : groups) {
+        const int d = dims[kv.first];
+        R.qn.push_back(kv.first);
+        R.dim.push_back(d);
+        R.off.push_back(R.off.back() + (int64_t)d * d);
+        R.groups.push_back(kv.second);
+    }
+    return R;
+}
+}  // namespace
+
+extern "C" dmrg_status dmrg_rdm_left_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                                            int64_t* offsets) {
+    g_err.clear();
+    try {
+        if (!H || !n_sec) throw Error(DMRG_ERR_ARG, "NULL argument");
+        const RdmLayout R = rdm_layout(*H);
+        *n_sec = (int32_t)R.dim.size();
+        for (size_t i = 0; i < R.dim.size(); ++i) {
+            if (qn) { qn[2 * i] = R.qn[i].first; qn[2 * i + 1] = R.qn[i].second; }
+            if (dims) dims[i] = R.dim[i];
+        }
+        if (offsets)
+            for (size_t i = 0; i < R.off.size(); ++i) offsets[i] = R.off[i];
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
+extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
+    g_err.clear();
+    try {
+        if (!H || !psi || !rho) throw Error(DMRG_ERR_ARG, "NULL argument");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        const RdmLayout R = rdm_layout(*H);
+        if (rho_len != R.off.back()) throw Error(DMRG_ERR_SHAPE, "rho_len must be the sum of dim_q^2 of the sectors");
+        // per row group: the psi blocks of its column groups c = 0..3 that exist; within a sector these
+        // are the same c (the right sector is fixed by q and c), checked below
+        std::vector<dmrg::RdmItem> items;
+        std::vector<int64_t> gblk;
+        std::vector<int32_t> cdmd;
+        for (size_t qi = 0; qi < R.dim.size(); ++qi) {
+            const auto& G = R.groups[qi];
+            const int cd0 = (int)cdmd.size();
+            std::vector<int> g0(G.size());
+            int n_cd = -1;
+            for (size_t k = 0; k < G.size(); ++k) {
+                g0[k] = (int)gblk.size();
+                int cnt = 0;
+                for (int c = 0; c < 4; ++c) {
+                    const int id = H->blk_index[(G[k][0] * 4 + G[k][1]) * 4 + c];
+                    if (id < 0) continue;
+                    if (k == 0) cdmd.push_back(H->blk_md[id]);
+                    else if (cnt >= n_cd || cdmd[cd0 + cnt] != H->blk_md[id])
+                        throw Error(DMRG_ERR_ARG, "internal: column groups differ within a sector");
+                    gblk.push_back(H->blk_off[id]);
+                    ++cnt;
+                }
+                if (k > 0 && cnt != n_cd) throw Error(DMRG_ERR_ARG, "internal: column groups differ within a sector");
+                n_cd = cnt;
+            }
+            for (size_t k = 0; k < G.size(); ++k)
+                for (size_t k2 = 0; k2 < G.size(); ++k2) {
+                    dmrg::RdmItem it{};
+                    it.rho_off = R.off[qi] + (int64_t)G[k][2] * R.dim[qi] + G[k2][2];
+                    it.ld = R.dim[qi];
+                    it.ma = H->left.dim[G[k][0]];
+                    it.ma2 = H->left.dim[G[k2][0]];
+                    it.g = g0[k];
+                    it.g2 = g0[k2];
+                    it.cd = cd0;
+                    it.n_cd = n_cd;
+                    items.push_back(it);
+                }
+        }
+        if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many density-matrix items");
+        HIPCHK(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)stream;
+        void *d_items = nullptr, *d_g = nullptr, *d_c = nullptr;
+        auto release = [&]() {
+            if (d_items) (void)hipFree(d_items);
+            if (d_g) (void)hipFree(d_g);
+            if (d_c) (void)hipFree(d_c);
+        };
+        try {
+            HIPCHK(hipMalloc(&d_items, std::max<size_t>(1, items.size()) * sizeof(dmrg::RdmItem)));
+            HIPCHK(hipMalloc(&d_g, std::max<size_t>(1, gblk.size()) * sizeof(int64_t)));
+            HIPCHK(hipMalloc(&d_c, std::max<size_t>(1, cdmd.size()) * sizeof(int32_t)));
+            if (!items.empty())
+                HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RdmItem), hipMemcpyHostToDevice, s));
+            if (!gblk.empty())
+                HIPCHK(hipMemcpyAsync(d_g, gblk.data(), gblk.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+            if (!cdmd.empty())
+                HIPCHK(hipMemcpyAsync(d_c, cdmd.data(), cdmd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            HIPCHK(dmrg::launch_rdm_left(static_cast<const dmrg::RdmItem*>(d_items), (int)items.size(),
+                                         static_cast<const int64_t*>(d_g), static_cast<const int32_t*>(d_c),
+                                         psi, rho, s));
+            HIPCHK(hipStreamSynchronize(s));   // the host work lists and scratch end here
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            release();
+            throw;
+        }
+        release();
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
 // ---------------------------------------------------------------- batching and tuning
 extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out) {
     g_err.clear();

@@ -239,6 +239,17 @@ int multidot_parts(int64_t n);
 // out -= sum_j c[j] V[j], c in device memory; x *= 1 / sqrt(*nrm2) with *nrm2 in device memory.
 hipError_t launch_project_out(const double* V, int nv, int64_t n, const double* c, double* out, hipStream_t s);
 hipError_t launch_scale_dev(double* x, const double* nrm2, int64_t n, hipStream_t s);
+
+// Reduced density matrix of the enlarged left block (Section 2.1), one item per (sector, row group,
+// row group): rho[rho_off + l * ld + l2] = sum over the sector's n_cd column groups k of
+// sum_r X_{g,k}[l][r] X_{g2,k}[l2][r], with X_{g,k} the psi block at gblk[g + k] (row-major, m_d =
+// cdmd[cd + k] columns), l < ma, l2 < ma2. Every element of rho is written by exactly one item.
+struct RdmItem {
+    int64_t rho_off;
+    int32_t ld, ma, ma2, g, g2, cd, n_cd, pad;
+};
+hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
+                           const double* psi, double* rho, hipStream_t s);
 // Tiled split-BF16 kernels (hpsi_lds.hip).
 hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).

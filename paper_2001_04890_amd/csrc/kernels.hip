@@ -691,4 +691,32 @@ hipError_t launch_scale(double* x, double a, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ reduced density matrix
+// rho^L = psi psi^T per enlarged-left sector (Section 2.1), FP64, one workgroup per item; each
+// thread owns output elements and sums over the column groups and columns in a fixed order.
+__global__ void k_rdm_left(const RdmItem* __restrict__ items, const int64_t* __restrict__ gblk,
+                           const int32_t* __restrict__ cdmd, const double* __restrict__ psi,
+                           double* __restrict__ rho) {
+    const RdmItem it = items[blockIdx.x];
+    const int n = it.ma * it.ma2;
+    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+        const int l = e / it.ma2, l2 = e - (e / it.ma2) * it.ma2;
+        double acc = 0.0;
+        for (int k = 0; k < it.n_cd; ++k) {
+            const int md = cdmd[it.cd + k];
+            const double* x = psi + gblk[it.g + k] + (int64_t)l * md;
+            const double* y = psi + gblk[it.g2 + k] + (int64_t)l2 * md;
+            for (int r = 0; r < md; ++r) acc = fma(x[r], y[r], acc);
+        }
+        rho[it.rho_off + (int64_t)l * it.ld + l2] = acc;
+    }
+}
+
+hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
+                           const double* psi, double* rho, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rdm_left, dim3((unsigned)n_items), dim3(256), 0, s, items, gblk, cdmd, psi, rho);
+    return hipGetLastError();
+}
+
 }  // namespace dmrg

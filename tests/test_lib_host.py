@@ -186,3 +186,37 @@ def test_bench_refuses_more_than_one_gpu():
         r = subprocess.run([sys.executable, os.path.join(root, "bench.py")] + args, capture_output=True, text=True,
                            env={**os.environ, **env}, timeout=120)
         assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+@pytest.mark.parametrize("case", ["exact8", "trunc10_odd", "synth12", "edge4_left_empty"])
+def test_rdm_left_layout_matches_oracle(case):
+    """dmrg_rdm_left_layout lists the enlarged-left sectors (ascending q) with the oracle's dimensions."""
+    from oracle import renorm
+    if case == "exact8":
+        p = exact_problem(8, 0)
+    elif case == "trunc10_odd":
+        p = exact_problem(10, 1, n_alpha=5, n_beta=4, trunc=40)
+    elif case == "edge4_left_empty":
+        p = exact_problem(4, 3, site=0)
+    else:
+        p = synth(12, 60, 1.2, 5)
+    hop = Hop(*p, device=-1)
+    qn, dims, off = hop.rdm_left_layout()
+    _, odims = renorm.enlarged_left_basis(p[2])
+    assert [tuple(int(v) for v in q) for q in qn] == list(odims)
+    assert dims.tolist() == list(odims.values())
+    assert off[0] == 0 and np.array_equal(np.diff(off), dims.astype(np.int64) ** 2)
+
+    class Fake:
+        def numel(self):
+            return hop.n_coeff
+
+        def is_contiguous(self):
+            return True
+
+        def data_ptr(self):
+            return 16
+
+    with pytest.raises(DmrgError) as e:
+        hop.rdm_left(Fake(), Fake())
+    assert e.value.status == -7
