@@ -189,6 +189,23 @@ dmrg_status dmrg_rdm_left_layout(const dmrg_hop* hop, int32_t* n_sec, int32_t* q
                                  int64_t* offsets);
 dmrg_status dmrg_rdm_left(dmrg_hop* hop, const double* psi, double* rho, int64_t rho_len, void* stream);
 
+/* The truncation of Section 2.1: the M eigenvectors of a block-diagonal density matrix with the
+ * largest eigenvalues (they form the renormalization matrix of Eq. renorm). Host routine, FP64: each
+ * sector by the cyclic Jacobi method (off-diagonal norm below 1e-15 of the Frobenius norm).
+ * rho (host, read only): n_sec symmetric dims[i] x dims[i] row-major blocks at offsets[i], the prefix
+ * sums of dims^2 (the layout of dmrg_rdm_left_layout). Outputs, all host, caller-allocated:
+ * evals (sum of dims doubles: per sector, in sector order, its eigenvalues in descending order);
+ * vecs (offsets[n_sec] doubles: per sector a row-major dims x dims matrix whose column k is the
+ * eigenvector of the k-th largest eigenvalue, its largest-magnitude component positive); kept (n_sec
+ * int32: how many leading columns of each sector are kept); discarded (1 double: trace minus the kept
+ * eigenvalues). The M largest eigenvalues are taken over all sectors together, ties in (sector,
+ * position) order; M = 0 keeps nothing, M >= sum of dims keeps everything. Only the projector onto
+ * the kept columns is unique (when the cut falls between distinct eigenvalues). Errors: DMRG_ERR_ARG
+ * (NULL, negative n_sec or M), DMRG_ERR_SHAPE (offsets), DMRG_ERR_NAN (non-finite input, no
+ * convergence). */
+dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int32_t* dims, const int64_t* offsets, int32_t M,
+                          int32_t* kept, double* evals, double* vecs, double* discarded);
+
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs (restarting from the

@@ -83,6 +83,8 @@ lib.dmrg_rdm_left_layout.argtypes = [C.c_void_p, i32p, i32p, i32p, i64p]
 lib.dmrg_rdm_left_layout.restype = C.c_int32
 lib.dmrg_rdm_left.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
 lib.dmrg_rdm_left.restype = C.c_int32
+lib.dmrg_truncate.argtypes = [f64p, C.c_int32, i32p, i64p, C.c_int32, i32p, f64p, f64p, f64p]
+lib.dmrg_truncate.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
 lib.dmrg_davidson.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
@@ -147,6 +149,24 @@ def _check(st, allow=(DMRG_OK,)):
 
 def _ptr(a, ctype):
     return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def truncate(rho, dims, M):
+    """dmrg_truncate on host arrays: rho (flat, sector blocks dims[i]^2 in order), dims, M.
+    Returns (kept (n_sec,), evals list of descending arrays, vecs list of (d, d) arrays, discarded)."""
+    rho = np.ascontiguousarray(rho, dtype=np.float64)
+    dims = np.ascontiguousarray(dims, dtype=np.int32)
+    off = np.concatenate([[0], np.cumsum(dims.astype(np.int64) ** 2)]).astype(np.int64)
+    kept = np.zeros(dims.size, dtype=np.int32)
+    evals = np.zeros(int(dims.sum()), dtype=np.float64)
+    vecs = np.zeros(int(off[-1]), dtype=np.float64)
+    disc = np.zeros(1, dtype=np.float64)
+    _check(lib.dmrg_truncate(_ptr(rho, C.c_double), int(dims.size), _ptr(dims, C.c_int32), _ptr(off, C.c_int64),
+                             int(M), _ptr(kept, C.c_int32), _ptr(evals, C.c_double), _ptr(vecs, C.c_double),
+                             _ptr(disc, C.c_double)))
+    e0 = np.concatenate([[0], np.cumsum(dims)])
+    return (kept, [evals[e0[i]:e0[i + 1]] for i in range(dims.size)],
+            [vecs[off[i]:off[i + 1]].reshape(dims[i], dims[i]) for i in range(dims.size)], float(disc[0]))
 
 
 class _BlockMarshal:

@@ -2085,6 +2085,118 @@ extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho
     }
 }
 
+namespace {
+// Eigenpairs of a symmetric n x n matrix (row-major, overwritten) by the cyclic Jacobi method: sweeps
+// over all pairs (p, q) of a plane rotation that zeroes a_pq, until the off-diagonal norm is below
+// 1e-15 of the Frobenius norm. V receives the eigenvectors as columns; the eigenvalues are left on
+// the diagonal of A.
+void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    double fro = 0.0;
+    for (double v : A) fro += v * v;
+    if (fro == 0.0) return;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2.0 * A[(size_t)p * n + q] * A[(size_t)p * n + q];
+        if (off <= 1e-30 * fro) return;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                // rotation angle: t = tan(phi) is the smaller root of t^2 + 2 theta t - 1 = 0
+                const double theta = (aqq - app) / (2.0 * apq);
+                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+                for (int k = 0; k < n; ++k) {           // columns p, q: A <- A J
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - sn * akq;
+                    A[(size_t)k * n + q] = sn * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {           // rows p, q: A <- J^T A
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - sn * aqk;
+                    A[(size_t)q * n + k] = sn * apk + c * aqk;
+                }
+                A[(size_t)p * n + q] = A[(size_t)q * n + p] = 0.0;
+                for (int k = 0; k < n; ++k) {           // V <- V J
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
+                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
+                }
+            }
+    }
+    throw Error(DMRG_ERR_NAN, "Jacobi eigensolver did not converge in 100 sweeps");
+}
+}  // namespace
+
+extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int32_t* dims, const int64_t* offsets,
+                                     int32_t M, int32_t* kept, double* evals, double* vecs, double* discarded) {
+    g_err.clear();
+    try {
+        if (!rho || !dims || !offsets || !kept || !evals || !vecs || !discarded) throw Error(DMRG_ERR_ARG, "NULL argument");
+        if (n_sec < 0 || M < 0) throw Error(DMRG_ERR_ARG, "n_sec and M must be >= 0");
+        int64_t pos = 0;
+        for (int i = 0; i < n_sec; ++i) {
+            if (dims[i] < 0 || offsets[i] != pos) throw Error(DMRG_ERR_SHAPE, "offsets must be the prefix sums of dims^2");
+            pos += (int64_t)dims[i] * dims[i];
+        }
+        // per sector: eigenpairs in descending eigenvalue order, each vector's largest-magnitude
+        // component positive; candidates ordered by (eigenvalue descending, sector, position)
+        struct Cand { double w; int sec, pos; };
+        std::vector<Cand> cand;
+        int64_t eoff = 0;
+        double trace = 0.0;
+        for (int i = 0; i < n_sec; ++i) {
+            const int n = dims[i];
+            std::vector<double> A(rho + offsets[i], rho + offsets[i] + (int64_t)n * n), V;
+            for (double v : A) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite density matrix element");
+            for (int r = 0; r < n; ++r)
+                for (int c = 0; c < r; ++c) {            // symmetrize: the input is psi psi^T up to rounding
+                    const double m = 0.5 * (A[(size_t)r * n + c] + A[(size_t)c * n + r]);
+                    A[(size_t)r * n + c] = A[(size_t)c * n + r] = m;
+                }
+            for (int r = 0; r < n; ++r) trace += A[(size_t)r * n + r];
+            jacobi_eigen(A, V, n);
+            std::vector<int> order(n);
+            for (int k = 0; k < n; ++k) order[k] = k;
+            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+                return A[(size_t)x * n + x] > A[(size_t)y * n + y];
+            });
+            double* out = vecs + offsets[i];
+            for (int k = 0; k < n; ++k) {
+                const int src = order[k];
+                int big = 0;
+                for (int r = 1; r < n; ++r)
+                    if (std::fabs(V[(size_t)r * n + src]) > std::fabs(V[(size_t)big * n + src])) big = r;
+                const double sg = V[(size_t)big * n + src] < 0.0 ? -1.0 : 1.0;
+                for (int r = 0; r < n; ++r) out[(size_t)r * n + k] = sg * V[(size_t)r * n + src];
+                evals[eoff + k] = A[(size_t)src * n + src];
+                cand.push_back({A[(size_t)src * n + src], i, k});
+            }
+            eoff += n;
+            kept[i] = 0;
+        }
+        std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
+            if (x.w != y.w) return x.w > y.w;
+            if (x.sec != y.sec) return x.sec < y.sec;
+            return x.pos < y.pos;
+        });
+        double sum = 0.0;
+        const size_t take = std::min(cand.size(), (size_t)M);
+        for (size_t k = 0; k < take; ++k) { ++kept[cand[k].sec]; sum += cand[k].w; }
+        *discarded = trace - sum;
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
 // ---------------------------------------------------------------- batching and tuning
 extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out) {
     g_err.clear();

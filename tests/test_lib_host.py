@@ -220,3 +220,80 @@ def test_rdm_left_layout_matches_oracle(case):
     with pytest.raises(DmrgError) as e:
         hop.rdm_left(Fake(), Fake())
     assert e.value.status == -7
+
+
+@pytest.fixture(scope="module")
+def rho_case():
+    """Oracle rho^L of a random psi over synthetic blocks (L = 12, M = 60), in the sector order of
+    dmrg_rdm_left_layout."""
+    from oracle import renorm
+    from oracle.layout import Layout
+    h, eri, left, right, na, nb, site = synth(12, 60, 1.2, 5)
+    x = random_vector(Layout(left, right, na, nb).size, 13)
+    x /= np.linalg.norm(x)
+    rho = renorm.rdm_left(renorm.psi_matrices(Layout(left, right, na, nb), left, right, na, nb, x))
+    dims = np.array([r.shape[0] for r in rho.values()], dtype=np.int32)
+    flat = np.concatenate([r.ravel() for r in rho.values()])
+    return rho, dims, flat
+
+
+def test_truncate_eigenpairs_match_dense_eigh(rho_case):
+    rho, dims, flat = rho_case
+    kept, evals, vecs, disc = lib_mod.truncate(flat, dims, 10 ** 6)
+    assert np.array_equal(kept, dims) and abs(disc) < 1e-13
+    scale = max(float(np.abs(r).max()) for r in rho.values())
+    for (q, r), w, V in zip(rho.items(), evals, vecs):
+        assert np.all(np.diff(w) <= 0)
+        assert np.abs(w - np.sort(np.linalg.eigvalsh(r))[::-1]).max(initial=0) < 1e-13 * scale
+        assert np.abs(V.T @ V - np.eye(len(w))).max(initial=0) < 1e-12
+        assert np.abs(r @ V - V * w).max(initial=0) < 1e-12 * scale
+        for k in range(len(w)):
+            assert V[np.argmax(np.abs(V[:, k])), k] > 0
+
+
+@pytest.mark.parametrize("M", [0, 1, 5, 17, 40, 60])
+def test_truncate_matches_oracle_cut(rho_case, M):
+    """Kept counts, discarded weight and the kept projector of each sector equal the oracle's global
+    M-cut (M up to the rank, where the cut falls in a gap)."""
+    from oracle import renorm
+    rho, dims, flat = rho_case
+    kept, evals, vecs, disc = lib_mod.truncate(flat, dims, M)
+    O, okept, odisc = renorm.select(rho, M)
+    assert int(kept.sum()) == M and abs(disc - odisc) < 1e-13
+    for i, q in enumerate(rho):
+        k = int(kept[i])
+        assert k == (O[q].shape[1] if q in O else 0), q
+        if k:
+            P = vecs[i][:, :k] @ vecs[i][:, :k].T
+            assert np.abs(P - O[q] @ O[q].T).max() < 1e-9
+
+
+def test_truncate_rejects_bad_arguments(rho_case):
+    rho, dims, flat = rho_case
+    with pytest.raises(DmrgError) as e:
+        lib_mod.truncate(flat, dims, -1)
+    assert e.value.status == -1
+    bad = flat.copy()
+    bad[0] = np.nan
+    with pytest.raises(DmrgError) as e:
+        lib_mod.truncate(bad, dims, 3)
+    assert e.value.status == -5
+
+
+def test_truncate_at_benchmark_size():
+    """L = 24, M = 1024 (77 sectors, up to 284 states): the same kept counts and discarded weight as
+    the oracle's cut to M = 1024."""
+    from oracle import renorm
+    from oracle.layout import Layout
+    from dmrg_inputs.synthetic import synthetic_problem
+    h, eri, left, right, site = synthetic_problem(24, 12, 12, 1024, 1.5, 1)
+    lay = Layout(left, right, 12, 12)
+    x = random_vector(lay.size, 1)
+    x /= np.linalg.norm(x)
+    rho = renorm.rdm_left(renorm.psi_matrices(lay, left, right, 12, 12, x))
+    dims = np.array([r.shape[0] for r in rho.values()], dtype=np.int32)
+    kept, evals, vecs, disc = lib_mod.truncate(np.concatenate([r.ravel() for r in rho.values()]), dims, 1024)
+    O, _, odisc = renorm.select(rho, 1024)
+    assert len(dims) == 77 and int(dims.max()) == 284
+    assert abs(disc - odisc) < 1e-12
+    assert [int(k) for k in kept] == [O[q].shape[1] if q in O else 0 for q in rho]
