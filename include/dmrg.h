@@ -206,6 +206,26 @@ dmrg_status dmrg_rdm_left(dmrg_hop* hop, const double* psi, double* rho, int64_t
 dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int32_t* dims, const int64_t* offsets, int32_t M,
                           int32_t* kept, double* evals, double* vecs, double* discarded);
 
+/* Eq. renorm_mat per sector block: out_b = O[sec_out[b]]^T A_b O[sec_in[b]] for n_blk operator blocks
+ * given in an enlarged (untruncated) basis of n_sec sectors. FP64 on `device`, two passes (T = A O_in,
+ * then O_out^T T), each element summed in a fixed order.
+ * Host arrays: dims, kept (n_sec: sector dimension, kept states, 0 <= kept <= dims), o_off (n_sec:
+ * offset of sector s's renormalization matrix in O), sec_out, sec_in (n_blk sector indices), a_off,
+ * out_off (n_blk offsets). Device arrays: O (o_len doubles; sector s at o_off[s], row-major dims[s] x
+ * kept[s], columns = kept eigenvectors, e.g. the leading columns of dmrg_truncate's vecs), A (a_len;
+ * block b at a_off[b], row-major dims[sec_out] x dims[sec_in]), out (out_len; block b at out_off[b],
+ * row-major kept[sec_out] x kept[sec_in]; blocks must not overlap each other, A or O). Blocks with
+ * nothing kept on a side are empty and skipped. Every index and extent is checked against the
+ * lengths before launch. Synchronizes `stream` before returning (allocates and frees the
+ * intermediate T). Errors: DMRG_ERR_ARG (NULL, negative counts, sector index, kept > dims),
+ * DMRG_ERR_SHAPE (a block outside its buffer), DMRG_ERR_UNSUPPORTED (block above 2^31 elements),
+ * DMRG_ERR_DEVICE. */
+dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t* dims, const int32_t* kept,
+                                    const int64_t* o_off, const double* O, int64_t o_len, int32_t n_blk,
+                                    const int32_t* sec_out, const int32_t* sec_in, const int64_t* a_off,
+                                    const double* A, int64_t a_len, const int64_t* out_off, double* out,
+                                    int64_t out_len, void* stream);
+
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs (restarting from the

@@ -85,6 +85,10 @@ lib.dmrg_rdm_left.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c
 lib.dmrg_rdm_left.restype = C.c_int32
 lib.dmrg_truncate.argtypes = [f64p, C.c_int32, i32p, i64p, C.c_int32, i32p, f64p, f64p, f64p]
 lib.dmrg_truncate.restype = C.c_int32
+lib.dmrg_renormalize_blocks.argtypes = [C.c_int32, C.c_int32, i32p, i32p, i64p, C.c_void_p, C.c_int64, C.c_int32,
+                                        i32p, i32p, i64p, C.c_void_p, C.c_int64, i64p, C.c_void_p, C.c_int64,
+                                        C.c_void_p]
+lib.dmrg_renormalize_blocks.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
 lib.dmrg_davidson.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
@@ -167,6 +171,22 @@ def truncate(rho, dims, M):
     e0 = np.concatenate([[0], np.cumsum(dims)])
     return (kept, [evals[e0[i]:e0[i + 1]] for i in range(dims.size)],
             [vecs[off[i]:off[i + 1]].reshape(dims[i], dims[i]) for i in range(dims.size)], float(disc[0]))
+
+
+def renormalize_blocks(dims, kept, o_off, O, sec_out, sec_in, a_off, A, out_off, out, device=0, stream=None):
+    """dmrg_renormalize_blocks: index arrays on the host (numpy), O, A, out device tensors (float64)."""
+    dims, kept = np.ascontiguousarray(dims, dtype=np.int32), np.ascontiguousarray(kept, dtype=np.int32)
+    o_off = np.ascontiguousarray(o_off, dtype=np.int64)
+    sec_out, sec_in = np.ascontiguousarray(sec_out, dtype=np.int32), np.ascontiguousarray(sec_in, dtype=np.int32)
+    a_off, out_off = np.ascontiguousarray(a_off, dtype=np.int64), np.ascontiguousarray(out_off, dtype=np.int64)
+    for t in (O, A, out):
+        assert t.is_contiguous()
+    _check(lib.dmrg_renormalize_blocks(int(device), int(dims.size), _ptr(dims, C.c_int32), _ptr(kept, C.c_int32),
+                                       _ptr(o_off, C.c_int64), C.c_void_p(O.data_ptr()), int(O.numel()),
+                                       int(sec_out.size), _ptr(sec_out, C.c_int32), _ptr(sec_in, C.c_int32),
+                                       _ptr(a_off, C.c_int64), C.c_void_p(A.data_ptr()), int(A.numel()),
+                                       _ptr(out_off, C.c_int64), C.c_void_p(out.data_ptr()), int(out.numel()),
+                                       _stream_ptr(stream)))
 
 
 class _BlockMarshal:

@@ -2197,6 +2197,74 @@ extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int
     }
 }
 
+extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t* dims, const int32_t* kept,
+                                               const int64_t* o_off, const double* O, int64_t o_len, int32_t n_blk,
+                                               const int32_t* sec_out, const int32_t* sec_in, const int64_t* a_off,
+                                               const double* A, int64_t a_len, const int64_t* out_off, double* out,
+                                               int64_t out_len, void* stream) {
+    g_err.clear();
+    try {
+        if (n_sec < 0 || n_blk < 0) throw Error(DMRG_ERR_ARG, "n_sec and n_blk must be >= 0");
+        if (n_blk == 0) return DMRG_OK;
+        if (!dims || !kept || !o_off || !O || !sec_out || !sec_in || !a_off || !A || !out_off || !out)
+            throw Error(DMRG_ERR_ARG, "NULL argument");
+        for (int s = 0; s < n_sec; ++s) {
+            if (dims[s] < 0 || kept[s] < 0 || kept[s] > dims[s]) throw Error(DMRG_ERR_ARG, "need 0 <= kept <= dims");
+            if (o_off[s] < 0 || o_off[s] + (int64_t)dims[s] * kept[s] > o_len)
+                throw Error(DMRG_ERR_SHAPE, "renormalization matrix outside O");
+        }
+        std::vector<dmrg::RenormItem> items;
+        int64_t t_len = 0;
+        for (int b = 0; b < n_blk; ++b) {
+            const int so = sec_out[b], si = sec_in[b];
+            if (so < 0 || so >= n_sec || si < 0 || si >= n_sec) throw Error(DMRG_ERR_ARG, "sector index out of range");
+            const int64_t rows = dims[so], cols = dims[si], ko = kept[so], ki = kept[si];
+            if (a_off[b] < 0 || a_off[b] + rows * cols > a_len) throw Error(DMRG_ERR_SHAPE, "operator block outside A");
+            if (out_off[b] < 0 || out_off[b] + ko * ki > out_len) throw Error(DMRG_ERR_SHAPE, "output block outside out");
+            if (rows * ki >= INT32_MAX || ko * ki >= INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "sector block too large");
+            if (ko == 0 || ki == 0) continue;                  // nothing kept on one side: empty block
+            dmrg::RenormItem it{};
+            it.a_off = a_off[b];
+            it.t_off = t_len;
+            it.out_off = out_off[b];
+            it.oo_off = o_off[so];
+            it.oi_off = o_off[si];
+            it.rows = (int32_t)rows;
+            it.cols = (int32_t)cols;
+            it.k_out = (int32_t)ko;
+            it.k_in = (int32_t)ki;
+            items.push_back(it);
+            t_len += rows * ki;
+        }
+        if (items.empty()) return DMRG_OK;
+        if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many blocks");
+        HIPCHK(hipSetDevice(device));
+        hipStream_t s = (hipStream_t)stream;
+        void *d_items = nullptr, *d_t = nullptr;
+        try {
+            HIPCHK(hipMalloc(&d_items, items.size() * sizeof(dmrg::RenormItem)));
+            HIPCHK(hipMalloc(&d_t, (size_t)std::max<int64_t>(1, t_len) * sizeof(double)));
+            HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RenormItem), hipMemcpyHostToDevice, s));
+            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), A, O,
+                                            static_cast<double*>(d_t), out, s));
+            HIPCHK(hipStreamSynchronize(s));   // the work list and T end here
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            if (d_items) (void)hipFree(d_items);
+            if (d_t) (void)hipFree(d_t);
+            throw;
+        }
+        (void)hipFree(d_items);
+        (void)hipFree(d_t);
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    } catch (const std::bad_alloc&) {
+        g_err = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
 // ---------------------------------------------------------------- batching and tuning
 extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out) {
     g_err.clear();

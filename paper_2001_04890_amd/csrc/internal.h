@@ -250,6 +250,16 @@ struct RdmItem {
 };
 hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
                            const double* psi, double* rho, hipStream_t s);
+
+// Eq. renorm_mat per sector block, out = O_out^T A O_in, in two passes over the same items:
+// pass 1 T = A O_in (rows_a x k_in, at t_off), pass 2 out = O_out^T T (k_out x k_in, at out_off).
+// A is rows_a x cols_a (= O_out rows x O_in rows), row-major; O matrices are row-major (rows x k).
+struct RenormItem {
+    int64_t a_off, t_off, out_off, oo_off, oi_off;
+    int32_t rows, cols, k_out, k_in;
+};
+hipError_t launch_renormalize(const RenormItem* items, int n_items, const double* A, const double* O, double* T,
+                              double* out, hipStream_t s);
 // Tiled split-BF16 kernels (hpsi_lds.hip).
 hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).

@@ -719,4 +719,45 @@ hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gbl
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ renormalized operator blocks
+// Eq. renorm_mat, FP64, one workgroup per sector block and pass; each thread owns output elements and
+// sums in a fixed order.
+__global__ void k_renorm_t(const RenormItem* __restrict__ items, const double* __restrict__ A,
+                           const double* __restrict__ O, double* __restrict__ T) {
+    const RenormItem it = items[blockIdx.x];
+    const int n = it.rows * it.k_in;
+    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+        const int r = e / it.k_in, j = e - (e / it.k_in) * it.k_in;
+        const double* a = A + it.a_off + (int64_t)r * it.cols;
+        const double* o = O + it.oi_off + j;                    // column j of O_in, stride k_in
+        double acc = 0.0;
+        for (int c = 0; c < it.cols; ++c) acc = fma(a[c], o[(int64_t)c * it.k_in], acc);
+        T[it.t_off + e] = acc;
+    }
+}
+
+__global__ void k_renorm_out(const RenormItem* __restrict__ items, const double* __restrict__ O,
+                             const double* __restrict__ T, double* __restrict__ out) {
+    const RenormItem it = items[blockIdx.x];
+    const int n = it.k_out * it.k_in;
+    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+        const int i = e / it.k_in, j = e - (e / it.k_in) * it.k_in;
+        const double* o = O + it.oo_off + i;                    // column i of O_out, stride k_out
+        const double* t = T + it.t_off + j;                     // column j of T, stride k_in
+        double acc = 0.0;
+        for (int r = 0; r < it.rows; ++r) acc = fma(o[(int64_t)r * it.k_out], t[(int64_t)r * it.k_in], acc);
+        out[it.out_off + e] = acc;
+    }
+}
+
+hipError_t launch_renormalize(const RenormItem* items, int n_items, const double* A, const double* O, double* T,
+                              double* out, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_renorm_t, dim3((unsigned)n_items), dim3(256), 0, s, items, A, O, T);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_renorm_out, dim3((unsigned)n_items), dim3(256), 0, s, items, O, T, out);
+    return hipGetLastError();
+}
+
 }  // namespace dmrg

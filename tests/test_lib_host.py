@@ -297,3 +297,28 @@ def test_truncate_at_benchmark_size():
     assert len(dims) == 77 and int(dims.max()) == 284
     assert abs(disc - odisc) < 1e-12
     assert [int(k) for k in kept] == [O[q].shape[1] if q in O else 0 for q in rho]
+
+
+def test_renormalize_blocks_checks_arguments_before_any_device_work():
+    class Fake:
+        def __init__(self, n):
+            self.n = n
+
+        def is_contiguous(self):
+            return True
+
+        def data_ptr(self):
+            return 16
+
+        def numel(self):
+            return self.n
+
+    dims, kept, o_off = [3, 4], [2, 4], [0, 6]
+    ok = dict(dims=dims, kept=kept, o_off=o_off, O=Fake(22), sec_out=[0, 1], sec_in=[1, 0], a_off=[0, 12],
+              A=Fake(24), out_off=[0, 8], out=Fake(16))
+    for change, status in (({"sec_out": [0, 2]}, -1), ({"kept": [4, 4]}, -1), ({"A": Fake(23)}, -2),
+                           ({"out": Fake(15)}, -2), ({"O": Fake(21)}, -2), ({"a_off": [-1, 12]}, -2)):
+        with pytest.raises(DmrgError) as e:
+            lib_mod.renormalize_blocks(**{**ok, **change})
+        assert e.value.status == status, change
+    lib_mod.renormalize_blocks(**{**ok, "sec_out": [], "sec_in": [], "a_off": [], "out_off": []})   # no blocks: no-op
