@@ -189,6 +189,14 @@ dmrg_status dmrg_rdm_left_layout(const dmrg_hop* hop, int32_t* n_sec, int32_t* q
                                  int64_t* offsets);
 dmrg_status dmrg_rdm_left(dmrg_hop* hop, const double* psi, double* rho, int64_t rho_len, void* stream);
 
+/* The same for the enlarged right block (backward sweeps): rho^R = psi^T psi, block diagonal in the
+ * enlarged-right quantum number q = qn(s_r) + qn(d), sectors ascending. Rows of sector q: the pairs
+ * (s_r, d) in (s_r, d) order, each with the dim(d) states of right sector d, including pairs that no
+ * psi block reaches. Arguments, layout of rho, determinism, synchronization and errors as above. */
+dmrg_status dmrg_rdm_right_layout(const dmrg_hop* hop, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                                  int64_t* offsets);
+dmrg_status dmrg_rdm_right(dmrg_hop* hop, const double* psi, double* rho, int64_t rho_len, void* stream);
+
 /* The truncation of Section 2.1: the M eigenvectors of a block-diagonal density matrix with the
  * largest eigenvalues (they form the renormalization matrix of Eq. renorm). Host routine, FP64: each
  * sector by the cyclic Jacobi method (off-diagonal norm below 1e-15 of the Frobenius norm).

@@ -83,6 +83,10 @@ lib.dmrg_rdm_left_layout.argtypes = [C.c_void_p, i32p, i32p, i32p, i64p]
 lib.dmrg_rdm_left_layout.restype = C.c_int32
 lib.dmrg_rdm_left.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
 lib.dmrg_rdm_left.restype = C.c_int32
+lib.dmrg_rdm_right_layout.argtypes = [C.c_void_p, i32p, i32p, i32p, i64p]
+lib.dmrg_rdm_right_layout.restype = C.c_int32
+lib.dmrg_rdm_right.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+lib.dmrg_rdm_right.restype = C.c_int32
 lib.dmrg_truncate.argtypes = [f64p, C.c_int32, i32p, i64p, C.c_int32, i32p, f64p, f64p, f64p]
 lib.dmrg_truncate.restype = C.c_int32
 lib.dmrg_renormalize_blocks.argtypes = [C.c_int32, C.c_int32, i32p, i32p, i64p, C.c_void_p, C.c_int64, C.c_int32,
@@ -313,22 +317,35 @@ class Hop:
         assert d.numel() == self.n_coeff and d.is_contiguous()
         _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
 
-    def rdm_left_layout(self):
-        """Sectors of rho^L: (qn (n, 2), dims (n,), offsets (n + 1,)) from dmrg_rdm_left_layout."""
+    def _rdm_layout(self, fn):
         n = C.c_int32(0)
-        _check(lib.dmrg_rdm_left_layout(self._h, C.byref(n), None, None, None))
+        _check(fn(self._h, C.byref(n), None, None, None))
         qn = np.zeros(2 * n.value, dtype=np.int32)
         dims = np.zeros(n.value, dtype=np.int32)
         off = np.zeros(n.value + 1, dtype=np.int64)
-        _check(lib.dmrg_rdm_left_layout(self._h, C.byref(n), _ptr(qn, C.c_int32), _ptr(dims, C.c_int32),
-                                        _ptr(off, C.c_int64)))
+        _check(fn(self._h, C.byref(n), _ptr(qn, C.c_int32), _ptr(dims, C.c_int32), _ptr(off, C.c_int64)))
         return qn.reshape(-1, 2), dims, off
+
+    def _rdm(self, fn, psi, rho, stream):
+        assert psi.numel() == self.n_coeff and psi.is_contiguous() and rho.is_contiguous()
+        _check(fn(self._h, C.c_void_p(psi.data_ptr()), C.c_void_p(rho.data_ptr()), int(rho.numel()),
+                  _stream_ptr(stream)))
+
+    def rdm_left_layout(self):
+        """Sectors of rho^L: (qn (n, 2), dims (n,), offsets (n + 1,)) from dmrg_rdm_left_layout."""
+        return self._rdm_layout(lib.dmrg_rdm_left_layout)
 
     def rdm_left(self, psi, rho, stream=None):
         """rho^L = psi psi^T per sector (dmrg_rdm_left) into the device buffer rho."""
-        assert psi.numel() == self.n_coeff and psi.is_contiguous() and rho.is_contiguous()
-        _check(lib.dmrg_rdm_left(self._h, C.c_void_p(psi.data_ptr()), C.c_void_p(rho.data_ptr()),
-                                 int(rho.numel()), _stream_ptr(stream)))
+        self._rdm(lib.dmrg_rdm_left, psi, rho, stream)
+
+    def rdm_right_layout(self):
+        """Sectors of rho^R (dmrg_rdm_right_layout)."""
+        return self._rdm_layout(lib.dmrg_rdm_right_layout)
+
+    def rdm_right(self, psi, rho, stream=None):
+        """rho^R = psi^T psi per sector (dmrg_rdm_right) into the device buffer rho."""
+        self._rdm(lib.dmrg_rdm_right, psi, rho, stream)
 
     def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
                  split_tol=1e-5, mlp=None, stream=None, use_graph=False):

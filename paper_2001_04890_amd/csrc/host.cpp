@@ -1944,30 +1944,39 @@ extern "C" dmrg_status dmrg_hop_diagonal(dmrg_hop* H, double* d, void* stream) {
     }
 }
 
-// ---------------------------------------------------------------- reduced density matrix
+// ---------------------------------------------------------------- reduced density matrices
 namespace {
-// Enlarged-left sectors q = qn(a) + qn(b) (Section 2.1: psi read as the matrix psi_{(l s_l),(s_r r)}) in
-// ascending (n_alpha, n_beta); the rows of sector q are the pairs (a, b) in (a, b) order, each with the
-// m_a states of left sector a, including pairs that no psi block reaches (zero rows).
+// psi read as the matrix psi_{(l s_l),(s_r r)} (Section 2.1). Left side: enlarged-left sectors
+// q = qn(a) + qn(b), groups (a, b) in (a, b) order with the m_a states of sector a; right side:
+// enlarged-right sectors q = qn(c) + qn(d), groups (c, d) in (c, d) order with the m_d states of
+// sector d. Sectors ascend in (n_alpha, n_beta); groups that no psi block reaches are included (zero
+// rows). groups[i] holds (x, y, first row) with (x, y) = (a, b) or (c, d).
 struct RdmLayout {
     std::vector<std::pair<int, int>> qn;
     std::vector<int> dim;
     std::vector<int64_t> off;                                  // n_sec + 1: dense dim x dim blocks
-    std::vector<std::vector<std::array<int, 3>>> groups;       // per sector: (a, b, first row)
+    std::vector<std::vector<std::array<int, 3>>> groups;
 };
 
-RdmLayout rdm_layout(const dmrg_hop& H) {
+RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
     if (H.n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: density matrices are per problem");
     std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> groups;
     std::map<std::pair<int, int>, int> dims;
-    for (int a = 0; a < H.left.n_sec; ++a) {
-        if (H.left.dim[a] <= 0) continue;
-        for (int b = 0; b < 4; ++b) {
-            const std::pair<int, int> q{H.left.qa[a] + kSiteQn[b][0], H.left.qb[a] + kSiteQn[b][1]};
-            int& d = dims[q];
-            groups[q].push_back({a, b, d});
-            d += H.left.dim[a];
-        }
+    const BlockIn& B = right ? H.right : H.left;
+    auto add = [&](int x, int y, int sec, int site) {
+        const std::pair<int, int> q{B.qa[sec] + kSiteQn[site][0], B.qb[sec] + kSiteQn[site][1]};
+        int& d = dims[q];
+        groups[q].push_back({x, y, d});
+        d += B.dim[sec];
+    };
+    if (!right) {
+        for (int a = 0; a < B.n_sec; ++a)
+            if (B.dim[a] > 0)
+                for (int b = 0; b < 4; ++b) add(a, b, a, b);
+    } else {
+        for (int c = 0; c < 4; ++c)
+            for (int d = 0; d < B.n_sec; ++d)
+                if (B.dim[d] > 0) add(c, d, d, c);
     }
     RdmLayout R;
     R.off.push_back(0);
@@ -1980,14 +1989,32 @@ RdmLayout rdm_layout(const dmrg_hop& H) {
     }
     return R;
 }
-}  // namespace
 
-extern "C" dmrg_status dmrg_rdm_left_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
-                                            int64_t* offsets) {
+// psi blocks of one group, in the order of the other side's groups: left group (a, b) -> blocks
+// (a, b, c, d) for c = 0..3; right group (c, d) -> blocks (a, b, c, d) for (a, b) in (a, b) order.
+std::vector<int> rdm_group_blocks(const dmrg_hop& H, bool right, int x, int y) {
+    std::vector<int> ids;
+    if (!right) {
+        for (int c = 0; c < 4; ++c) {
+            const int id = H.blk_index[(x * 4 + y) * 4 + c];
+            if (id >= 0) ids.push_back(id);
+        }
+    } else {
+        for (int a = 0; a < H.left.n_sec; ++a)
+            for (int b = 0; b < 4; ++b) {
+                const int id = H.blk_index[(a * 4 + b) * 4 + x];
+                if (id >= 0 && H.blk[id][3] == y) ids.push_back(id);
+            }
+    }
+    return ids;
+}
+
+dmrg_status rdm_layout_entry(const dmrg_hop* H, bool right, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                             int64_t* offsets) {
     g_err.clear();
     try {
         if (!H || !n_sec) throw Error(DMRG_ERR_ARG, "NULL argument");
-        const RdmLayout R = rdm_layout(*H);
+        const RdmLayout R = rdm_layout(*H, right);
         *n_sec = (int32_t)R.dim.size();
         for (size_t i = 0; i < R.dim.size(); ++i) {
             if (qn) { qn[2 * i] = R.qn[i].first; qn[2 * i + 1] = R.qn[i].second; }
@@ -2001,49 +2028,48 @@ extern "C" dmrg_status dmrg_rdm_left_layout(const dmrg_hop* H, int32_t* n_sec, i
     }
 }
 
-extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
+dmrg_status rdm_entry(dmrg_hop* H, bool right, const double* psi, double* rho, int64_t rho_len, void* stream) {
     g_err.clear();
     try {
         if (!H || !psi || !rho) throw Error(DMRG_ERR_ARG, "NULL argument");
         if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
-        const RdmLayout R = rdm_layout(*H);
+        const RdmLayout R = rdm_layout(*H, right);
         if (rho_len != R.off.back()) throw Error(DMRG_ERR_SHAPE, "rho_len must be the sum of dim_q^2 of the sectors");
-        // per row group: the psi blocks of its column groups c = 0..3 that exist; within a sector these
-        // are the same c (the right sector is fixed by q and c), checked below
+        // per group: its psi blocks; within a sector every group has the same inner dimensions
+        // (m_d on the left side, m_a on the right), checked here
         std::vector<dmrg::RdmItem> items;
         std::vector<int64_t> gblk;
-        std::vector<int32_t> cdmd;
+        std::vector<int32_t> inner;
+        const BlockIn& B = right ? H->right : H->left;
         for (size_t qi = 0; qi < R.dim.size(); ++qi) {
             const auto& G = R.groups[qi];
-            const int cd0 = (int)cdmd.size();
+            const int in0 = (int)inner.size();
             std::vector<int> g0(G.size());
-            int n_cd = -1;
+            int n_in = -1;
             for (size_t k = 0; k < G.size(); ++k) {
                 g0[k] = (int)gblk.size();
-                int cnt = 0;
-                for (int c = 0; c < 4; ++c) {
-                    const int id = H->blk_index[(G[k][0] * 4 + G[k][1]) * 4 + c];
-                    if (id < 0) continue;
-                    if (k == 0) cdmd.push_back(H->blk_md[id]);
-                    else if (cnt >= n_cd || cdmd[cd0 + cnt] != H->blk_md[id])
-                        throw Error(DMRG_ERR_ARG, "internal: column groups differ within a sector");
-                    gblk.push_back(H->blk_off[id]);
-                    ++cnt;
+                const std::vector<int> ids = rdm_group_blocks(*H, right, G[k][0], G[k][1]);
+                if (k > 0 && (int)ids.size() != n_in)
+                    throw Error(DMRG_ERR_ARG, "internal: groups of a sector meet different blocks");
+                for (size_t t = 0; t < ids.size(); ++t) {
+                    const int m = right ? H->blk_ma[ids[t]] : H->blk_md[ids[t]];
+                    if (k == 0) inner.push_back(m);
+                    else if (inner[in0 + t] != m) throw Error(DMRG_ERR_ARG, "internal: groups of a sector meet different blocks");
+                    gblk.push_back(H->blk_off[ids[t]]);
                 }
-                if (k > 0 && cnt != n_cd) throw Error(DMRG_ERR_ARG, "internal: column groups differ within a sector");
-                n_cd = cnt;
+                n_in = (int)ids.size();
             }
             for (size_t k = 0; k < G.size(); ++k)
                 for (size_t k2 = 0; k2 < G.size(); ++k2) {
                     dmrg::RdmItem it{};
                     it.rho_off = R.off[qi] + (int64_t)G[k][2] * R.dim[qi] + G[k2][2];
                     it.ld = R.dim[qi];
-                    it.ma = H->left.dim[G[k][0]];
-                    it.ma2 = H->left.dim[G[k2][0]];
+                    it.ma = B.dim[right ? G[k][1] : G[k][0]];
+                    it.ma2 = B.dim[right ? G[k2][1] : G[k2][0]];
                     it.g = g0[k];
                     it.g2 = g0[k2];
-                    it.cd = cd0;
-                    it.n_cd = n_cd;
+                    it.cd = in0;
+                    it.n_cd = n_in;
                     items.push_back(it);
                 }
         }
@@ -2059,16 +2085,18 @@ extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho
         try {
             HIPCHK(hipMalloc(&d_items, std::max<size_t>(1, items.size()) * sizeof(dmrg::RdmItem)));
             HIPCHK(hipMalloc(&d_g, std::max<size_t>(1, gblk.size()) * sizeof(int64_t)));
-            HIPCHK(hipMalloc(&d_c, std::max<size_t>(1, cdmd.size()) * sizeof(int32_t)));
+            HIPCHK(hipMalloc(&d_c, std::max<size_t>(1, inner.size()) * sizeof(int32_t)));
             if (!items.empty())
                 HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RdmItem), hipMemcpyHostToDevice, s));
             if (!gblk.empty())
                 HIPCHK(hipMemcpyAsync(d_g, gblk.data(), gblk.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            if (!cdmd.empty())
-                HIPCHK(hipMemcpyAsync(d_c, cdmd.data(), cdmd.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            HIPCHK(dmrg::launch_rdm_left(static_cast<const dmrg::RdmItem*>(d_items), (int)items.size(),
-                                         static_cast<const int64_t*>(d_g), static_cast<const int32_t*>(d_c),
-                                         psi, rho, s));
+            if (!inner.empty())
+                HIPCHK(hipMemcpyAsync(d_c, inner.data(), inner.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+            const auto* di = static_cast<const dmrg::RdmItem*>(d_items);
+            const auto* dg = static_cast<const int64_t*>(d_g);
+            const auto* dc = static_cast<const int32_t*>(d_c);
+            if (right) HIPCHK(dmrg::launch_rdm_right(di, (int)items.size(), dg, dc, psi, rho, s));
+            else HIPCHK(dmrg::launch_rdm_left(di, (int)items.size(), dg, dc, psi, rho, s));
             HIPCHK(hipStreamSynchronize(s));   // the host work lists and scratch end here
         } catch (...) {
             (void)hipStreamSynchronize(s);
@@ -2083,6 +2111,25 @@ extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho
         g_err = "host allocation failed";
         return DMRG_ERR_NOMEM;
     }
+}
+}  // namespace
+
+extern "C" dmrg_status dmrg_rdm_left_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                                            int64_t* offsets) {
+    return rdm_layout_entry(H, false, n_sec, qn, dims, offsets);
+}
+
+extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
+    return rdm_entry(H, false, psi, rho, rho_len, stream);
+}
+
+extern "C" dmrg_status dmrg_rdm_right_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
+                                             int64_t* offsets) {
+    return rdm_layout_entry(H, true, n_sec, qn, dims, offsets);
+}
+
+extern "C" dmrg_status dmrg_rdm_right(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
+    return rdm_entry(H, true, psi, rho, rho_len, stream);
 }
 
 namespace {

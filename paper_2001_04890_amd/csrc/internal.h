@@ -250,6 +250,10 @@ struct RdmItem {
 };
 hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
                            const double* psi, double* rho, hipStream_t s);
+// rho^R = psi^T psi with the same items: here ma, ma2 are the column counts of the two psi blocks of
+// each term (their m_d), cdmd[cd + k] the k-th row count (m_a), and the sum runs over rows.
+hipError_t launch_rdm_right(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
+                            const double* psi, double* rho, hipStream_t s);
 
 // Eq. renorm_mat per sector block, out = O_out^T A O_in, in two passes over the same items:
 // pass 1 T = A O_in (rows_a x k_in, at t_off), pass 2 out = O_out^T T (k_out x k_in, at out_off).

@@ -719,6 +719,33 @@ hipError_t launch_rdm_left(const RdmItem* items, int n_items, const int64_t* gbl
     return hipGetLastError();
 }
 
+// rho^R = psi^T psi per enlarged-right sector: element (r, r2) sums X_k[l][r] X2_k[l][r2] over the
+// sector's row groups k and their rows l (columns r of blocks with ma columns, r2 of blocks with ma2).
+__global__ void k_rdm_right(const RdmItem* __restrict__ items, const int64_t* __restrict__ gblk,
+                            const int32_t* __restrict__ rows, const double* __restrict__ psi,
+                            double* __restrict__ rho) {
+    const RdmItem it = items[blockIdx.x];
+    const int n = it.ma * it.ma2;
+    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+        const int r = e / it.ma2, r2 = e - (e / it.ma2) * it.ma2;
+        double acc = 0.0;
+        for (int k = 0; k < it.n_cd; ++k) {
+            const int ml = rows[it.cd + k];
+            const double* x = psi + gblk[it.g + k] + r;
+            const double* y = psi + gblk[it.g2 + k] + r2;
+            for (int l = 0; l < ml; ++l) acc = fma(x[(int64_t)l * it.ma], y[(int64_t)l * it.ma2], acc);
+        }
+        rho[it.rho_off + (int64_t)r * it.ld + r2] = acc;
+    }
+}
+
+hipError_t launch_rdm_right(const RdmItem* items, int n_items, const int64_t* gblk, const int32_t* cdmd,
+                            const double* psi, double* rho, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rdm_right, dim3((unsigned)n_items), dim3(256), 0, s, items, gblk, cdmd, psi, rho);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ renormalized operator blocks
 // Eq. renorm_mat, FP64, one workgroup per sector block and pass; each thread owns output elements and
 // sums in a fixed order.

@@ -190,7 +190,8 @@ def test_bench_refuses_more_than_one_gpu():
 
 @pytest.mark.parametrize("case", ["exact8", "trunc10_odd", "synth12", "edge4_left_empty"])
 def test_rdm_left_layout_matches_oracle(case):
-    """dmrg_rdm_left_layout lists the enlarged-left sectors (ascending q) with the oracle's dimensions."""
+    """dmrg_rdm_left_layout / dmrg_rdm_right_layout list the enlarged-left / -right sectors (ascending q)
+    with the oracle's dimensions."""
     from oracle import renorm
     if case == "exact8":
         p = exact_problem(8, 0)
@@ -201,11 +202,13 @@ def test_rdm_left_layout_matches_oracle(case):
     else:
         p = synth(12, 60, 1.2, 5)
     hop = Hop(*p, device=-1)
-    qn, dims, off = hop.rdm_left_layout()
-    _, odims = renorm.enlarged_left_basis(p[2])
-    assert [tuple(int(v) for v in q) for q in qn] == list(odims)
-    assert dims.tolist() == list(odims.values())
-    assert off[0] == 0 and np.array_equal(np.diff(off), dims.astype(np.int64) ** 2)
+    for layout, basis, blk in ((hop.rdm_left_layout, renorm.enlarged_left_basis, p[2]),
+                               (hop.rdm_right_layout, renorm.enlarged_right_basis, p[3])):
+        qn, dims, off = layout()
+        _, odims = basis(blk)
+        assert [tuple(int(v) for v in q) for q in qn] == list(odims)
+        assert dims.tolist() == list(odims.values())
+        assert off[0] == 0 and np.array_equal(np.diff(off), dims.astype(np.int64) ** 2)
 
     class Fake:
         def numel(self):
@@ -217,9 +220,10 @@ def test_rdm_left_layout_matches_oracle(case):
         def data_ptr(self):
             return 16
 
-    with pytest.raises(DmrgError) as e:
-        hop.rdm_left(Fake(), Fake())
-    assert e.value.status == -7
+    for fn in (hop.rdm_left, hop.rdm_right):
+        with pytest.raises(DmrgError) as e:
+            fn(Fake(), Fake())
+        assert e.value.status == -7
 
 
 @pytest.fixture(scope="module")
