@@ -326,3 +326,15 @@ def test_renormalize_blocks_checks_arguments_before_any_device_work():
             lib_mod.renormalize_blocks(**{**ok, **change})
         assert e.value.status == status, change
     lib_mod.renormalize_blocks(**{**ok, "sec_out": [], "sec_in": [], "a_off": [], "out_off": []})   # no blocks: no-op
+
+
+def test_header_is_plain_c():
+    """include/dmrg.h compiles as C99 (the boundary is a C ABI) and as C++17, without warnings."""
+    import shutil
+    import subprocess
+    for cc, args in (("gcc", ["-std=c99", "-x", "c"]), ("g++", ["-std=c++17", "-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip(f"{cc} not available")
+        r = subprocess.run([cc, *args, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", HEADER],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
