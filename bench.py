@@ -47,7 +47,7 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-converge", action="store_true")
-    ap.add_argument("--workload", choices=["precision", "batch", "large", "precond"], default="precision",
+    ap.add_argument("--workload", choices=["precision", "batch", "large", "precond", "renorm"], default="precision",
                     help="precision: L=24 M=1024 split vs FP64 (default); batch: many uneven problems; "
                          "large: L=76 (57,56) M=6000, one GPU's share of the operator pairs; "
                          "precond: learned vs diagonal Davidson preconditioner at L=32 M=1500")
@@ -76,6 +76,8 @@ def main():
         return bench_large(args)
     if args.workload == "precond":
         return bench_precond(args)
+    if args.workload == "renorm":
+        return bench_renorm(args)
     dev = torch.device("cuda:0")
     L, M = args.L, args.M
     na = nb = L // 2
@@ -398,6 +400,76 @@ def bench_precond(args):
                        "bonds": bonds},
             "diag_iters": it_d, "mlp_iters": it_m, "diag_seconds": round(t_d, 2), "mlp_seconds": round(t_m, 2),
             "max_dE": max(r["dE"] for r in rows), "per_bond": rows, "train_seconds": round(t_train, 1)}
+    print(json.dumps(line), flush=True)
+
+
+def bench_renorm(args):
+    """Renormalization steps (Section 2.1, Eq. renorm_mat) at the H.psi workload's bond (L = 24, N = 24,
+    M = 1024, synthetic blocks sigma 1.5), FP64: rho^L of a normalized random psi on the GPU
+    (dmrg_rdm_left), its cut to M states on the host (dmrg_truncate), and O^T A O on the GPU
+    (dmrg_renormalize_blocks) for a random number-conserving operator of the enlarged block (one
+    block per sector). Wall time per call, host work lists included; not the headline benchmark."""
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_vector
+    from dmrg_inputs.synthetic import synthetic_problem
+    L, na, nb, M, sigma, seed = 24, 12, 12, 1024, 1.5, 1
+    h, eri, left, right, site = synthetic_problem(L, na, nb, M, sigma, seed)
+    stream = torch.cuda.current_stream()
+    hop = dm.Hop(h, eri, left, right, na, nb, site, device=0, stream=stream)
+    log("[bench] renorm: handle built")
+    x = random_vector(hop.n_coeff, 3)
+    x /= np.linalg.norm(x)
+    xd = torch.as_tensor(x, device="cuda:0")
+    qn, dims, off = hop.rdm_left_layout()
+    # coefficients per enlarged-left sector: rows_q x cols_q, so rho costs 2 rows_q coeff_q flops
+    qidx = {(int(q[0]), int(q[1])): i for i, q in enumerate(qn)}
+    coeff = np.zeros(len(dims))
+    for (a, b, c, d), (ma, md) in zip(hop.abcd, hop.dims):
+        q = (int(left.qn[a][0]) + (b in (1, 3)), int(left.qn[a][1]) + (b in (2, 3)))
+        coeff[qidx[q]] += ma * md
+    fl_rho = float(np.sum(2.0 * dims * coeff))
+    rho = torch.empty(int(off[-1]), dtype=torch.float64, device="cuda:0")
+    reps = max(3, args.kernel_reps)
+
+    def wall(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / n * 1e3
+
+    ms_rho = wall(lambda: hop.rdm_left(xd, rho, stream=stream), reps)
+    log(f"[bench] renorm: rho^L {ms_rho:.3f} ms")
+    flat = rho.cpu().numpy()
+    t = time.perf_counter()
+    kept, evals, vecs, disc = dm.truncate(flat, dims, M)
+    ms_cut = (time.perf_counter() - t) * 1e3
+    log(f"[bench] renorm: cut {ms_cut:.1f} ms, discarded {disc:.3e}")
+    Os = [vecs[i][:, :int(kept[i])] for i in range(len(dims))]
+    o_off = np.concatenate([[0], np.cumsum([o.size for o in Os])]).astype(np.int64)
+    O = torch.as_tensor(np.concatenate([o.ravel() for o in Os] + [np.zeros(1)]), device="cuda:0")
+    rng = np.random.default_rng(5)
+    A = torch.as_tensor(rng.normal(size=int(off[-1])), device="cuda:0")
+    out_off = np.concatenate([[0], np.cumsum(kept.astype(np.int64) ** 2)]).astype(np.int64)
+    out = torch.empty(int(out_off[-1]) + 1, dtype=torch.float64, device="cuda:0")
+    sec = np.arange(len(dims), dtype=np.int32)
+    fl_ren = float(np.sum(2.0 * dims * kept * (dims + kept)))
+    ms_ren = wall(lambda: dm.renormalize_blocks(dims, kept, o_off[:-1], O, sec, sec, off[:-1], A, out_off[:-1], out,
+                                                stream=stream), reps)
+    log(f"[bench] renorm: O^T A O {ms_ren:.3f} ms")
+    line = {"metric": "renormalization steps (rho^L, M-state cut, O^T A O), ms per call", "unit": "ms",
+            "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": f"renormalization at the two-site bond, L={L} N={na + nb} ({na},{nb}) M={M}, "
+                                   f"synthetic block operators sigma={sigma}, random normalized psi",
+                       "sectors": int(len(dims)), "max_sector": int(dims.max()), "enlarged_states": int(dims.sum()),
+                       "kept": int(kept.sum())},
+            "rho_left": {"ms": round(ms_rho, 4), "flops": fl_rho, "tflops": round(fl_rho / ms_rho / 1e9, 4)},
+            "cut_host": {"ms": round(ms_cut, 2), "discarded": disc},
+            "renorm_mat": {"ms": round(ms_ren, 4), "flops": fl_ren, "tflops": round(fl_ren / ms_ren / 1e9, 4),
+                           "blocks": int(len(dims))}}
     print(json.dumps(line), flush=True)
 
 
