@@ -2261,7 +2261,7 @@ extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, co
                 throw Error(DMRG_ERR_SHAPE, "renormalization matrix outside O");
         }
         std::vector<dmrg::RenormItem> items;
-        int64_t t_len = 0;
+        int64_t t_len = 0, max_t = 0, max_out = 0;
         for (int b = 0; b < n_blk; ++b) {
             const int so = sec_out[b], si = sec_in[b];
             if (so < 0 || so >= n_sec || si < 0 || si >= n_sec) throw Error(DMRG_ERR_ARG, "sector index out of range");
@@ -2282,6 +2282,8 @@ extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, co
             it.k_in = (int32_t)ki;
             items.push_back(it);
             t_len += rows * ki;
+            max_t = std::max(max_t, rows * ki);
+            max_out = std::max(max_out, ko * ki);
         }
         if (items.empty()) return DMRG_OK;
         if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many blocks");
@@ -2292,8 +2294,8 @@ extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, co
             HIPCHK(hipMalloc(&d_items, items.size() * sizeof(dmrg::RenormItem)));
             HIPCHK(hipMalloc(&d_t, (size_t)std::max<int64_t>(1, t_len) * sizeof(double)));
             HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RenormItem), hipMemcpyHostToDevice, s));
-            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), A, O,
-                                            static_cast<double*>(d_t), out, s));
+            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), max_t,
+                                            max_out, A, O, static_cast<double*>(d_t), out, s));
             HIPCHK(hipStreamSynchronize(s));   // the work list and T end here
         } catch (...) {
             (void)hipStreamSynchronize(s);

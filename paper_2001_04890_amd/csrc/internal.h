@@ -262,8 +262,8 @@ struct RenormItem {
     int64_t a_off, t_off, out_off, oo_off, oi_off;
     int32_t rows, cols, k_out, k_in;
 };
-hipError_t launch_renormalize(const RenormItem* items, int n_items, const double* A, const double* O, double* T,
-                              double* out, hipStream_t s);
+hipError_t launch_renormalize(const RenormItem* items, int n_items, int64_t max_t, int64_t max_out, const double* A,
+                              const double* O, double* T, double* out, hipStream_t s);
 // Tiled split-BF16 kernels (hpsi_lds.hip).
 hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).

@@ -750,10 +750,11 @@ hipError_t launch_rdm_right(const RdmItem* items, int n_items, const int64_t* gb
 // Eq. renorm_mat, FP64, one workgroup per sector block and pass; each thread owns output elements and
 // sums in a fixed order.
 __global__ void k_renorm_t(const RenormItem* __restrict__ items, const double* __restrict__ A,
-                           const double* __restrict__ O, double* __restrict__ T) {
+                           const double* __restrict__ O, double* __restrict__ T, int chunk) {
     const RenormItem it = items[blockIdx.x];
     const int n = it.rows * it.k_in;
-    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+    const int e0 = (int)blockIdx.y * chunk, e1 = min(n, e0 + chunk);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += (int)blockDim.x) {
         const int r = e / it.k_in, j = e - (e / it.k_in) * it.k_in;
         const double* a = A + it.a_off + (int64_t)r * it.cols;
         const double* o = O + it.oi_off + j;                    // column j of O_in, stride k_in
@@ -764,10 +765,11 @@ __global__ void k_renorm_t(const RenormItem* __restrict__ items, const double* _
 }
 
 __global__ void k_renorm_out(const RenormItem* __restrict__ items, const double* __restrict__ O,
-                             const double* __restrict__ T, double* __restrict__ out) {
+                             const double* __restrict__ T, double* __restrict__ out, int chunk) {
     const RenormItem it = items[blockIdx.x];
     const int n = it.k_out * it.k_in;
-    for (int e = (int)threadIdx.x; e < n; e += (int)blockDim.x) {
+    const int e0 = (int)blockIdx.y * chunk, e1 = min(n, e0 + chunk);
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += (int)blockDim.x) {
         const int i = e / it.k_in, j = e - (e / it.k_in) * it.k_in;
         const double* o = O + it.oo_off + i;                    // column i of O_out, stride k_out
         const double* t = T + it.t_off + j;                     // column j of T, stride k_in
@@ -777,13 +779,23 @@ __global__ void k_renorm_out(const RenormItem* __restrict__ items, const double*
     }
 }
 
-hipError_t launch_renormalize(const RenormItem* items, int n_items, const double* A, const double* O, double* T,
-                              double* out, hipStream_t s) {
+// Output elements of one item are cut into chunks of at least 1024 (grid.y <= 65535), so that a few
+// large sector blocks still spread over the chip; max_t / max_out: most elements of one item per pass.
+hipError_t launch_renormalize(const RenormItem* items, int n_items, int64_t max_t, int64_t max_out, const double* A,
+                              const double* O, double* T, double* out, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_renorm_t, dim3((unsigned)n_items), dim3(256), 0, s, items, A, O, T);
+    auto grid = [&](int64_t most, int& chunk) {
+        int64_t c = std::max<int64_t>(1024, (most + 65534) / 65535);
+        c = (c + 255) / 256 * 256;
+        chunk = (int)c;
+        return dim3((unsigned)n_items, (unsigned)std::max<int64_t>(1, (most + c - 1) / c));
+    };
+    int ct = 0, co = 0;
+    const dim3 gt = grid(max_t, ct), go = grid(max_out, co);
+    hipLaunchKernelGGL(k_renorm_t, gt, dim3(256), 0, s, items, A, O, T, ct);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_renorm_out, dim3((unsigned)n_items), dim3(256), 0, s, items, O, T, out);
+    hipLaunchKernelGGL(k_renorm_out, go, dim3(256), 0, s, items, O, T, out, co);
     return hipGetLastError();
 }
 
