@@ -17,6 +17,7 @@
 // combination is the transpose of each of its three matrices.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -26,6 +27,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -2186,26 +2188,26 @@ extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int
         if (!rho || !dims || !offsets || !kept || !evals || !vecs || !discarded) throw Error(DMRG_ERR_ARG, "NULL argument");
         if (n_sec < 0 || M < 0) throw Error(DMRG_ERR_ARG, "n_sec and M must be >= 0");
         int64_t pos = 0;
+        std::vector<int64_t> eoff(n_sec + 1, 0);
         for (int i = 0; i < n_sec; ++i) {
             if (dims[i] < 0 || offsets[i] != pos) throw Error(DMRG_ERR_SHAPE, "offsets must be the prefix sums of dims^2");
             pos += (int64_t)dims[i] * dims[i];
+            eoff[i + 1] = eoff[i] + dims[i];
         }
-        // per sector: eigenpairs in descending eigenvalue order, each vector's largest-magnitude
-        // component positive; candidates ordered by (eigenvalue descending, sector, position)
-        struct Cand { double w; int sec, pos; };
-        std::vector<Cand> cand;
-        int64_t eoff = 0;
-        double trace = 0.0;
-        for (int i = 0; i < n_sec; ++i) {
+        for (int64_t k = 0; k < pos; ++k)
+            if (!std::isfinite(rho[k])) throw Error(DMRG_ERR_NAN, "non-finite density matrix element");
+        // one sector: eigenpairs in descending eigenvalue order, each vector's largest-magnitude
+        // component positive, written to the sector's own parts of evals and vecs
+        std::vector<double> trace(n_sec, 0.0);
+        auto solve = [&](int i) {
             const int n = dims[i];
             std::vector<double> A(rho + offsets[i], rho + offsets[i] + (int64_t)n * n), V;
-            for (double v : A) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite density matrix element");
             for (int r = 0; r < n; ++r)
                 for (int c = 0; c < r; ++c) {            // symmetrize: the input is psi psi^T up to rounding
                     const double m = 0.5 * (A[(size_t)r * n + c] + A[(size_t)c * n + r]);
                     A[(size_t)r * n + c] = A[(size_t)c * n + r] = m;
                 }
-            for (int r = 0; r < n; ++r) trace += A[(size_t)r * n + r];
+            for (int r = 0; r < n; ++r) trace[i] += A[(size_t)r * n + r];
             jacobi_eigen(A, V, n);
             std::vector<int> order(n);
             for (int k = 0; k < n; ++k) order[k] = k;
@@ -2220,11 +2222,47 @@ extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int
                     if (std::fabs(V[(size_t)r * n + src]) > std::fabs(V[(size_t)big * n + src])) big = r;
                 const double sg = V[(size_t)big * n + src] < 0.0 ? -1.0 : 1.0;
                 for (int r = 0; r < n; ++r) out[(size_t)r * n + k] = sg * V[(size_t)r * n + src];
-                evals[eoff + k] = A[(size_t)src * n + src];
-                cand.push_back({A[(size_t)src * n + src], i, k});
+                evals[eoff[i] + k] = A[(size_t)src * n + src];
             }
-            eoff += n;
+        };
+        // sectors are independent: a few host threads take them largest first; the first error (in
+        // sector order) is reported
+        std::vector<int> todo(n_sec);
+        for (int i = 0; i < n_sec; ++i) todo[i] = i;
+        std::stable_sort(todo.begin(), todo.end(), [&](int x, int y) { return dims[x] > dims[y]; });
+        std::vector<dmrg_status> st(n_sec, DMRG_OK);
+        std::vector<std::string> msg(n_sec);
+        std::atomic<int> next{0};
+        auto worker = [&]() {
+            for (int t = next++; t < n_sec; t = next++) {
+                const int i = todo[t];
+                try {
+                    solve(i);
+                } catch (const Error& e) {
+                    st[i] = e.code;
+                    msg[i] = e.what();
+                } catch (const std::bad_alloc&) {
+                    st[i] = DMRG_ERR_NOMEM;
+                    msg[i] = "host allocation failed";
+                }
+            }
+        };
+        const int n_thr = std::max(1, std::min({n_sec, 16, (int)std::thread::hardware_concurrency()}));
+        std::vector<std::thread> pool;
+        for (int k = 1; k < n_thr; ++k) pool.emplace_back(worker);
+        worker();
+        for (auto& th : pool) th.join();
+        for (int i = 0; i < n_sec; ++i)
+            if (st[i] != DMRG_OK) throw Error(st[i], msg[i]);
+        // the M largest eigenvalues over all sectors, ties in (sector, position) order
+        struct Cand { double w; int sec, pos; };
+        std::vector<Cand> cand;
+        cand.reserve((size_t)eoff[n_sec]);
+        double tr = 0.0;
+        for (int i = 0; i < n_sec; ++i) {
+            tr += trace[i];
             kept[i] = 0;
+            for (int k = 0; k < dims[i]; ++k) cand.push_back({evals[eoff[i] + k], i, k});
         }
         std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
             if (x.w != y.w) return x.w > y.w;
@@ -2234,7 +2272,7 @@ extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int
         double sum = 0.0;
         const size_t take = std::min(cand.size(), (size_t)M);
         for (size_t k = 0; k < take; ++k) { ++kept[cand[k].sec]; sum += cand[k].w; }
-        *discarded = trace - sum;
+        *discarded = tr - sum;
         return DMRG_OK;
     } catch (const Error& e) {
         return fail(e);
