@@ -199,8 +199,8 @@ dmrg_status dmrg_rdm_right(dmrg_hop* hop, const double* psi, double* rho, int64_
 
 /* The truncation of Section 2.1: the M eigenvectors of a block-diagonal density matrix with the
  * largest eigenvalues (they form the renormalization matrix of Eq. renorm). Host routine, FP64: each
- * sector by the cyclic Jacobi method (off-diagonal norm below 1e-15 of the Frobenius norm); sectors
- * are solved on up to 16 host threads (results do not depend on their number).
+ * sector by Householder tridiagonalization and the implicit symmetric QR iteration with Wilkinson
+ * shifts; sectors are solved on up to 16 host threads (results do not depend on their number).
  * rho (host, read only): n_sec symmetric dims[i] x dims[i] row-major blocks at offsets[i], the prefix
  * sums of dims^2 (the layout of dmrg_rdm_left_layout). Outputs, all host, caller-allocated:
  * evals (sum of dims doubles: per sector, in sector order, its eigenvalues in descending order);

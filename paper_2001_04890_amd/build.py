@@ -4,6 +4,7 @@
 
 (Run by path: importing the package would load the library that is being rebuilt.)
 """
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -16,7 +17,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for every HIP translation unit.
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "mlp.hip", "host.cpp", "mlp_host.cpp"]
+SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "mlp.hip", "host.cpp", "mlp_host.cpp",
+           "renorm_host.cpp", "davidson.cpp", "eigen.cpp"]
 
 
 def _run(cmd):
@@ -30,11 +32,16 @@ def _run(cmd):
 def build(verbose=False):
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    objs = []
-    for src in SOURCES:
+    def compile_one(src):
         obj = os.path.join(build_dir, src.replace(".", "_") + ".o")
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        out = _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+        return obj, _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
+
+    # translation units compile in parallel (at most 8 hipcc processes)
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    objs = []
+    for obj, out in results:
         if verbose and out.strip():
             print(out)
         objs.append(obj)

@@ -1,0 +1,288 @@
+// Davidson's method for the lowest eigenpair of the two-site H (Sections 2.1, 2.2.1): FP64 basis,
+// device-side Gram-Schmidt, host Rayleigh-Ritz (Householder + implicit QR), diagonal or learned preconditioner.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "eigen.h"
+#include "hop.h"
+#include "mlp.h"
+
+using dmrg::Error;
+
+// ---------------------------------------------------------------- Davidson (Sections 2.1, 2.2.1)
+namespace {
+
+struct DavWork {
+    double* V = nullptr;     // max_sub x n
+    double* W = nullptr;     // max_sub x n
+    double* tmp = nullptr;   // 3 x n  (u, r, t)
+    double* prev = nullptr;  // n
+    double* part = nullptr;  // partial dots
+    double* dots = nullptr;  // max_sub + 4: dot products [0, max_sub], squared norms at max_sub + 1, + 2
+    std::vector<void*> allocs;
+    ~DavWork() { for (void* p : allocs) (void)hipFree(p); }
+    template <class T> T* get(size_t n) { void* p; if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw Error(DMRG_ERR_NOMEM, "device allocation failed (Davidson work space)"); allocs.push_back(p); return (T*)p; }
+};
+
+}  // namespace
+
+dmrg::MlpProblem dmrg::mlp_problem_of(const dmrg_hop* H) {
+    if (H->device < 0 || !H->d_diag) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+    HIPCHK(hipSetDevice(H->device));
+    MlpProblem p;
+    p.n = H->n_coeff;
+    p.diag = H->d_diag;
+    for (size_t k = 0; k < H->blk.size(); ++k) {
+        p.off.push_back(H->blk_off[k]);
+        p.m_a.push_back(H->blk_ma[k]);
+        p.m_d.push_back(H->blk_md[k]);
+        p.b.push_back(H->blk[k][1]);
+        p.c.push_back(H->blk[k][2]);
+    }
+    return p;
+}
+
+extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res,
+                                     void* stream) {
+    return dmrg::davidson_run(H, psi, o, res, stream, nullptr);
+}
+
+dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res, void* stream,
+                               MlpRecord* rec) {
+    dmrg::clear_error();
+    try {
+        if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
+        if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
+        if (o->use_graph != 0 && o->use_graph != 1) throw Error(DMRG_ERR_ARG, "use_graph must be 0 or 1");
+        if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
+        if (o->precond != DMRG_PRECOND_DIAG && o->precond != DMRG_PRECOND_MLP) throw Error(DMRG_ERR_ARG, "unknown preconditioner");
+        if (o->precond == DMRG_PRECOND_MLP && !o->mlp) throw Error(DMRG_ERR_ARG, "learned preconditioner requested without a network");
+        HIPCHK(hipSetDevice(H->device));
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t n = H->n_coeff;
+        const int K = o->max_sub;
+        std::unique_ptr<dmrg::MlpSession> sess;
+        if (o->precond == DMRG_PRECOND_MLP || rec)
+            sess.reset(new dmrg::MlpSession(o->precond == DMRG_PRECOND_MLP ? o->mlp : nullptr, rec ? rec->mlp : nullptr,
+                                            rec ? rec->slot : 0, rec ? rec->rows_per_iter : 1, rec ? rec->seed : 0,
+                                            rec ? rec->psi_star : nullptr, mlp_problem_of(H), s));
+        DavWork w;
+        w.V = w.get<double>((size_t)K * n);
+        w.W = w.get<double>((size_t)K * n);
+        w.tmp = w.get<double>((size_t)3 * n);
+        w.prev = w.get<double>(n);
+        int np = dmrg::multidot_parts(n);
+        w.part = w.get<double>((size_t)np * (K + 2));
+        w.dots = w.get<double>(K + 4);
+        double* restart_scratch = w.get<double>((size_t)4 * n);
+        double* u = w.tmp;
+        double* r = w.tmp + n;
+        double* t = w.tmp + 2 * n;
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        double t_hpsi = 0.0;
+        int prec = o->precision;
+        int matvecs = 0, matvecs_split = 0;
+        // every matvec is followed by a host synchronization (dots / fetch) before the next one; its
+        // event-timed duration is collected there
+        bool timing_pending = false;
+        auto collect_timing = [&]() {
+            if (!timing_pending) return;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            t_hpsi += ms * 1e-3;
+            timing_pending = false;
+        };
+        auto matvec = [&](const double* x, double* y) {
+            HIPCHK(hipEventRecord(e0, s));
+            dmrg_status st = o->use_graph ? dmrg_hpsi_graph(H, x, y, 1, prec, s) : dmrg_hpsi(H, x, y, 1, prec, s);
+            if (st != DMRG_OK) throw Error(st, dmrg::last_error());
+            HIPCHK(hipEventRecord(e1, s));
+            timing_pending = true;
+            ++matvecs;
+            if (prec == DMRG_PREC_SPLIT2) ++matvecs_split;
+        };
+        std::vector<double> hd(K + 4);
+        auto fetch = [&](int count) {               // w.dots[0, count) -> hd, synchronizing the stream
+            HIPCHK(hipMemcpyAsync(hd.data(), w.dots, count * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            collect_timing();
+        };
+        auto dots = [&](const double* Vs, int nv, const double* x) {
+            HIPCHK(dmrg::launch_multidot(Vs, nv, n, x, w.part, np, w.dots, s));
+            fetch(nv);
+        };
+        // device-side classical Gram-Schmidt (twice) of x against the first k columns of V, and
+        // normalization with the squared norm left in w.dots[slot]: no host round trip
+        auto orth_dev = [&](int k, double* x) {
+            for (int pass = 0; pass < 2 && k > 0; ++pass) {
+                HIPCHK(dmrg::launch_multidot(w.V, k, n, x, w.part, np, w.dots, s));
+                HIPCHK(dmrg::launch_project_out(w.V, k, n, w.dots, x, s));
+            }
+        };
+        auto normalize_dev = [&](double* x, int slot) {
+            HIPCHK(dmrg::launch_multidot(x, 1, n, x, w.part, np, w.dots + slot, s));
+            HIPCHK(dmrg::launch_scale_dev(x, w.dots + slot, n, s));
+        };
+        auto combine = [&](const double* Vs, int nv, const std::vector<double>& c, double* out, double beta) {
+            dmrg::Coefs cf;
+            for (int j = 0; j < nv; ++j) cf.c[j] = c[j];
+            HIPCHK(dmrg::launch_combine(Vs, nv, n, cf, out, beta, s));
+        };
+        auto normalize = [&](double* x) -> double {
+            dots(x, 1, x);
+            double nrm = std::sqrt(hd[0]);
+            if (!std::isfinite(nrm)) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
+            if (nrm == 0.0) return 0.0;
+            HIPCHK(dmrg::launch_scale(x, 1.0 / nrm, n, s));
+            return nrm;
+        };
+        const char* tr_env = std::getenv("DMRG_DAVIDSON_TRACE");
+        const bool trace = tr_env && tr_env[0] == '1';
+        double t_start = dmrg::now_seconds();
+        HIPCHK(hipMemcpyAsync(w.V, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        if (normalize(w.V) == 0.0) throw Error(DMRG_ERR_ARG, "start vector is zero");
+        matvec(w.V, w.W);
+        int k = 1;
+        std::vector<double> G((size_t)K * K, 0.0);
+        dots(w.V, 1, w.W);
+        G[0] = hd[0];
+        double theta = G[0], rnorm = INFINITY;
+        bool have_prev = false, converged = false;
+        int it = 0;
+        std::vector<double> evals, evecs;
+        double best_split_r = INFINITY;
+        int stall = 0;
+        bool mlp_on = o->precond == DMRG_PRECOND_MLP;
+        double best_mlp_r = INFINITY;
+        int mlp_stall = 0;
+        res->precond_fallback_iter = -1;
+        for (it = 1; it <= o->max_iter; ++it) {
+            std::vector<double> A((size_t)k * k);
+            for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j)
+                A[(size_t)i * k + j] = 0.5 * (G[(size_t)i * K + j] + G[(size_t)j * K + i]);
+            dmrg::sym_eigen(k, A.data(), evals, evecs, 1);   // ascending; row 0 = lowest eigenvector
+            theta = evals[0];
+            std::vector<double> sv(k), ms(k);
+            for (int i = 0; i < k; ++i) { sv[i] = evecs[i]; ms[i] = -theta * sv[i]; }
+            combine(w.V, k, sv, u, 0.0);               // u = V s
+            combine(w.W, k, sv, r, 0.0);               // r = W s
+            combine(w.V, k, ms, r, 1.0);               // r -= theta V s
+            dots(r, 1, r);
+            rnorm = std::sqrt(hd[0]);
+            if (trace) std::fprintf(stderr, "[dmrg_davidson] it %d k %d prec %d theta %.15f resid %.3e\n", it, k,
+                                    prec, theta, rnorm);
+            if (!std::isfinite(rnorm) || !std::isfinite(theta)) throw Error(DMRG_ERR_NAN, "non-finite Davidson residual");
+            if (prec == DMRG_PREC_SPLIT2 && o->fp64_polish) {
+                // hand over at split_tol, or, within 30x of it, when the split residual has stopped
+                // improving (no new minimum by 1% for 10 iterations: the matvec rounding floor has
+                // been reached; far above split_tol a plateau is ordinary Davidson progress)
+                bool hand_over = rnorm <= std::max(o->split_tol, o->tol);
+                if (rnorm < 0.99 * best_split_r) { best_split_r = rnorm; stall = 0; }
+                else if (++stall >= 10 && rnorm < 30.0 * o->split_tol) hand_over = true;
+                if (hand_over) {
+                    // restart in FP64 from the current Ritz vector
+                    prec = DMRG_PREC_FP64;
+                    HIPCHK(hipMemcpyAsync(w.V, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    normalize(w.V);
+                    matvec(w.V, w.W);
+                    dots(w.V, 1, w.W);
+                    k = 1;
+                    G[0] = hd[0];
+                    have_prev = false;
+                    continue;
+                }
+            }
+            if (rnorm <= o->tol) { converged = true; break; }
+            HIPCHK(dmrg::launch_precond(r, H->d_diag, theta, t, n, s));
+            if (k >= K) {
+                // restart: V <- orth{u, previous u}, W <- the same combinations of W (no new matvecs)
+                std::vector<std::vector<double>> Y;
+                Y.push_back(sv);
+                if (have_prev) {
+                    dots(w.V, k, w.prev);                // coefficients of u_prev in V
+                    std::vector<double> cp(hd.begin(), hd.begin() + k);
+                    // near convergence u_prev ~ u: project twice and drop a remainder that is mostly
+                    // rounding noise, otherwise the restarted basis is not orthonormal
+                    for (int pass = 0; pass < 2; ++pass) {
+                        double d = 0.0;
+                        for (int i = 0; i < k; ++i) d += cp[i] * sv[i];
+                        for (int i = 0; i < k; ++i) cp[i] -= d * sv[i];
+                    }
+                    double nn = 0.0; for (double v : cp) nn += v * v;
+                    nn = std::sqrt(nn);
+                    if (nn > 1e-6) { for (double& v : cp) v /= nn; Y.push_back(cp); }
+                }
+                while ((int)Y.size() > K - 1) Y.pop_back();   // leave room for the next vector
+                int kn = (int)Y.size();
+                double* scratch = restart_scratch;       // 2 * kn <= 4 vectors
+                for (int j = 0; j < kn; ++j) {
+                    combine(w.V, k, Y[j], scratch + (size_t)j * n, 0.0);
+                    combine(w.W, k, Y[j], scratch + (size_t)(kn + j) * n, 0.0);
+                }
+                for (int j = 0; j < kn; ++j) {
+                    HIPCHK(hipMemcpyAsync(w.V + (size_t)j * n, scratch + (size_t)j * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                    HIPCHK(hipMemcpyAsync(w.W + (size_t)j * n, scratch + (size_t)(kn + j) * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+                }
+                std::vector<double> Gn((size_t)K * K, 0.0);
+                for (int a = 0; a < kn; ++a) for (int b = 0; b < kn; ++b) {
+                    double v = 0.0;
+                    for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j) v += Y[a][i] * G[(size_t)i * K + j] * Y[b][j];
+                    Gn[(size_t)a * K + b] = v;
+                }
+                G = Gn;
+                k = kn;
+            }
+            HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            have_prev = true;
+            if (o->precond == DMRG_PRECOND_MLP && mlp_on) {
+                // the diagonal preconditioner is the network's yardstick: once the residual has made no new
+                // minimum (by 1%) for 20 iterations, the rest of the solve uses the diagonal correction
+                if (rnorm < 0.99 * best_mlp_r) { best_mlp_r = rnorm; mlp_stall = 0; }
+                else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
+            }
+            if (sess) sess->correction(r, u, t, theta, w.V, k, mlp_on);
+            // next basis vector, built in place on the device: orthogonalize, normalize, and once more
+            // after scaling (cheap insurance); its norm before scaling returns with the new column of G
+            double* vk = w.V + (size_t)k * n;
+            HIPCHK(hipMemcpyAsync(vk, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+            orth_dev(k, vk);
+            normalize_dev(vk, K + 1);
+            orth_dev(k, vk);
+            normalize_dev(vk, K + 2);
+            matvec(vk, w.W + (size_t)k * n);
+            HIPCHK(dmrg::launch_multidot(w.V, k + 1, n, w.W + (size_t)k * n, w.part, np, w.dots, s));
+            fetch(K + 3);
+            const double nt = std::sqrt(hd[K + 1]);
+            if (!std::isfinite(nt) || !std::isfinite(hd[K + 2])) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
+            if (nt < 1e-14) break;                        // the correction lies in span(V): no new direction
+            for (int i = 0; i <= k; ++i) { G[(size_t)i * K + k] = hd[i]; G[(size_t)k * K + i] = hd[i]; }
+            ++k;
+        }
+        HIPCHK(hipMemcpyAsync(psi, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        res->energy = theta;
+        res->resid = rnorm;
+        res->iters = std::min(it, o->max_iter);
+        res->matvecs = matvecs;
+        res->matvecs_split = matvecs_split;
+        res->t_total = dmrg::now_seconds() - t_start;
+        res->t_hpsi = t_hpsi;
+        if (rec) rec->rows_added = sess->rows_recorded();
+        if (!converged) { dmrg::last_error() = "Davidson did not converge"; return DMRG_NOT_CONVERGED; }
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return dmrg::record_error(e);
+    }
+}
+

@@ -34,6 +34,7 @@
 #include "../../include/dmrg.h"
 #include "host_common.h"
 #include "internal.h"
+#include "hop.h"
 #include "mlp.h"
 
 namespace {
@@ -42,7 +43,15 @@ thread_local std::string g_err;
 
 using dmrg::Error;
 
-using M16 = std::array<double, 256>;   // two-site operator, index (b'*4+c') * 16 + (b*4+c)
+using dmrg::M16;
+using dmrg::kSiteQn;
+using dmrg::OpIn;
+using dmrg::BlockIn;
+using dmrg::Term;
+using dmrg::MatDef;
+using dmrg::Alpha;
+using dmrg::kind_name;
+using dmrg::import_block;
 
 M16 zero16() { M16 m; m.fill(0.0); return m; }
 M16 eye16() { M16 m = zero16(); for (int i = 0; i < 16; ++i) m[i * 17] = 1.0; return m; }
@@ -88,26 +97,10 @@ M16 site_parity() {
     return m;
 }
 
-const int kSiteQn[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
 
-// ---------------------------------------------------------------- imported blocks
-struct OpIn {
-    int kind, i0, i1;
-    std::vector<int> out_of_in;       // per ket sector: bra sector or -1
-    std::vector<int64_t> off_of_in;   // host element offset of the block
-};
-struct BlockIn {
-    int n_sec = 0;
-    std::vector<int> qa, qb, dim;
-    std::vector<OpIn> ops;
-    std::map<std::array<int, 3>, int> index;
-    const double* data = nullptr;
-    int64_t n_data = 0;
-    int find(int kind, int i0, int i1) const {
-        auto it = index.find({kind, i0, i1});
-        return it == index.end() ? -1 : it->second;
-    }
-};
+}  // namespace
+
+namespace dmrg {
 
 const char* kind_name(int k) {
     static const char* n[] = {"H", "C", "A", "B", "S", "U", "P", "Q"};
@@ -161,115 +154,7 @@ BlockIn import_block(const dmrg_block* b, const char* side) {
     return B;
 }
 
-// ---------------------------------------------------------------- matrices and combinations
-struct Term { double c; int op; bool tr; };
-struct MatDef {
-    int side;                       // 0 left, 1 right
-    std::vector<Term> terms;        // matrix = sum c * op (or op^T)
-    int transpose_id = -1;          // cache
-    // materialized:
-    std::vector<int> out_of_in;
-    std::vector<int64_t> pool_of_in;
-    double bytes = 0.0;             // padded pool bytes of all its sector blocks
-};
-
-struct Alpha {
-    double coeff;
-    int lmat;       // -1 identity
-    int lpar;       // 0 none, 1 (-1)^{n(ket sector)}, 2 (-1)^{n(bra sector)}
-    M16 S;
-    int rmat;       // -1 identity
-    int family;
-};
-
-}  // namespace
-
-struct dmrg_hop {
-    int L = 0, na = 0, nb = 0, site = 0;
-    BlockIn left, right;
-    std::vector<double> h, eri;
-    // layout
-    std::vector<std::array<int, 4>> blk;     // (a, b, c, d)
-    std::vector<int> blk_ma, blk_md;
-    std::vector<int64_t> blk_off;
-    std::vector<int> blk_index;              // [(a*4+b)*4+c] -> block id or -1
-    int64_t n_coeff = 0;
-    // terms
-    std::vector<MatDef> mats;
-    std::map<std::tuple<int, int, bool>, int> mat_cache;
-    std::vector<Alpha> alphas;
-    // tasks
-    struct HTask { int i, j, lm, rm; double f; };
-    std::vector<HTask> tasks;
-    double flops = 0.0, bytes = 0.0;
-    // device
-    int device = -1;
-    bool has_split = false;
-    int64_t pool_size = 0;
-    double* d_pool = nullptr;
-    uint16_t* d_hi = nullptr;
-    uint16_t* d_lo = nullptr;
-    dmrg::Task* d_tasks = nullptr;
-    dmrg::HpsiPlan plan{};
-    std::vector<dmrg::HpsiLaunch> launches;
-    std::vector<dmrg::HpsiPhase> phases;
-    // split path: LDS-staged kernel over tiled operands, plus the one-wave kernel (row-major hi/lo
-    // operands, plan_fb) for targets whose blocks exceed the LDS stage size
-    std::vector<dmrg::PoolBlock> pool_blocks;   // every block of the FP64 pool (for the tiled split)
-    uint16_t* d_tiled = nullptr;                // tiled hi/lo operators + identity blocks
-    int64_t tiled_size = 0;
-    std::vector<int64_t> ident_off;             // tiled identity block of size 32 (k + 1), k = 0, 1, ...
-    dmrg::LdsPlan lplan{};
-    dmrg::HpsiPlan plan_fb{};
-    std::vector<dmrg::HpsiLaunch> launches_fb;
-    std::vector<dmrg::HpsiPhase> phases_fb;
-    int n_fallback_targets = 0;
-    int tune_lds_items = 16384;                 // target number of LDS work items per H.psi
-    int tune_small_mode = 1;                    // 1: single-tile sources run in the task-mode kernel
-    int tune_small_nr = 2;                      // task mode: most row tiles per wavefront (1 or 2)
-    // hipGraphs of the H.psi launch sequence, one per (x, y, nvec, precision); dropped when a plan is rebuilt
-    struct GraphEntry { const double* x; double* y; int nvec, prec; hipGraph_t graph; hipGraphExec_t exec; };
-    std::vector<GraphEntry> graphs;
-    hipStream_t cap_stream = nullptr;           // capture stream (default priority)
-    bool share = false;                         // build only the combinations whose operators are supplied
-    int tune_lds_order = 0;                     // 0: heaviest item first; 1: XCD-aware by left sector;
-                                                // 2: merged handle, each problem's items together
-    int tune_lds_task_order = 0;                // 0: tasks by source; 1: by operator pair
-    int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
-    int tune_lds_pf = 0x4;                      // row-mode classes with a prefetch wavefront (bit mask)
-    int tune_lds_w6 = 0x8;                      // (S, 2) row-mode classes run as six one-row-tile wavefronts
-    int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
-    int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
-    int tune_big_stages1 = 16;                  // pass-1 workgroup size in 32-wide k steps
-    int tune_big_tbudget_mb = 1024;             // T buffer of one chunk of large targets (MB)
-    dmrg::BigPlan bplan{};
-    std::vector<dmrg::BigChunk> big_chunks;
-    std::vector<std::pair<int32_t, int32_t>> big_t2_range;
-    int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
-    // FP64 two-pass path (hpsi_big64.hip) for the same large targets
-    int tune_big64 = 1;                         // FP64 two-pass path: 0 off, 1 where cheaper, 2 every target above 96
-    double* d_tiled64 = nullptr;                // FP64 tiled operators + identity blocks (made on first use)
-    int64_t tiled64_size = 0;
-    std::vector<int64_t> ident64_off;           // FP64 tiled identity block of size 32 (k + 1)
-    dmrg::BigPlan bplan64{};
-    std::vector<dmrg::BigChunk> big_chunks64;
-    double* xt64 = nullptr;                     // FP64 tiled X^T of one vector (plan allocation)
-    std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
-    int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)
-    int vec_step = 1;                      // vectors per launch sequence (packed-input and partial buffers)
-    bool trimmed = false;                  // dmrg_hop_trim: plans and derived operator copies released
-    int64_t n_alpha = 0;
-    int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
-    std::vector<int64_t> part_coeff;       // first coefficient of each merged problem (+ end)
-    int n_items = 0;
-    int64_t n_dev_tasks = 0;
-    int tune_max_tq = 8;       // widest output tile, in 16-column MFMA tiles (1..8)
-    int tune_items = 32768;    // target number of work items per H.psi launch
-    int tune_order = 2;        // item launch order (see build_plan)
-    int tune_phases = 1;       // 0: from the operator footprint and kCacheBudget
-    double* d_diag = nullptr;
-    std::vector<void*> allocations;
-};
+}  // namespace dmrg
 
 namespace {
 
@@ -1694,6 +1579,7 @@ dmrg_status fail(const Error& e) { g_err = e.what(); return e.code; }
 
 namespace dmrg {
 dmrg_status record_error(const Error& e) { return fail(e); }
+std::string& last_error() { return g_err; }
 void clear_error() { g_err.clear(); }
 double now_seconds() { return now(); }
 }  // namespace dmrg
@@ -1946,412 +1832,6 @@ extern "C" dmrg_status dmrg_hop_diagonal(dmrg_hop* H, double* d, void* stream) {
     }
 }
 
-// ---------------------------------------------------------------- reduced density matrices
-namespace {
-// psi read as the matrix psi_{(l s_l),(s_r r)} (Section 2.1). Left side: enlarged-left sectors
-// q = qn(a) + qn(b), groups (a, b) in (a, b) order with the m_a states of sector a; right side:
-// enlarged-right sectors q = qn(c) + qn(d), groups (c, d) in (c, d) order with the m_d states of
-// sector d. Sectors ascend in (n_alpha, n_beta); groups that no psi block reaches are included (zero
-// rows). groups[i] holds (x, y, first row) with (x, y) = (a, b) or (c, d).
-struct RdmLayout {
-    std::vector<std::pair<int, int>> qn;
-    std::vector<int> dim;
-    std::vector<int64_t> off;                                  // n_sec + 1: dense dim x dim blocks
-    std::vector<std::vector<std::array<int, 3>>> groups;
-};
-
-RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
-    if (H.n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: density matrices are per problem");
-    std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> groups;
-    std::map<std::pair<int, int>, int> dims;
-    const BlockIn& B = right ? H.right : H.left;
-    auto add = [&](int x, int y, int sec, int site) {
-        const std::pair<int, int> q{B.qa[sec] + kSiteQn[site][0], B.qb[sec] + kSiteQn[site][1]};
-        int& d = dims[q];
-        groups[q].push_back({x, y, d});
-        d += B.dim[sec];
-    };
-    if (!right) {
-        for (int a = 0; a < B.n_sec; ++a)
-            if (B.dim[a] > 0)
-                for (int b = 0; b < 4; ++b) add(a, b, a, b);
-    } else {
-        for (int c = 0; c < 4; ++c)
-            for (int d = 0; d < B.n_sec; ++d)
-                if (B.dim[d] > 0) add(c, d, d, c);
-    }
-    RdmLayout R;
-    R.off.push_back(0);
-    for (auto& kv : groups) {
-        const int d = dims[kv.first];
-        R.qn.push_back(kv.first);
-        R.dim.push_back(d);
-        R.off.push_back(R.off.back() + (int64_t)d * d);
-        R.groups.push_back(kv.second);
-    }
-    return R;
-}
-
-// psi blocks of one group, in the order of the other side's groups: left group (a, b) -> blocks
-// (a, b, c, d) for c = 0..3; right group (c, d) -> blocks (a, b, c, d) for (a, b) in (a, b) order.
-std::vector<int> rdm_group_blocks(const dmrg_hop& H, bool right, int x, int y) {
-    std::vector<int> ids;
-    if (!right) {
-        for (int c = 0; c < 4; ++c) {
-            const int id = H.blk_index[(x * 4 + y) * 4 + c];
-            if (id >= 0) ids.push_back(id);
-        }
-    } else {
-        for (int a = 0; a < H.left.n_sec; ++a)
-            for (int b = 0; b < 4; ++b) {
-                const int id = H.blk_index[(a * 4 + b) * 4 + x];
-                if (id >= 0 && H.blk[id][3] == y) ids.push_back(id);
-            }
-    }
-    return ids;
-}
-
-dmrg_status rdm_layout_entry(const dmrg_hop* H, bool right, int32_t* n_sec, int32_t* qn, int32_t* dims,
-                             int64_t* offsets) {
-    g_err.clear();
-    try {
-        if (!H || !n_sec) throw Error(DMRG_ERR_ARG, "NULL argument");
-        const RdmLayout R = rdm_layout(*H, right);
-        *n_sec = (int32_t)R.dim.size();
-        for (size_t i = 0; i < R.dim.size(); ++i) {
-            if (qn) { qn[2 * i] = R.qn[i].first; qn[2 * i + 1] = R.qn[i].second; }
-            if (dims) dims[i] = R.dim[i];
-        }
-        if (offsets)
-            for (size_t i = 0; i < R.off.size(); ++i) offsets[i] = R.off[i];
-        return DMRG_OK;
-    } catch (const Error& e) {
-        return fail(e);
-    }
-}
-
-dmrg_status rdm_entry(dmrg_hop* H, bool right, const double* psi, double* rho, int64_t rho_len, void* stream) {
-    g_err.clear();
-    try {
-        if (!H || !psi || !rho) throw Error(DMRG_ERR_ARG, "NULL argument");
-        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
-        const RdmLayout R = rdm_layout(*H, right);
-        if (rho_len != R.off.back()) throw Error(DMRG_ERR_SHAPE, "rho_len must be the sum of dim_q^2 of the sectors");
-        // per group: its psi blocks; within a sector every group has the same inner dimensions
-        // (m_d on the left side, m_a on the right), checked here
-        std::vector<dmrg::RdmItem> items;
-        std::vector<int64_t> gblk;
-        std::vector<int32_t> inner;
-        const BlockIn& B = right ? H->right : H->left;
-        for (size_t qi = 0; qi < R.dim.size(); ++qi) {
-            const auto& G = R.groups[qi];
-            const int in0 = (int)inner.size();
-            std::vector<int> g0(G.size());
-            int n_in = -1;
-            for (size_t k = 0; k < G.size(); ++k) {
-                g0[k] = (int)gblk.size();
-                const std::vector<int> ids = rdm_group_blocks(*H, right, G[k][0], G[k][1]);
-                if (k > 0 && (int)ids.size() != n_in)
-                    throw Error(DMRG_ERR_ARG, "internal: groups of a sector meet different blocks");
-                for (size_t t = 0; t < ids.size(); ++t) {
-                    const int m = right ? H->blk_ma[ids[t]] : H->blk_md[ids[t]];
-                    if (k == 0) inner.push_back(m);
-                    else if (inner[in0 + t] != m) throw Error(DMRG_ERR_ARG, "internal: groups of a sector meet different blocks");
-                    gblk.push_back(H->blk_off[ids[t]]);
-                }
-                n_in = (int)ids.size();
-            }
-            for (size_t k = 0; k < G.size(); ++k)
-                for (size_t k2 = 0; k2 < G.size(); ++k2) {
-                    dmrg::RdmItem it{};
-                    it.rho_off = R.off[qi] + (int64_t)G[k][2] * R.dim[qi] + G[k2][2];
-                    it.ld = R.dim[qi];
-                    it.ma = B.dim[right ? G[k][1] : G[k][0]];
-                    it.ma2 = B.dim[right ? G[k2][1] : G[k2][0]];
-                    it.g = g0[k];
-                    it.g2 = g0[k2];
-                    it.cd = in0;
-                    it.n_cd = n_in;
-                    items.push_back(it);
-                }
-        }
-        if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many density-matrix items");
-        HIPCHK(hipSetDevice(H->device));
-        hipStream_t s = (hipStream_t)stream;
-        void *d_items = nullptr, *d_g = nullptr, *d_c = nullptr;
-        auto release = [&]() {
-            if (d_items) (void)hipFree(d_items);
-            if (d_g) (void)hipFree(d_g);
-            if (d_c) (void)hipFree(d_c);
-        };
-        try {
-            HIPCHK(hipMalloc(&d_items, std::max<size_t>(1, items.size()) * sizeof(dmrg::RdmItem)));
-            HIPCHK(hipMalloc(&d_g, std::max<size_t>(1, gblk.size()) * sizeof(int64_t)));
-            HIPCHK(hipMalloc(&d_c, std::max<size_t>(1, inner.size()) * sizeof(int32_t)));
-            if (!items.empty())
-                HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RdmItem), hipMemcpyHostToDevice, s));
-            if (!gblk.empty())
-                HIPCHK(hipMemcpyAsync(d_g, gblk.data(), gblk.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
-            if (!inner.empty())
-                HIPCHK(hipMemcpyAsync(d_c, inner.data(), inner.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
-            const auto* di = static_cast<const dmrg::RdmItem*>(d_items);
-            const auto* dg = static_cast<const int64_t*>(d_g);
-            const auto* dc = static_cast<const int32_t*>(d_c);
-            if (right) HIPCHK(dmrg::launch_rdm_right(di, (int)items.size(), dg, dc, psi, rho, s));
-            else HIPCHK(dmrg::launch_rdm_left(di, (int)items.size(), dg, dc, psi, rho, s));
-            HIPCHK(hipStreamSynchronize(s));   // the host work lists and scratch end here
-        } catch (...) {
-            (void)hipStreamSynchronize(s);
-            release();
-            throw;
-        }
-        release();
-        return DMRG_OK;
-    } catch (const Error& e) {
-        return fail(e);
-    } catch (const std::bad_alloc&) {
-        g_err = "host allocation failed";
-        return DMRG_ERR_NOMEM;
-    }
-}
-}  // namespace
-
-extern "C" dmrg_status dmrg_rdm_left_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
-                                            int64_t* offsets) {
-    return rdm_layout_entry(H, false, n_sec, qn, dims, offsets);
-}
-
-extern "C" dmrg_status dmrg_rdm_left(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
-    return rdm_entry(H, false, psi, rho, rho_len, stream);
-}
-
-extern "C" dmrg_status dmrg_rdm_right_layout(const dmrg_hop* H, int32_t* n_sec, int32_t* qn, int32_t* dims,
-                                             int64_t* offsets) {
-    return rdm_layout_entry(H, true, n_sec, qn, dims, offsets);
-}
-
-extern "C" dmrg_status dmrg_rdm_right(dmrg_hop* H, const double* psi, double* rho, int64_t rho_len, void* stream) {
-    return rdm_entry(H, true, psi, rho, rho_len, stream);
-}
-
-namespace {
-// Eigenpairs of a symmetric n x n matrix (row-major, overwritten) by the cyclic Jacobi method: sweeps
-// over all pairs (p, q) of a plane rotation that zeroes a_pq, until the off-diagonal norm is below
-// 1e-15 of the Frobenius norm. V receives the eigenvectors as columns; the eigenvalues are left on
-// the diagonal of A.
-void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
-    V.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-    double fro = 0.0;
-    for (double v : A) fro += v * v;
-    if (fro == 0.0) return;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) off += 2.0 * A[(size_t)p * n + q] * A[(size_t)p * n + q];
-        if (off <= 1e-30 * fro) return;
-        for (int p = 0; p < n - 1; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                const double apq = A[(size_t)p * n + q];
-                if (apq == 0.0) continue;
-                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-                // rotation angle: t = tan(phi) is the smaller root of t^2 + 2 theta t - 1 = 0
-                const double theta = (aqq - app) / (2.0 * apq);
-                const double t = (theta >= 0.0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
-                for (int k = 0; k < n; ++k) {           // columns p, q: A <- A J
-                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-                    A[(size_t)k * n + p] = c * akp - sn * akq;
-                    A[(size_t)k * n + q] = sn * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {           // rows p, q: A <- J^T A
-                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-                    A[(size_t)p * n + k] = c * apk - sn * aqk;
-                    A[(size_t)q * n + k] = sn * apk + c * aqk;
-                }
-                A[(size_t)p * n + q] = A[(size_t)q * n + p] = 0.0;
-                for (int k = 0; k < n; ++k) {           // V <- V J
-                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = c * vkp - sn * vkq;
-                    V[(size_t)k * n + q] = sn * vkp + c * vkq;
-                }
-            }
-    }
-    throw Error(DMRG_ERR_NAN, "Jacobi eigensolver did not converge in 100 sweeps");
-}
-}  // namespace
-
-extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int32_t* dims, const int64_t* offsets,
-                                     int32_t M, int32_t* kept, double* evals, double* vecs, double* discarded) {
-    g_err.clear();
-    try {
-        if (!rho || !dims || !offsets || !kept || !evals || !vecs || !discarded) throw Error(DMRG_ERR_ARG, "NULL argument");
-        if (n_sec < 0 || M < 0) throw Error(DMRG_ERR_ARG, "n_sec and M must be >= 0");
-        int64_t pos = 0;
-        std::vector<int64_t> eoff(n_sec + 1, 0);
-        for (int i = 0; i < n_sec; ++i) {
-            if (dims[i] < 0 || offsets[i] != pos) throw Error(DMRG_ERR_SHAPE, "offsets must be the prefix sums of dims^2");
-            pos += (int64_t)dims[i] * dims[i];
-            eoff[i + 1] = eoff[i] + dims[i];
-        }
-        for (int64_t k = 0; k < pos; ++k)
-            if (!std::isfinite(rho[k])) throw Error(DMRG_ERR_NAN, "non-finite density matrix element");
-        // one sector: eigenpairs in descending eigenvalue order, each vector's largest-magnitude
-        // component positive, written to the sector's own parts of evals and vecs
-        std::vector<double> trace(n_sec, 0.0);
-        auto solve = [&](int i) {
-            const int n = dims[i];
-            std::vector<double> A(rho + offsets[i], rho + offsets[i] + (int64_t)n * n), V;
-            for (int r = 0; r < n; ++r)
-                for (int c = 0; c < r; ++c) {            // symmetrize: the input is psi psi^T up to rounding
-                    const double m = 0.5 * (A[(size_t)r * n + c] + A[(size_t)c * n + r]);
-                    A[(size_t)r * n + c] = A[(size_t)c * n + r] = m;
-                }
-            for (int r = 0; r < n; ++r) trace[i] += A[(size_t)r * n + r];
-            jacobi_eigen(A, V, n);
-            std::vector<int> order(n);
-            for (int k = 0; k < n; ++k) order[k] = k;
-            std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-                return A[(size_t)x * n + x] > A[(size_t)y * n + y];
-            });
-            double* out = vecs + offsets[i];
-            for (int k = 0; k < n; ++k) {
-                const int src = order[k];
-                int big = 0;
-                for (int r = 1; r < n; ++r)
-                    if (std::fabs(V[(size_t)r * n + src]) > std::fabs(V[(size_t)big * n + src])) big = r;
-                const double sg = V[(size_t)big * n + src] < 0.0 ? -1.0 : 1.0;
-                for (int r = 0; r < n; ++r) out[(size_t)r * n + k] = sg * V[(size_t)r * n + src];
-                evals[eoff[i] + k] = A[(size_t)src * n + src];
-            }
-        };
-        // sectors are independent: a few host threads take them largest first; the first error (in
-        // sector order) is reported
-        std::vector<int> todo(n_sec);
-        for (int i = 0; i < n_sec; ++i) todo[i] = i;
-        std::stable_sort(todo.begin(), todo.end(), [&](int x, int y) { return dims[x] > dims[y]; });
-        std::vector<dmrg_status> st(n_sec, DMRG_OK);
-        std::vector<std::string> msg(n_sec);
-        std::atomic<int> next{0};
-        auto worker = [&]() {
-            for (int t = next++; t < n_sec; t = next++) {
-                const int i = todo[t];
-                try {
-                    solve(i);
-                } catch (const Error& e) {
-                    st[i] = e.code;
-                    msg[i] = e.what();
-                } catch (const std::bad_alloc&) {
-                    st[i] = DMRG_ERR_NOMEM;
-                    msg[i] = "host allocation failed";
-                }
-            }
-        };
-        const int n_thr = std::max(1, std::min({n_sec, 16, (int)std::thread::hardware_concurrency()}));
-        std::vector<std::thread> pool;
-        for (int k = 1; k < n_thr; ++k) pool.emplace_back(worker);
-        worker();
-        for (auto& th : pool) th.join();
-        for (int i = 0; i < n_sec; ++i)
-            if (st[i] != DMRG_OK) throw Error(st[i], msg[i]);
-        // the M largest eigenvalues over all sectors, ties in (sector, position) order
-        struct Cand { double w; int sec, pos; };
-        std::vector<Cand> cand;
-        cand.reserve((size_t)eoff[n_sec]);
-        double tr = 0.0;
-        for (int i = 0; i < n_sec; ++i) {
-            tr += trace[i];
-            kept[i] = 0;
-            for (int k = 0; k < dims[i]; ++k) cand.push_back({evals[eoff[i] + k], i, k});
-        }
-        std::stable_sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
-            if (x.w != y.w) return x.w > y.w;
-            if (x.sec != y.sec) return x.sec < y.sec;
-            return x.pos < y.pos;
-        });
-        double sum = 0.0;
-        const size_t take = std::min(cand.size(), (size_t)M);
-        for (size_t k = 0; k < take; ++k) { ++kept[cand[k].sec]; sum += cand[k].w; }
-        *discarded = tr - sum;
-        return DMRG_OK;
-    } catch (const Error& e) {
-        return fail(e);
-    } catch (const std::bad_alloc&) {
-        g_err = "host allocation failed";
-        return DMRG_ERR_NOMEM;
-    }
-}
-
-extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t* dims, const int32_t* kept,
-                                               const int64_t* o_off, const double* O, int64_t o_len, int32_t n_blk,
-                                               const int32_t* sec_out, const int32_t* sec_in, const int64_t* a_off,
-                                               const double* A, int64_t a_len, const int64_t* out_off, double* out,
-                                               int64_t out_len, void* stream) {
-    g_err.clear();
-    try {
-        if (n_sec < 0 || n_blk < 0) throw Error(DMRG_ERR_ARG, "n_sec and n_blk must be >= 0");
-        if (n_blk == 0) return DMRG_OK;
-        if (!dims || !kept || !o_off || !O || !sec_out || !sec_in || !a_off || !A || !out_off || !out)
-            throw Error(DMRG_ERR_ARG, "NULL argument");
-        for (int s = 0; s < n_sec; ++s) {
-            if (dims[s] < 0 || kept[s] < 0 || kept[s] > dims[s]) throw Error(DMRG_ERR_ARG, "need 0 <= kept <= dims");
-            if (o_off[s] < 0 || o_off[s] + (int64_t)dims[s] * kept[s] > o_len)
-                throw Error(DMRG_ERR_SHAPE, "renormalization matrix outside O");
-        }
-        std::vector<dmrg::RenormItem> items;
-        int64_t t_len = 0, max_t = 0, max_out = 0;
-        for (int b = 0; b < n_blk; ++b) {
-            const int so = sec_out[b], si = sec_in[b];
-            if (so < 0 || so >= n_sec || si < 0 || si >= n_sec) throw Error(DMRG_ERR_ARG, "sector index out of range");
-            const int64_t rows = dims[so], cols = dims[si], ko = kept[so], ki = kept[si];
-            if (a_off[b] < 0 || a_off[b] + rows * cols > a_len) throw Error(DMRG_ERR_SHAPE, "operator block outside A");
-            if (out_off[b] < 0 || out_off[b] + ko * ki > out_len) throw Error(DMRG_ERR_SHAPE, "output block outside out");
-            if (rows * ki >= INT32_MAX || ko * ki >= INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "sector block too large");
-            if (ko == 0 || ki == 0) continue;                  // nothing kept on one side: empty block
-            dmrg::RenormItem it{};
-            it.a_off = a_off[b];
-            it.t_off = t_len;
-            it.out_off = out_off[b];
-            it.oo_off = o_off[so];
-            it.oi_off = o_off[si];
-            it.rows = (int32_t)rows;
-            it.cols = (int32_t)cols;
-            it.k_out = (int32_t)ko;
-            it.k_in = (int32_t)ki;
-            items.push_back(it);
-            t_len += rows * ki;
-            max_t = std::max(max_t, rows * ki);
-            max_out = std::max(max_out, ko * ki);
-        }
-        if (items.empty()) return DMRG_OK;
-        if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many blocks");
-        HIPCHK(hipSetDevice(device));
-        hipStream_t s = (hipStream_t)stream;
-        void *d_items = nullptr, *d_t = nullptr;
-        try {
-            HIPCHK(hipMalloc(&d_items, items.size() * sizeof(dmrg::RenormItem)));
-            HIPCHK(hipMalloc(&d_t, (size_t)std::max<int64_t>(1, t_len) * sizeof(double)));
-            HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RenormItem), hipMemcpyHostToDevice, s));
-            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), max_t,
-                                            max_out, A, O, static_cast<double*>(d_t), out, s));
-            HIPCHK(hipStreamSynchronize(s));   // the work list and T end here
-        } catch (...) {
-            (void)hipStreamSynchronize(s);
-            if (d_items) (void)hipFree(d_items);
-            if (d_t) (void)hipFree(d_t);
-            throw;
-        }
-        (void)hipFree(d_items);
-        (void)hipFree(d_t);
-        return DMRG_OK;
-    } catch (const Error& e) {
-        return fail(e);
-    } catch (const std::bad_alloc&) {
-        g_err = "host allocation failed";
-        return DMRG_ERR_NOMEM;
-    }
-}
-
 // ---------------------------------------------------------------- batching and tuning
 extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out) {
     g_err.clear();
@@ -2558,314 +2038,3 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
     }
 }
 
-// ---------------------------------------------------------------- Davidson (Sections 2.1, 2.2.1)
-namespace {
-
-// Cyclic Jacobi eigensolver for a small symmetric matrix (k <= 64), FP64.
-void jacobi_eigh(int n, std::vector<double>& A, std::vector<double>& evals, std::vector<double>& V) {
-    V.assign((size_t)n * n, 0.0);
-    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, diag = 0.0;
-        for (int i = 0; i < n; ++i) for (int j = 0; j < n; ++j)
-            (i == j ? diag : off) += A[(size_t)i * n + j] * A[(size_t)i * n + j];
-        if (off <= 1e-32 * (diag + 1e-300)) break;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                double apq = A[(size_t)p * n + q];
-                if (std::fabs(apq) < 1e-300) continue;
-                double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
-                double theta = (aqq - app) / (2.0 * apq);
-                double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
-                for (int k = 0; k < n; ++k) {
-                    double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
-                    A[(size_t)k * n + p] = c * akp - s * akq;
-                    A[(size_t)k * n + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {
-                    double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
-                    A[(size_t)p * n + k] = c * apk - s * aqk;
-                    A[(size_t)q * n + k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-                    V[(size_t)k * n + p] = c * vkp - s * vkq;
-                    V[(size_t)k * n + q] = s * vkp + c * vkq;
-                }
-            }
-    }
-    evals.resize(n);
-    for (int i = 0; i < n; ++i) evals[i] = A[(size_t)i * n + i];
-}
-
-struct DavWork {
-    double* V = nullptr;     // max_sub x n
-    double* W = nullptr;     // max_sub x n
-    double* tmp = nullptr;   // 3 x n  (u, r, t)
-    double* prev = nullptr;  // n
-    double* part = nullptr;  // partial dots
-    double* dots = nullptr;  // max_sub + 4: dot products [0, max_sub], squared norms at max_sub + 1, + 2
-    std::vector<void*> allocs;
-    ~DavWork() { for (void* p : allocs) (void)hipFree(p); }
-    template <class T> T* get(size_t n) { void* p; if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw Error(DMRG_ERR_NOMEM, "device allocation failed (Davidson work space)"); allocs.push_back(p); return (T*)p; }
-};
-
-}  // namespace
-
-dmrg::MlpProblem dmrg::mlp_problem_of(const dmrg_hop* H) {
-    if (H->device < 0 || !H->d_diag) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
-    HIPCHK(hipSetDevice(H->device));
-    MlpProblem p;
-    p.n = H->n_coeff;
-    p.diag = H->d_diag;
-    for (size_t k = 0; k < H->blk.size(); ++k) {
-        p.off.push_back(H->blk_off[k]);
-        p.m_a.push_back(H->blk_ma[k]);
-        p.m_d.push_back(H->blk_md[k]);
-        p.b.push_back(H->blk[k][1]);
-        p.c.push_back(H->blk[k][2]);
-    }
-    return p;
-}
-
-extern "C" dmrg_status dmrg_davidson(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res,
-                                     void* stream) {
-    return dmrg::davidson_run(H, psi, o, res, stream, nullptr);
-}
-
-dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o, dmrg_dav_result* res, void* stream,
-                               MlpRecord* rec) {
-    g_err.clear();
-    try {
-        if (!H || !psi || !o || !res) throw Error(DMRG_ERR_ARG, "NULL argument");
-        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
-        if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
-        if (o->max_sub < 2 || o->max_sub > 64 || o->max_iter < 1 || !(o->tol > 0)) throw Error(DMRG_ERR_ARG, "bad Davidson options");
-        if (o->use_graph != 0 && o->use_graph != 1) throw Error(DMRG_ERR_ARG, "use_graph must be 0 or 1");
-        if (o->precision == DMRG_PREC_SPLIT2 && !H->has_split) throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
-        if (o->precond != DMRG_PRECOND_DIAG && o->precond != DMRG_PRECOND_MLP) throw Error(DMRG_ERR_ARG, "unknown preconditioner");
-        if (o->precond == DMRG_PRECOND_MLP && !o->mlp) throw Error(DMRG_ERR_ARG, "learned preconditioner requested without a network");
-        HIPCHK(hipSetDevice(H->device));
-        hipStream_t s = (hipStream_t)stream;
-        const int64_t n = H->n_coeff;
-        const int K = o->max_sub;
-        std::unique_ptr<dmrg::MlpSession> sess;
-        if (o->precond == DMRG_PRECOND_MLP || rec)
-            sess.reset(new dmrg::MlpSession(o->precond == DMRG_PRECOND_MLP ? o->mlp : nullptr, rec ? rec->mlp : nullptr,
-                                            rec ? rec->slot : 0, rec ? rec->rows_per_iter : 1, rec ? rec->seed : 0,
-                                            rec ? rec->psi_star : nullptr, mlp_problem_of(H), s));
-        DavWork w;
-        w.V = w.get<double>((size_t)K * n);
-        w.W = w.get<double>((size_t)K * n);
-        w.tmp = w.get<double>((size_t)3 * n);
-        w.prev = w.get<double>(n);
-        int np = dmrg::multidot_parts(n);
-        w.part = w.get<double>((size_t)np * (K + 2));
-        w.dots = w.get<double>(K + 4);
-        double* restart_scratch = w.get<double>((size_t)4 * n);
-        double* u = w.tmp;
-        double* r = w.tmp + n;
-        double* t = w.tmp + 2 * n;
-        hipEvent_t e0, e1;
-        HIPCHK(hipEventCreate(&e0));
-        HIPCHK(hipEventCreate(&e1));
-        double t_hpsi = 0.0;
-        int prec = o->precision;
-        int matvecs = 0, matvecs_split = 0;
-        // every matvec is followed by a host synchronization (dots / fetch) before the next one; its
-        // event-timed duration is collected there
-        bool timing_pending = false;
-        auto collect_timing = [&]() {
-            if (!timing_pending) return;
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            t_hpsi += ms * 1e-3;
-            timing_pending = false;
-        };
-        auto matvec = [&](const double* x, double* y) {
-            HIPCHK(hipEventRecord(e0, s));
-            dmrg_status st = o->use_graph ? dmrg_hpsi_graph(H, x, y, 1, prec, s) : dmrg_hpsi(H, x, y, 1, prec, s);
-            if (st != DMRG_OK) throw Error(st, g_err);
-            HIPCHK(hipEventRecord(e1, s));
-            timing_pending = true;
-            ++matvecs;
-            if (prec == DMRG_PREC_SPLIT2) ++matvecs_split;
-        };
-        std::vector<double> hd(K + 4);
-        auto fetch = [&](int count) {               // w.dots[0, count) -> hd, synchronizing the stream
-            HIPCHK(hipMemcpyAsync(hd.data(), w.dots, count * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            collect_timing();
-        };
-        auto dots = [&](const double* Vs, int nv, const double* x) {
-            HIPCHK(dmrg::launch_multidot(Vs, nv, n, x, w.part, np, w.dots, s));
-            fetch(nv);
-        };
-        // device-side classical Gram-Schmidt (twice) of x against the first k columns of V, and
-        // normalization with the squared norm left in w.dots[slot]: no host round trip
-        auto orth_dev = [&](int k, double* x) {
-            for (int pass = 0; pass < 2 && k > 0; ++pass) {
-                HIPCHK(dmrg::launch_multidot(w.V, k, n, x, w.part, np, w.dots, s));
-                HIPCHK(dmrg::launch_project_out(w.V, k, n, w.dots, x, s));
-            }
-        };
-        auto normalize_dev = [&](double* x, int slot) {
-            HIPCHK(dmrg::launch_multidot(x, 1, n, x, w.part, np, w.dots + slot, s));
-            HIPCHK(dmrg::launch_scale_dev(x, w.dots + slot, n, s));
-        };
-        auto combine = [&](const double* Vs, int nv, const std::vector<double>& c, double* out, double beta) {
-            dmrg::Coefs cf;
-            for (int j = 0; j < nv; ++j) cf.c[j] = c[j];
-            HIPCHK(dmrg::launch_combine(Vs, nv, n, cf, out, beta, s));
-        };
-        auto normalize = [&](double* x) -> double {
-            dots(x, 1, x);
-            double nrm = std::sqrt(hd[0]);
-            if (!std::isfinite(nrm)) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
-            if (nrm == 0.0) return 0.0;
-            HIPCHK(dmrg::launch_scale(x, 1.0 / nrm, n, s));
-            return nrm;
-        };
-        const char* tr_env = std::getenv("DMRG_DAVIDSON_TRACE");
-        const bool trace = tr_env && tr_env[0] == '1';
-        double t_start = now();
-        HIPCHK(hipMemcpyAsync(w.V, psi, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        if (normalize(w.V) == 0.0) throw Error(DMRG_ERR_ARG, "start vector is zero");
-        matvec(w.V, w.W);
-        int k = 1;
-        std::vector<double> G((size_t)K * K, 0.0);
-        dots(w.V, 1, w.W);
-        G[0] = hd[0];
-        double theta = G[0], rnorm = INFINITY;
-        bool have_prev = false, converged = false;
-        int it = 0;
-        std::vector<double> evals, evecs;
-        double best_split_r = INFINITY;
-        int stall = 0;
-        bool mlp_on = o->precond == DMRG_PRECOND_MLP;
-        double best_mlp_r = INFINITY;
-        int mlp_stall = 0;
-        res->precond_fallback_iter = -1;
-        for (it = 1; it <= o->max_iter; ++it) {
-            std::vector<double> A((size_t)k * k);
-            for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j)
-                A[(size_t)i * k + j] = 0.5 * (G[(size_t)i * K + j] + G[(size_t)j * K + i]);
-            jacobi_eigh(k, A, evals, evecs);
-            int lo = 0;
-            for (int i = 1; i < k; ++i) if (evals[i] < evals[lo]) lo = i;
-            theta = evals[lo];
-            std::vector<double> sv(k), ms(k);
-            for (int i = 0; i < k; ++i) { sv[i] = evecs[(size_t)i * k + lo]; ms[i] = -theta * sv[i]; }
-            combine(w.V, k, sv, u, 0.0);               // u = V s
-            combine(w.W, k, sv, r, 0.0);               // r = W s
-            combine(w.V, k, ms, r, 1.0);               // r -= theta V s
-            dots(r, 1, r);
-            rnorm = std::sqrt(hd[0]);
-            if (trace) std::fprintf(stderr, "[dmrg_davidson] it %d k %d prec %d theta %.15f resid %.3e\n", it, k,
-                                    prec, theta, rnorm);
-            if (!std::isfinite(rnorm) || !std::isfinite(theta)) throw Error(DMRG_ERR_NAN, "non-finite Davidson residual");
-            if (prec == DMRG_PREC_SPLIT2 && o->fp64_polish) {
-                // hand over at split_tol, or, within 30x of it, when the split residual has stopped
-                // improving (no new minimum by 1% for 10 iterations: the matvec rounding floor has
-                // been reached; far above split_tol a plateau is ordinary Davidson progress)
-                bool hand_over = rnorm <= std::max(o->split_tol, o->tol);
-                if (rnorm < 0.99 * best_split_r) { best_split_r = rnorm; stall = 0; }
-                else if (++stall >= 10 && rnorm < 30.0 * o->split_tol) hand_over = true;
-                if (hand_over) {
-                    // restart in FP64 from the current Ritz vector
-                    prec = DMRG_PREC_FP64;
-                    HIPCHK(hipMemcpyAsync(w.V, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-                    normalize(w.V);
-                    matvec(w.V, w.W);
-                    dots(w.V, 1, w.W);
-                    k = 1;
-                    G[0] = hd[0];
-                    have_prev = false;
-                    continue;
-                }
-            }
-            if (rnorm <= o->tol) { converged = true; break; }
-            HIPCHK(dmrg::launch_precond(r, H->d_diag, theta, t, n, s));
-            if (k >= K) {
-                // restart: V <- orth{u, previous u}, W <- the same combinations of W (no new matvecs)
-                std::vector<std::vector<double>> Y;
-                Y.push_back(sv);
-                if (have_prev) {
-                    dots(w.V, k, w.prev);                // coefficients of u_prev in V
-                    std::vector<double> cp(hd.begin(), hd.begin() + k);
-                    // near convergence u_prev ~ u: project twice and drop a remainder that is mostly
-                    // rounding noise, otherwise the restarted basis is not orthonormal
-                    for (int pass = 0; pass < 2; ++pass) {
-                        double d = 0.0;
-                        for (int i = 0; i < k; ++i) d += cp[i] * sv[i];
-                        for (int i = 0; i < k; ++i) cp[i] -= d * sv[i];
-                    }
-                    double nn = 0.0; for (double v : cp) nn += v * v;
-                    nn = std::sqrt(nn);
-                    if (nn > 1e-6) { for (double& v : cp) v /= nn; Y.push_back(cp); }
-                }
-                while ((int)Y.size() > K - 1) Y.pop_back();   // leave room for the next vector
-                int kn = (int)Y.size();
-                double* scratch = restart_scratch;       // 2 * kn <= 4 vectors
-                for (int j = 0; j < kn; ++j) {
-                    combine(w.V, k, Y[j], scratch + (size_t)j * n, 0.0);
-                    combine(w.W, k, Y[j], scratch + (size_t)(kn + j) * n, 0.0);
-                }
-                for (int j = 0; j < kn; ++j) {
-                    HIPCHK(hipMemcpyAsync(w.V + (size_t)j * n, scratch + (size_t)j * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-                    HIPCHK(hipMemcpyAsync(w.W + (size_t)j * n, scratch + (size_t)(kn + j) * n, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-                }
-                std::vector<double> Gn((size_t)K * K, 0.0);
-                for (int a = 0; a < kn; ++a) for (int b = 0; b < kn; ++b) {
-                    double v = 0.0;
-                    for (int i = 0; i < k; ++i) for (int j = 0; j < k; ++j) v += Y[a][i] * G[(size_t)i * K + j] * Y[b][j];
-                    Gn[(size_t)a * K + b] = v;
-                }
-                G = Gn;
-                k = kn;
-            }
-            HIPCHK(hipMemcpyAsync(w.prev, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-            have_prev = true;
-            if (o->precond == DMRG_PRECOND_MLP && mlp_on) {
-                // the diagonal preconditioner is the network's yardstick: once the residual has made no new
-                // minimum (by 1%) for 20 iterations, the rest of the solve uses the diagonal correction
-                if (rnorm < 0.99 * best_mlp_r) { best_mlp_r = rnorm; mlp_stall = 0; }
-                else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
-            }
-            if (sess) sess->correction(r, u, t, theta, w.V, k, mlp_on);
-            // next basis vector, built in place on the device: orthogonalize, normalize, and once more
-            // after scaling (cheap insurance); its norm before scaling returns with the new column of G
-            double* vk = w.V + (size_t)k * n;
-            HIPCHK(hipMemcpyAsync(vk, t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-            orth_dev(k, vk);
-            normalize_dev(vk, K + 1);
-            orth_dev(k, vk);
-            normalize_dev(vk, K + 2);
-            matvec(vk, w.W + (size_t)k * n);
-            HIPCHK(dmrg::launch_multidot(w.V, k + 1, n, w.W + (size_t)k * n, w.part, np, w.dots, s));
-            fetch(K + 3);
-            const double nt = std::sqrt(hd[K + 1]);
-            if (!std::isfinite(nt) || !std::isfinite(hd[K + 2])) throw Error(DMRG_ERR_NAN, "non-finite vector in Davidson");
-            if (nt < 1e-14) break;                        // the correction lies in span(V): no new direction
-            for (int i = 0; i <= k; ++i) { G[(size_t)i * K + k] = hd[i]; G[(size_t)k * K + i] = hd[i]; }
-            ++k;
-        }
-        HIPCHK(hipMemcpyAsync(psi, u, n * sizeof(double), hipMemcpyDeviceToDevice, s));
-        HIPCHK(hipStreamSynchronize(s));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        res->energy = theta;
-        res->resid = rnorm;
-        res->iters = std::min(it, o->max_iter);
-        res->matvecs = matvecs;
-        res->matvecs_split = matvecs_split;
-        res->t_total = now() - t_start;
-        res->t_hpsi = t_hpsi;
-        if (rec) rec->rows_added = sess->rows_recorded();
-        if (!converged) { g_err = "Davidson did not converge"; return DMRG_NOT_CONVERGED; }
-        return DMRG_OK;
-    } catch (const Error& e) {
-        return fail(e);
-    }
-}

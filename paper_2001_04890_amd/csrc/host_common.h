@@ -1,4 +1,4 @@
-// Error handling shared by the host-side translation units of libdmrg (host.cpp, mlp_host.cpp).
+// Error handling shared by the host-side translation units of libdmrg.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -18,6 +18,8 @@ struct Error : std::runtime_error {
 // Stores e's message as the thread's dmrg_last_error() and returns its code.
 dmrg_status record_error(const Error& e);
 void clear_error();
+// The calling thread's last-error message (what dmrg_last_error returns), writable.
+std::string& last_error();
 double now_seconds();
 
 }  // namespace dmrg
