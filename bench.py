@@ -3,8 +3,10 @@
 Workload (the precision configuration): L = 24 orbitals, N = 24 (N_alpha = N_beta = 12),
 bond dimension M = 1024 per block at the middle bond (site 11 | 12), random integrals (seed 1),
 synthetic block operators with the real operator structure and Gaussian sector sizes (sigma = 1.5),
-built by dmrg_inputs/synthetic.py. One step = one Davidson iteration (H.psi in split-BF16 precision,
-Gram-Schmidt, Rayleigh-Ritz, residual, diagonal preconditioner), inputs resident in HBM.
+built by dmrg_inputs/synthetic.py. One step = one Davidson iteration at the paper's precision (FP64
+H.psi, Gram-Schmidt, Rayleigh-Ritz, residual, diagonal preconditioner), inputs resident in HBM; the
+headline `value` is its algorithmic H.psi TFLOP/s. The split-BF16 iteration, the relative matvec
+error and the time to |dE| <= 1e-6 of split + FP64 polish vs FP64 are reported beside it.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 
@@ -23,6 +25,11 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                        # GB/s
+# HBM traffic of one FP64 H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
+# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the launches of one call, scaled by the factors of
+# a 1 GiB device copy in the same runs (profiles/hpsi_fp64_L24_M1024_kernel_trace.md); None until
+# measured for the current kernels.
+FP64_TRAFFIC_L24_M1024 = None
 # HBM traffic of one split H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the k_pack_xt / k_zero_lds / k_hpsi_lds /
 # k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
@@ -128,9 +135,10 @@ def main():
         torch.cuda.synchronize()
         return time.perf_counter() - t, r
 
+    dav_steps(dm.PREC_FP64, args.warmup)
+    wall_64, r_64 = dav_steps(dm.PREC_FP64, args.steps)
     dav_steps(dm.PREC_SPLIT2, args.warmup)
     wall_sp, r_sp = dav_steps(dm.PREC_SPLIT2, args.steps)
-    wall_64, r_64 = dav_steps(dm.PREC_FP64, args.steps)
     s_iter_sp = wall_sp / args.steps
     s_iter_64 = wall_64 / args.steps
     value = st["flops"] * r_sp["matvecs"] / wall_sp / 1e12
@@ -158,44 +166,51 @@ def main():
     mlp_ms = mlp_apply_ms(hop, n, stream)
     log(f"[bench] learned preconditioner application: {mlp_ms:.3f} ms")
 
-    # --- roofline of the dominant kernel: the split H.psi launch sequence (k_pack_xt, the LDS-staged
-    #     k_hpsi_lds classes, the task-mode k_hpsi_small classes and the two k_reduce_lds launches)
-    achieved = st["flops"] / tsp / 1e12
+    # --- roofline of the dominant kernel: the FP64 H.psi launch sequence (the headline precision);
+    #     the split sequence's figures follow under "split_roofline"
     default_shape = (L, M, args.sigma, args.seed) == (24, 1024, 1.5, 1)
-    traffic = (SPLIT_TRAFFIC_L24_M1024["fetch_bytes"] + SPLIT_TRAFFIC_L24_M1024["write_bytes"]) if default_shape else None
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK["bf16"], 5), "traffic": traffic,
-                "traffic_note": "HBM bytes per split H.psi call (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, "
-                                "profiles/hpsi_split_L24_M1024_kernel_trace.md)" if traffic else None,
-                "kernel": "split H.psi sequence (k_hpsi_lds + k_hpsi_small + k_reduce_lds)",
-                "mfma_products_per_flop": 3,
-                "fp64_kernel": {"achieved": round(st["flops"] / t64 / 1e12, 3), "peak": PEAK["fp64"],
-                                "frac": round(st["flops"] / t64 / 1e12 / PEAK["fp64"], 4)},
+    achieved = st["flops"] / t64 / 1e12
+    tr64 = FP64_TRAFFIC_L24_M1024 if default_shape else None
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK["fp64"], 4),
+                "traffic": (tr64["fetch_bytes"] + tr64["write_bytes"]) if tr64 else None,
+                "kernel": "FP64 H.psi sequence (k_pack, k_hpsi_f64 tile classes, k_big64 passes, k_reduce)",
                 "algorithmic_bytes": st["bytes"],
-                "hbm_frac_split": round(st["bytes"] / tsp / 1e9 / HBM_PEAK, 4)}
+                "hbm_frac": round(st["bytes"] / t64 / 1e9 / HBM_PEAK, 4)}
+    achieved_sp = st["flops"] / tsp / 1e12
+    traffic_sp = (SPLIT_TRAFFIC_L24_M1024["fetch_bytes"] + SPLIT_TRAFFIC_L24_M1024["write_bytes"]) \
+        if default_shape else None
+    split_roofline = {"bound": "mfma", "achieved": round(achieved_sp, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
+                      "frac": round(achieved_sp / PEAK["bf16"], 5), "traffic": traffic_sp,
+                      "kernel": "split H.psi sequence (k_hpsi_lds + k_hpsi_small + k_reduce_lds)",
+                      "mfma_products_per_flop": 3,
+                      "algorithmic_bytes": st["bytes"] / 2,
+                      "hbm_frac": round(st["bytes"] / 2 / tsp / 1e9 / HBM_PEAK, 4)}
 
     # --- CPU oracle on a bounded sample of the same workload
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(h, eri, left, right, na, nb, site, n)
+        cpu = cpu_baseline(h, eri, left, right, na, nb, site, n, st["flops"])
 
     out = {
         "metric": "H·ψ TFLOP/s & Davidson s/iter, split-FP32 vs FP64 at |ΔE|≤1e-6 Eh",
-        "value": round(value, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(s_iter_sp * 1e3, 3), "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16", "accumulate": "fp32", "data": "synthetic",
+        "value": round(value_64, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(s_iter_64 * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"two-site H.psi + Davidson iteration, L={L} N={na + nb} ({na},{nb}) M={M} "
                                f"middle bond, synthetic block operators sigma={args.sigma}",
                    "n_coeff": n, "psi_blocks": hop.n_blocks, "n_alpha": st["n_alpha"], "n_tasks": st["n_tasks"],
                    "flops_per_matvec": st["flops"]},
         "fp64": {"tflops": round(value_64, 3), "ms_per_iter": round(s_iter_64 * 1e3, 3),
                  "kernel_ms": round(t64 * 1e3, 4)},
-        "split": {"tflops": round(value, 3), "ms_per_iter": round(s_iter_sp * 1e3, 3),
-                  "kernel_ms": round(tsp * 1e3, 4), "rel_matvec_err": rel_mv},
+        "split": {"dtype": "bf16 hi/lo products, fp32 accumulation", "tflops": round(value, 3),
+                  "ms_per_iter": round(s_iter_sp * 1e3, 3), "kernel_ms": round(tsp * 1e3, 4),
+                  "rel_matvec_err": rel_mv},
         "converge": conv,
         "mlp_precond_ms": round(mlp_ms, 4),
         "build_seconds": round(t_build, 2),
         "roofline": roofline,
+        "split_roofline": split_roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
@@ -473,30 +488,49 @@ def bench_renorm(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(h, eri, left, right, na, nb, site, n):
-    """The oracle's full H.psi of the same workload, single-threaded numpy, repeated until at least
-    10 s of CPU work (at most 3 calls); the oracle's setup (task list) is not timed."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(h, eri, left, right, na, nb, site, n, flops):
+    """The oracle's full H.psi of the same workload (numpy / OpenBLAS FP64 on every host core this
+    process may use), repeated until at least 10 s of work (at most 3 calls); the oracle's setup
+    (its task list) is not timed. The rate is the library's algorithmic flop count of one H.psi (the
+    metric's unit of work) over the oracle's seconds per H.psi; the oracle's own decomposition
+    executes a slightly different task list, reported beside it."""
     from threadpoolctl import threadpool_limits
 
     from dmrg_inputs import random_vector
     from oracle.hpsi import OracleHop
-    log("[bench] cpu baseline: oracle setup (untimed)")
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    log(f"[bench] cpu baseline: oracle setup (untimed), {cores} threads")
     oh = OracleHop(h, eri, left, right, na, nb, site)
     tasks = oh.tasks()
-    fl = oh.flops(tasks)
+    fl_oracle = oh.flops(tasks)
     x = random_vector(n, 7)
     calls, dt = 0, 0.0
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=cores):
         while calls < 3 and dt < 10.0:
             t = time.perf_counter()
             oh.apply(x, tasks=tasks)
             dt += time.perf_counter() - t
             calls += 1
-    log(f"[bench] cpu baseline: {calls} x {fl:.3e} flops in {dt:.1f}s")
-    return {"value": round(calls * fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "seconds": round(dt, 2),
-            "sample": f"{calls} full H.psi call(s) of the same workload ({len(tasks)} sector tasks, {fl:.3e} flops "
-                      f"each), oracle numpy FP64 on one host thread; oracle setup untimed"}
+    s_call = dt / calls
+    log(f"[bench] cpu baseline: {calls} H.psi calls in {dt:.1f}s ({s_call:.2f} s each)")
+    return {"value": round(flops / s_call / 1e12, 6), "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+            "seconds": round(dt, 2), "seconds_per_hpsi": round(s_call, 3), "cpu_model": _cpu_model(),
+            "nproc": os.cpu_count(),
+            "sample": f"{calls} full H.psi call(s) of the same workload (FP64, numpy/OpenBLAS on {cores} host "
+                      f"threads; rate = the library's {flops:.4e} algorithmic flops per H.psi / seconds per "
+                      f"call; the oracle's own task list has {len(tasks)} sector tasks, {fl_oracle:.4e} flops); "
+                      f"oracle setup untimed"}
 
 
 def mlp_apply_ms(hop, n, stream, reps=5):

@@ -119,9 +119,12 @@ typedef struct {
     int32_t share;           /* 0: every operator of the sets below must be supplied (missing ->
                                 DMRG_ERR_ARG). 1: one device's share of the sum over operator
                                 combinations (the paper's distribution of the combinations over
-                                processes, Section 2.2.1): combinations that need an operator the
-                                blocks do not supply, directly or inside a pre-summed operator, are
-                                left out, and H.psi is the sum over the remaining ones */
+                                processes, Section 2.2.1), defined term by term: H.psi is the sum of
+                                the Hamiltonian terms (left operator) x (site part) x (right operator)
+                                whose left and right block operators are both supplied (identity
+                                counts as supplied); a pre-summed left operator keeps its supplied
+                                summands. Shares of disjoint operator pairs add up to the full sum
+                                (terms without block operators belong to every share) */
 } dmrg_build_opts;
 
 /* Build the H.psi operator of one bond, once per bond and before Davidson starts (the pre-generated
@@ -235,6 +238,55 @@ dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t
                                     const double* A, int64_t a_len, const int64_t* out_off, double* out,
                                     int64_t out_len, void* stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Growth and renormalization of a block (Section 2.1: the operators of the enlarged block, its
+ * truncation by the M eigenvectors of rho with the largest eigenvalues, Eq. renorm, Eq. renorm_mat;
+ * Section 2.2.2).
+ * side 0 grows the left block of the bond (site, site+1): orbitals [0, site) + orbital `site` become
+ * the left block of the bond (site+1, site+2), with the normal set H, C (P in the block), A (P < Q),
+ * B (P <= Q only: B_QP = B_PQ^T), S (W >= 2(site+1)). side 1 grows the right block: orbital site+1 +
+ * orbitals [site+2, L) become the right block of the bond (site-1, site), with the complementary set
+ * H, C (Z in the block), U (P < 2(site+1)), P (P < Q < 2(site+1)), Q (X <= Y < 2(site+1) only: Q_YX =
+ * Q_XY^T). Every grown operator is formed from its definition with single stored operators of the
+ * old block (pre-summed over old-block indices where the definition sums them), so operators that are
+ * projections of the exact ones stay so. The basis of the enlarged block is the one of
+ * dmrg_rdm_left_layout / dmrg_rdm_right_layout: sectors ascending, left pairs (a, s) in (a, s) order,
+ * right pairs (s, d) in (s, d) order. The new block's sectors are the enlarged sectors that keep
+ * states, ascending; its states in sector q are the kept columns of O_q in order.
+ * The returned block is owned by the library (host arrays, valid until dmrg_block_free) and can be
+ * passed to dmrg_build_blocks and grown again. FP64, on the GPU (pre-sums and O^T Z O per sector
+ * block); synchronizes the stream.
+ * ------------------------------------------------------------------------------------------- */
+
+/* Sectors of the enlarged block (block + site) that `block` grows into: *n_sec, and when not NULL qn
+ * (2 * n_sec) and dims (n_sec). Host only. */
+dmrg_status dmrg_block_grow_layout(const dmrg_block* block, int32_t side, int32_t* n_sec, int32_t* qn,
+                                   int32_t* dims);
+
+/* Grow `block` (host data, as for dmrg_build_blocks) by one site at the bond of `problem` (its site
+ * field) and renormalize it with the caller's O: kept (host, n_sec of dmrg_block_grow_layout: states
+ * kept per enlarged sector, 0 <= kept <= dims) and O (host, per enlarged sector a dims x kept
+ * row-major matrix whose columns span the kept states, concatenated in sector order). kept = O = NULL
+ * keeps every state (exact growth). Runs on opts->device / opts->stream. *out receives a
+ * library-owned block. Errors: DMRG_ERR_ARG (missing operator of the old block, bad side or kept),
+ * DMRG_ERR_NAN, DMRG_ERR_NOMEM, DMRG_ERR_DEVICE. */
+dmrg_status dmrg_block_grow(const dmrg_problem* problem, const dmrg_block* block, int32_t side, const int32_t* kept,
+                            const double* O, const dmrg_build_opts* opts, dmrg_block** out);
+
+/* One renormalization step of the sweep for the handle's bond: rho of the enlarged block from the
+ * device vector psi (dir 0: rho^L = psi psi^T, growing the left block; dir 1: rho^R = psi^T psi,
+ * growing the right block), its M-state cut with M = m_max (dmrg_truncate: the m_max largest
+ * eigenvalues over all sectors), and the grown block's operators renormalized with those eigenvectors
+ * (Eq. renorm_mat), using the handle's device copy of the old block. *out receives a library-owned
+ * block; *discarded (may be NULL) the discarded weight (trace of rho minus the kept eigenvalues).
+ * Works on handles built with a device (not merged ones). Synchronizes `stream`. */
+dmrg_status dmrg_renormalize(dmrg_hop* hop, const double* psi, int32_t dir, int32_t m_max, dmrg_block** out,
+                             double* discarded, void* stream);
+
+/* Release a block returned by dmrg_block_grow / dmrg_renormalize (NULL and blocks the library did not
+ * create are ignored). */
+void dmrg_block_free(dmrg_block* block);
+
 /* Davidson's method for the lowest eigenpair (Sections 2.1, 2.2.1). FP64 basis, Gram-Schmidt
  * (classical, applied twice), Rayleigh-Ritz and energies; the matvec runs in `precision`.
  * With precision = SPLIT2 and fp64_polish = 1 the solve switches to FP64 matvecs (restarting from the
@@ -317,6 +369,52 @@ dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, vo
  * Matrix id -1 is the identity. Pass NULL arrays to query the counts. */
 dmrg_status dmrg_hop_export_tasks(const dmrg_hop* hop, int64_t* n_tasks, int32_t* quads, double* f,
                                   int64_t* n_terms, int32_t* term_int, double* term_coeff);
+
+/* ---------------------------------------------------------------------------------------------
+ * Two-site DMRG sweeps (Section 2.1). Warm-up: the right blocks of the last 1 .. L-2 orbitals are
+ * grown from the vacuum (dmrg_block_grow), each step keeping at most m_warmup states of the enlarged
+ * block (every state while they fit; else a seeded random orthonormal basis per sector, with the kept
+ * counts spread over the sectors near the filling N k / L of the block's k orbitals). Sweep j (of
+ * n_sweeps, bond dimension m_per_sweep[j]): forward over the bonds (0, 1) .. (L-2, L-1) -- Davidson
+ * for the lowest eigenpair (seeded random start vector), then dmrg_renormalize of the left block --
+ * and backward over (L-3, L-2) .. (0, 1), renormalizing the right block (the solve at (L-2, L-1)
+ * and, between sweeps, at (0, 1) serves both directions). Each solve builds its H.psi with
+ * dmrg_build_blocks from the current blocks, so every step runs on the GPU; blocks are kept in host
+ * memory between bonds.
+ * ------------------------------------------------------------------------------------------- */
+typedef struct {
+    int32_t        n_sweeps;       /* >= 1 */
+    const int32_t* m_per_sweep;    /* n_sweeps bond dimensions (M of each sweep, >= 1) */
+    int32_t        m_warmup;       /* states kept per warm-up growth step (>= 1) */
+    double         tol;            /* Davidson residual tolerance per bond */
+    int32_t        max_iter;       /* Davidson iterations per bond */
+    int32_t        max_sub;        /* Davidson subspace size (2 .. 64) */
+    int32_t        precision;      /* DMRG_PREC_* of the matvec */
+    int32_t        fp64_polish;    /* see dmrg_dav_opts */
+    double         split_tol;
+    uint64_t       seed;           /* warm-up bases and start vectors (splitmix64 stream) */
+    int32_t        device;
+    void*          stream;
+    int32_t        verbose;        /* 1: one line per solve on stderr */
+} dmrg_sweep_opts;
+
+typedef struct {
+    int32_t  capacity;             /* length of the caller's arrays below (they may be NULL) */
+    double*  energies;             /* per Davidson solve, in order: lowest Ritz value */
+    double*  discarded;            /* discarded weight of the renormalization after that solve (0 if none) */
+    int32_t* iters;                /* Davidson iterations */
+    int32_t* sites;                /* left site of the solve's bond */
+    int32_t  n_solves;             /* solves performed (n_sweeps (2L - 3) + 1) */
+    int32_t  n_not_converged;      /* solves that reached max_iter */
+    double   energy;               /* energy of the last solve */
+    double   best_energy;          /* lowest energy of any solve */
+    double   seconds;              /* wall time */
+} dmrg_sweep_result;
+
+/* Run the warm-up and n_sweeps sweeps for `problem` (its site field is ignored). Returns
+ * DMRG_NOT_CONVERGED when some Davidson solve reached max_iter (the sweep goes on with its best
+ * pair), errors as the calls it makes. */
+dmrg_status dmrg_sweep(const dmrg_problem* problem, const dmrg_sweep_opts* opts, dmrg_sweep_result* result);
 
 /* ---------------------------------------------------------------------------------------------
  * Learned Davidson preconditioner (an addition to the method of the paper, which uses Davidson's

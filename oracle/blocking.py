@@ -169,3 +169,75 @@ class GrownLeft:
         ops += [op("S", W, -1, self.S(W)) for W in range(2 * self.site + 2, 2 * L)]
         return Block(side="left", orbitals=tuple(range(self.site + 1)), qn=np.array(qs, dtype=np.int32),
                      dim=np.array([O[q].shape[1] for q in qs], dtype=np.int32), ops=ops)
+
+
+# ---------------------------------------------------------------- growth by the Fock-space route
+def _fock_basis(block):
+    """(root exact block, per-sector basis columns over the root's sector states) of a block built by
+    ``oracle.fock`` (exact, or truncated by projection)."""
+    if hasattr(block, "bases"):
+        root = block.parent
+        ridx = root.sector_index()
+        return root, {i: (ridx[(int(q[0]), int(q[1]))], block.bases[i]) for i, q in enumerate(block.qn)}
+    return block, {i: (i, np.eye(int(block.dim[i]))) for i in range(block.n_sec)}
+
+
+def grown_block(side, block, site, O, t, w):
+    """The block grown by one site and renormalized by O (Eq. renorm_mat), from the definition: every
+    operator of the grown orbital set taken exactly in its own Fock space (``oracle.fock``) and
+    projected onto the kept basis. Valid for blocks whose operators are projections of the exact
+    ones (exact blocks and their truncations), which is what Section 2.1 asks of stored operators.
+
+    side  : "left" (block = orbitals 0 .. site-1, grown by orbital ``site``) or "right" (block =
+            orbitals site+1 .. L-1, grown by orbital ``site``, i.e. the site becomes the first orbital)
+    O     : enlarged sector q -> (dim_q, kept_q) orthonormal columns, rows in the enlarged basis of
+            ``oracle.renorm.enlarged_left_basis`` / ``enlarged_right_basis`` of ``block``
+    Returns the renormalized Block (sectors = the q with kept_q > 0, ascending), with ``bases`` over
+    the grown orbitals' Fock space (so it can grow again).
+    """
+    from oracle.fock import exact_block
+    n_modes = t.shape[0]
+    L = n_modes // 2
+    root, basis = _fock_basis(block)
+    k = len(block.orbitals)
+    if side == "left":
+        orbitals = tuple(range(0, site + 1))
+        outside = [P for P in range(n_modes) if P // 2 > site]
+        parts, dims = renorm.enlarged_left_basis(block)
+    else:
+        orbitals = tuple(range(site, L))
+        outside = [P for P in range(n_modes) if P // 2 < site]
+        parts, dims = renorm.enlarged_right_basis(block)
+    grown = exact_block(list(orbitals), side, t, w, outside)
+    F = grown.fock
+    Froot = getattr(root, "fock", None)
+    gidx = {tuple(int(v) for v in q): i for i, q in enumerate(grown.qn)}
+    pos = {}                                      # grown Fock state -> (sector, position)
+    for i, states in enumerate(F.sector_states):
+        for p, s in enumerate(states):
+            pos[int(s)] = (i, p)
+    bases = [np.zeros((int(d), 0)) for d in grown.dim]
+    for q in dims:
+        if q not in O or O[q].shape[1] == 0:
+            continue
+        gi = gidx[q]
+        E = np.zeros((int(grown.dim[gi]), dims[q]))   # enlarged basis of sector q over the grown Fock states
+        for entry in parts[q]:
+            if side == "left":
+                a, s, st, m = entry
+            else:
+                s, a, st, m = entry
+            ri, V = basis[a]
+            states = Froot.sector_states[ri] if Froot is not None else np.zeros(1, dtype=np.int64)
+            for col in range(m):
+                for r, x in enumerate(states):
+                    if V[r, col] == 0.0:
+                        continue
+                    # product state -> grown Fock determinant, sign +1 (ascending modes, parts in order)
+                    g = (int(x) | (s << (2 * k))) if side == "left" else (s | (int(x) << 2))
+                    sec, p = pos[g]
+                    assert sec == gi
+                    E[p, st + col] += V[r, col]
+        bases[gi] = E @ O[q]
+    from oracle.fock import truncate
+    return truncate(grown, bases)

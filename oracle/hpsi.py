@@ -50,12 +50,36 @@ def presum_left(block, terms):
 class OracleHop:
     """H.psi at the bond (s1, s1+1) for given left/right blocks, following Section 2.2.1."""
 
-    def __init__(self, h, eri, left, right, n_alpha, n_beta, s1, alphas=None):
+    def __init__(self, h, eri, left, right, n_alpha, n_beta, s1, alphas=None, share=False):
+        """share: one device's share of the sum over combinations (Section 2.2.1 distributes them):
+        H restricted to the terms (left operator) x (site part) x (right operator) whose left and
+        right block operators are both supplied by the blocks -- a pre-summed left operator keeps
+        its supplied summands, a combination whose right operator is missing is left out."""
         self.left, self.right = left, right
         self.layout = Layout(left, right, n_alpha, n_beta)
         t, w = spin_orbital_integrals(h, eri)
         self.alphas = alphas if alphas is not None else expand(t, w, h.shape[0], s1)
+        if share:
+            self.alphas = self._share(self.alphas)
         self._prepare()
+
+    def _supplied(self, block, desc):
+        kind, i0, i1, _ = desc
+        if kind == "I":
+            return True
+        if block.get(kind, i0, i1) is not None:
+            return True
+        return kind in ("B", "Q") and block.get(kind, i1, i0) is not None
+
+    def _share(self, alphas):
+        kept = []
+        for al in alphas:
+            if not self._supplied(self.right, al["right"]):
+                continue
+            left = [(c, d) for c, d in al["left"] if self._supplied(self.left, d)]
+            if left:
+                kept.append(dict(al, left=left))
+        return kept
 
     def _prepare(self):
         lnum = self.left.qn.sum(axis=1)
@@ -132,6 +156,26 @@ class OracleHop:
                 T = T.reshape(nj, mj, nv).transpose(1, 0, 2)
             y[offj:offj + mj * nj] += f * T.reshape(mj * nj, nv)
         return y.reshape(x.shape)
+
+    def magnitude(self, x, targets=None, tasks=None):
+        """sum over tasks of |f| |A| |X| |B|^T (absolute values taken element by element): the size
+        of the summands of every output element, which bounds the rounding error of a summation in
+        any order and precision of the same summands (x of shape (n,))."""
+        lay = self.layout
+        ax = np.abs(x)
+        y = np.zeros_like(ax)
+        if tasks is None:
+            tasks = self.tasks() if targets is None else self.target_tasks(targets)
+        for i, j, f, A, B in tasks:
+            _, _, _, _, off, ma, md = lay.blocks[i]
+            _, _, _, _, offj, mj, nj = lay.blocks[j]
+            T = ax[off:off + ma * md].reshape(ma, md)
+            if A is not None:
+                T = np.abs(A) @ T
+            if B is not None:
+                T = T @ np.abs(B).T
+            y[offj:offj + mj * nj] += abs(f) * T.ravel()
+        return y
 
     def diagonal(self):
         """diag(H): sum over combinations mapping a block to itself of f diag(A_l) diag(A_r)^T."""

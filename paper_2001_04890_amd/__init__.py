@@ -5,8 +5,9 @@ runs inside the HIP library (``csrc/``). PyTorch supplies device memory and stre
 CPU fallback: importing the package fails loudly when ``libdmrg.so`` is missing.
 """
 from .binding import (DMRG_OK, DMRG_NOT_CONVERGED, MLP_IN, MLP_PARAMS, PREC_FP64, PREC_SPLIT2, DmrgError,
-                      Hop, Mlp, lib, lib_path, renormalize_blocks, truncate, version)
+                      Hop, Mlp, block_grow, block_grow_layout, lib, lib_path, renormalize_blocks, sweep, truncate,
+                      version)
 
 __all__ = ["Hop", "Mlp", "DmrgError", "PREC_FP64", "PREC_SPLIT2", "DMRG_OK", "DMRG_NOT_CONVERGED", "MLP_IN",
-           "MLP_PARAMS", "lib", "lib_path", "renormalize_blocks", "truncate",
+           "MLP_PARAMS", "block_grow", "block_grow_layout", "lib", "lib_path", "renormalize_blocks", "sweep", "truncate",
            "version"]

@@ -62,6 +62,19 @@ class DavResult(C.Structure):
                 ("precond_fallback_iter", C.c_int32)]
 
 
+class SweepOpts(C.Structure):
+    _fields_ = [("n_sweeps", C.c_int32), ("m_per_sweep", i32p), ("m_warmup", C.c_int32), ("tol", C.c_double),
+                ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32), ("fp64_polish", C.c_int32),
+                ("split_tol", C.c_double), ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
+                ("verbose", C.c_int32)]
+
+
+class SweepResult(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("energies", f64p), ("discarded", f64p), ("iters", i32p), ("sites", i32p),
+                ("n_solves", C.c_int32), ("n_not_converged", C.c_int32), ("energy", C.c_double),
+                ("best_energy", C.c_double), ("seconds", C.c_double)]
+
+
 lib.dmrg_last_error.restype = C.c_char_p
 lib.dmrg_version.restype = C.c_char_p
 lib.dmrg_build_blocks.argtypes = [C.POINTER(Problem), C.POINTER(BlockDesc), C.POINTER(BlockDesc),
@@ -93,6 +106,18 @@ lib.dmrg_renormalize_blocks.argtypes = [C.c_int32, C.c_int32, i32p, i32p, i64p, 
                                         i32p, i32p, i64p, C.c_void_p, C.c_int64, i64p, C.c_void_p, C.c_int64,
                                         C.c_void_p]
 lib.dmrg_renormalize_blocks.restype = C.c_int32
+lib.dmrg_block_grow_layout.argtypes = [C.POINTER(BlockDesc), C.c_int32, i32p, i32p, i32p]
+lib.dmrg_block_grow_layout.restype = C.c_int32
+lib.dmrg_block_grow.argtypes = [C.POINTER(Problem), C.POINTER(BlockDesc), C.c_int32, i32p, f64p, C.POINTER(BuildOpts),
+                                C.POINTER(C.POINTER(BlockDesc))]
+lib.dmrg_block_grow.restype = C.c_int32
+lib.dmrg_renormalize.argtypes = [C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.POINTER(BlockDesc)),
+                                 f64p, C.c_void_p]
+lib.dmrg_renormalize.restype = C.c_int32
+lib.dmrg_block_free.argtypes = [C.POINTER(BlockDesc)]
+lib.dmrg_block_free.restype = None
+lib.dmrg_sweep.argtypes = [C.POINTER(Problem), C.POINTER(SweepOpts), C.POINTER(SweepResult)]
+lib.dmrg_sweep.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
 lib.dmrg_davidson.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
@@ -177,20 +202,114 @@ def truncate(rho, dims, M):
             [vecs[off[i]:off[i + 1]].reshape(dims[i], dims[i]) for i in range(dims.size)], float(disc[0]))
 
 
+def _device_f64(t, device, what):
+    """The C-ABI reads 8-byte doubles from device memory: refuse tensors of another dtype or device."""
+    if torch is not None and isinstance(t, torch.Tensor):
+        if t.dtype != torch.float64:
+            raise TypeError(f"{what} must be float64, got {t.dtype}")
+        if t.device.type != "cuda" or (device is not None and t.device.index != device):
+            raise ValueError(f"{what} must be on cuda:{device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+
+
 def renormalize_blocks(dims, kept, o_off, O, sec_out, sec_in, a_off, A, out_off, out, device=0, stream=None):
     """dmrg_renormalize_blocks: index arrays on the host (numpy), O, A, out device tensors (float64)."""
     dims, kept = np.ascontiguousarray(dims, dtype=np.int32), np.ascontiguousarray(kept, dtype=np.int32)
     o_off = np.ascontiguousarray(o_off, dtype=np.int64)
     sec_out, sec_in = np.ascontiguousarray(sec_out, dtype=np.int32), np.ascontiguousarray(sec_in, dtype=np.int32)
     a_off, out_off = np.ascontiguousarray(a_off, dtype=np.int64), np.ascontiguousarray(out_off, dtype=np.int64)
-    for t in (O, A, out):
-        assert t.is_contiguous()
+    for t, what in ((O, "O"), (A, "A"), (out, "out")):
+        _device_f64(t, device, what)
     _check(lib.dmrg_renormalize_blocks(int(device), int(dims.size), _ptr(dims, C.c_int32), _ptr(kept, C.c_int32),
                                        _ptr(o_off, C.c_int64), C.c_void_p(O.data_ptr()), int(O.numel()),
                                        int(sec_out.size), _ptr(sec_out, C.c_int32), _ptr(sec_in, C.c_int32),
                                        _ptr(a_off, C.c_int64), C.c_void_p(A.data_ptr()), int(A.numel()),
                                        _ptr(out_off, C.c_int64), C.c_void_p(out.data_ptr()), int(out.numel()),
                                        _stream_ptr(stream)))
+
+
+_KIND_NAME = {v: k for k, v in _KIND.items()}
+
+
+def _take_block(ptr, side, orbitals):
+    """Copy a library-owned dmrg_block into a dmrg_inputs Block and release it."""
+    from dmrg_inputs.blocks import Block, Op
+    try:
+        d = ptr.contents
+        n_sec = d.n_sec
+        qn = np.array([d.qn[i] for i in range(2 * n_sec)], dtype=np.int32).reshape(-1, 2)
+        dim = np.array([d.dim[i] for i in range(n_sec)], dtype=np.int32)
+        data = np.ctypeslib.as_array(d.data, shape=(max(1, d.n_data),))[:d.n_data].copy() if d.n_data else np.zeros(0)
+        ops = []
+        for k in range(d.n_ops):
+            o = d.ops[k]
+            blocks = {}
+            for j in range(o.n_blk):
+                so, si, off = o.sec_out[j], o.sec_in[j], o.off[j]
+                r, c = int(dim[so]), int(dim[si])
+                blocks[(so, si)] = data[off:off + r * c].reshape(r, c).copy()
+            ops.append(Op(_KIND_NAME[o.kind], o.i0, o.i1, blocks))
+        return Block(side=side, orbitals=tuple(orbitals), qn=qn, dim=dim, ops=ops)
+    finally:
+        lib.dmrg_block_free(ptr)
+
+
+def block_grow_layout(block, side):
+    """Enlarged sectors (qn (n, 2), dims (n,)) that ``block`` grows into (dmrg_block_grow_layout)."""
+    m = _BlockMarshal(block)
+    n = C.c_int32()
+    _check(lib.dmrg_block_grow_layout(C.byref(m.desc), int(side), C.byref(n), None, None))
+    qn = np.zeros(2 * n.value, dtype=np.int32)
+    dims = np.zeros(n.value, dtype=np.int32)
+    _check(lib.dmrg_block_grow_layout(C.byref(m.desc), int(side), C.byref(n), _ptr(qn, C.c_int32),
+                                      _ptr(dims, C.c_int32)))
+    return qn.reshape(-1, 2), dims
+
+
+def block_grow(h, eri, n_alpha, n_beta, site, block, side, kept=None, O=None, device=0, stream=None):
+    """dmrg_block_grow: ``block`` grown by one site at the bond (site, site+1) and renormalized by O
+    (a list of per-enlarged-sector (dims, kept) arrays, or None to keep every state). Returns a Block."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    L = h.shape[0]
+    prob = Problem(L, n_alpha, n_beta, site, _ptr(h, C.c_double), _ptr(eri, C.c_double))
+    m = _BlockMarshal(block)
+    opts = BuildOpts(device, 0, 0, _stream_ptr(stream), 0)
+    kp = op = None
+    if O is not None:
+        kk = np.ascontiguousarray([o.shape[1] for o in O], dtype=np.int32)
+        flat = np.ascontiguousarray(np.concatenate([np.asarray(o, dtype=np.float64).ravel() for o in O] + [np.zeros(0)]))
+        kp, op = _ptr(kk, C.c_int32), _ptr(flat, C.c_double)
+    out = C.POINTER(BlockDesc)()
+    _check(lib.dmrg_block_grow(C.byref(prob), C.byref(m.desc), int(side), kp, op, C.byref(opts), C.byref(out)))
+    orbitals = range(0, site + 1) if side == 0 else range(site + 1, L)
+    return _take_block(out, "left" if side == 0 else "right", orbitals)
+
+
+def sweep(h, eri, n_alpha, n_beta, m_per_sweep, m_warmup=None, tol=1e-8, max_iter=300, max_sub=24,
+          precision=PREC_FP64, fp64_polish=False, split_tol=1e-5, seed=0, device=0, stream=None, verbose=False):
+    """dmrg_sweep: warm-up plus len(m_per_sweep) two-site sweeps. Returns a dict with the per-solve
+    energies, discarded weights, iterations and bond sites, and the run's summary fields."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    eri = np.ascontiguousarray(eri, dtype=np.float64)
+    L = h.shape[0]
+    ms = np.ascontiguousarray(m_per_sweep, dtype=np.int32)
+    prob = Problem(L, n_alpha, n_beta, 0, _ptr(h, C.c_double), _ptr(eri, C.c_double))
+    opts = SweepOpts(int(ms.size), _ptr(ms, C.c_int32), int(m_warmup if m_warmup else ms[0]), tol, max_iter, max_sub,
+                     precision, 1 if fp64_polish else 0, split_tol, seed, device, _stream_ptr(stream),
+                     1 if verbose else 0)
+    cap = int(ms.size) * (2 * L) + 2
+    e = np.zeros(cap)
+    d = np.zeros(cap)
+    it = np.zeros(cap, dtype=np.int32)
+    si = np.zeros(cap, dtype=np.int32)
+    res = SweepResult(cap, _ptr(e, C.c_double), _ptr(d, C.c_double), _ptr(it, C.c_int32), _ptr(si, C.c_int32))
+    st = _check(lib.dmrg_sweep(C.byref(prob), C.byref(opts), C.byref(res)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
+    n = res.n_solves
+    return dict(energies=e[:n], discarded=d[:n], iters=it[:n], sites=si[:n], energy=res.energy,
+                best_energy=res.best_energy, seconds=res.seconds, n_not_converged=res.n_not_converged,
+                converged=st == DMRG_OK)
 
 
 class _BlockMarshal:
@@ -250,6 +369,8 @@ class Hop:
                                      C.byref(handle)))
         self._h = handle
         self.device = device
+        self.site = site
+        self.L = h.shape[0]
         self._load_layout()
 
     def _load_layout(self):
@@ -300,7 +421,8 @@ class Hop:
     def hpsi(self, x, y, precision=PREC_FP64, stream=None):
         """y = H x for device tensors (torch, float64) of shape (n,) or (nvec, n)."""
         nvec = 1 if x.dim() == 1 else x.shape[0]
-        assert x.dtype == y.dtype and x.is_contiguous() and y.is_contiguous()
+        _device_f64(x, self.device, "x")
+        _device_f64(y, self.device, "y")
         assert x.numel() == nvec * self.n_coeff and y.numel() == x.numel()
         _check(lib.dmrg_hpsi(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nvec, precision,
                              _stream_ptr(stream)))
@@ -308,13 +430,15 @@ class Hop:
     def hpsi_graph(self, x, y, precision=PREC_FP64, stream=None):
         """Same as hpsi, replaying a cached hipGraph of the launch sequence for these buffers."""
         nvec = 1 if x.dim() == 1 else x.shape[0]
-        assert x.dtype == y.dtype and x.is_contiguous() and y.is_contiguous()
+        _device_f64(x, self.device, "x")
+        _device_f64(y, self.device, "y")
         assert x.numel() == nvec * self.n_coeff and y.numel() == x.numel()
         _check(lib.dmrg_hpsi_graph(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nvec, precision,
                                    _stream_ptr(stream)))
 
     def diagonal(self, d, stream=None):
-        assert d.numel() == self.n_coeff and d.is_contiguous()
+        _device_f64(d, self.device, "d")
+        assert d.numel() == self.n_coeff
         _check(lib.dmrg_hop_diagonal(self._h, C.c_void_p(d.data_ptr()), _stream_ptr(stream)))
 
     def _rdm_layout(self, fn):
@@ -327,7 +451,9 @@ class Hop:
         return qn.reshape(-1, 2), dims, off
 
     def _rdm(self, fn, psi, rho, stream):
-        assert psi.numel() == self.n_coeff and psi.is_contiguous() and rho.is_contiguous()
+        _device_f64(psi, self.device, "psi")
+        _device_f64(rho, self.device, "rho")
+        assert psi.numel() == self.n_coeff
         _check(fn(self._h, C.c_void_p(psi.data_ptr()), C.c_void_p(rho.data_ptr()), int(rho.numel()),
                   _stream_ptr(stream)))
 
@@ -347,12 +473,25 @@ class Hop:
         """rho^R = psi^T psi per sector (dmrg_rdm_right) into the device buffer rho."""
         self._rdm(lib.dmrg_rdm_right, psi, rho, stream)
 
+    def renormalize(self, psi, direction, m_max, stream=None):
+        """dmrg_renormalize: rho from psi, the m_max-state cut and the grown block's renormalized
+        operators. direction 0 grows the left block, 1 the right block. Returns (Block, discarded)."""
+        _device_f64(psi, self.device, "psi")
+        assert psi.numel() == self.n_coeff
+        out = C.POINTER(BlockDesc)()
+        disc = C.c_double()
+        _check(lib.dmrg_renormalize(self._h, C.c_void_p(psi.data_ptr()), int(direction), int(m_max), C.byref(out),
+                                    C.byref(disc), _stream_ptr(stream)))
+        orbitals = range(0, self.site + 1) if direction == 0 else range(self.site + 1, self.L)
+        return _take_block(out, "left" if direction == 0 else "right", orbitals), disc.value
+
     def davidson(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
                  split_tol=1e-5, mlp=None, stream=None, use_graph=False):
         """In-place Davidson on the device vector psi; returns a dict of the result fields.
         ``mlp``: a Mlp network to use as the preconditioner (default: the diagonal one).
         ``use_graph``: run the matvecs through cached hipGraphs (dmrg_hpsi_graph)."""
-        assert psi.numel() == self.n_coeff and psi.is_contiguous()
+        _device_f64(psi, self.device, "psi")
+        assert psi.numel() == self.n_coeff
         o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, mlp, use_graph)
         r = DavResult()
         st = _check(lib.dmrg_davidson(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),

@@ -66,6 +66,45 @@ struct Alpha {
     int family;
 };
 
+// Spin-orbital integrals (reading of Eq. H2q: v_pqrs = (ps|qr)/2).
+struct Integrals {
+    int L;
+    const double* h;
+    const double* eri;
+    double t(int P, int Q) const {
+        if ((P & 1) != (Q & 1)) return 0.0;
+        return h[(P >> 1) * L + (Q >> 1)];
+    }
+    double w(int P, int Q, int R, int S) const {
+        if ((P & 1) != (S & 1) || (Q & 1) != (R & 1)) return 0.0;
+        int p = P >> 1, q = Q >> 1, r = R >> 1, s = S >> 1;
+        return eri[(((int64_t)p * L + s) * L + q) * L + r];
+    }
+};
+
+// Basis of an enlarged block (block + one site), the rows of rho and of the renormalization matrix
+// O of Eq. renorm: sectors q ascending in (n_alpha, n_beta); left side: pairs (a, s) in (a, s) order
+// with q = qn(a) + qn(s), right side: pairs (s, d) in (s, d) order with q = qn(s) + qn(d); each pair
+// contributes the dim states of its block sector consecutively (pairs of empty sectors are left
+// out). groups[i] holds (x, y, first row) with (x, y) = (a, s) or (s, d).
+struct EnlargedLayout {
+    std::vector<std::pair<int, int>> qn;
+    std::vector<int> dim;
+    std::vector<int64_t> off;                                  // n_sec + 1: dense dim x dim blocks
+    std::vector<std::vector<std::array<int, 3>>> groups;
+};
+EnlargedLayout enlarged_layout(const BlockIn& B, bool right);
+
+// Block B (left: orbitals [0, site); right: orbitals (site, L)) grown by orbital `site` and
+// renormalized by O (Eq. renorm_mat): B's operators on the device at data + op_off[op * n_sec + ket
+// sector] (data_len doubles; leading dimension ld_of(columns) when `padded`, else the column count;
+// every access is checked against data_len before launch); O on the host,
+// per sector of enlarged_layout(B, right) a dim x kept row-major matrix, concatenated. Returns a
+// library-owned block (free with dmrg_block_free). Synchronizes `s`.
+dmrg_block* grow_block(const BlockIn& B, bool right, int site, const Integrals& I, const double* data,
+                       int64_t data_len, const std::vector<int64_t>& op_off, bool padded, const std::vector<int>& kept,
+                       const std::vector<double>& O, int device, hipStream_t s);
+
 }  // namespace dmrg
 
 struct dmrg_hop {
@@ -156,4 +195,7 @@ struct dmrg_hop {
     int tune_phases = 1;       // 0: from the operator footprint and kCacheBudget
     double* d_diag = nullptr;
     std::vector<void*> allocations;
+    // pool offset of every stored operator sector block, per side: [op * n_sec + ket sector] or -1
+    // (row-major, leading dimension ld_of(columns)); used to grow and renormalize the blocks
+    std::vector<int64_t> op_pool_off[2];
 };

@@ -158,21 +158,7 @@ BlockIn import_block(const dmrg_block* b, const char* side) {
 
 namespace {
 
-// Spin-orbital integrals (reading of Eq. H2q: v_pqrs = (ps|qr)/2).
-struct Integrals {
-    int L;
-    const double* h;
-    const double* eri;
-    double t(int P, int Q) const {
-        if ((P & 1) != (Q & 1)) return 0.0;
-        return h[(P >> 1) * L + (Q >> 1)];
-    }
-    double w(int P, int Q, int R, int S) const {
-        if ((P & 1) != (S & 1) || (Q & 1) != (R & 1)) return 0.0;
-        int p = P >> 1, q = Q >> 1, r = R >> 1, s = S >> 1;
-        return eri[(((int64_t)p * L + s) * L + q) * L + r];
-    }
-};
+using dmrg::Integrals;
 
 struct Builder {
     dmrg_hop& H;
@@ -211,10 +197,11 @@ struct Builder {
         return id;
     }
     int presum(int s, const std::vector<Term>& terms) {
+        // share mode: a summand whose operator the blocks do not supply (op < 0) belongs to another
+        // device's share and is left out; the combination keeps its supplied summands
         std::vector<Term> nz;
-        for (const Term& t : terms) if (t.c != 0.0) nz.push_back(t);
-        if (nz.empty()) return -2;   // identically zero
-        for (const Term& t : nz) if (t.op < 0) return -2;   // a summand is absent (share mode)
+        for (const Term& t : terms) if (t.c != 0.0 && t.op >= 0) nz.push_back(t);
+        if (nz.empty()) return -2;   // identically zero, or no summand supplied
         if (nz.size() == 1 && nz[0].c == 1.0) return mat(s, {nz[0].op, nz[0].tr});
         MatDef m;
         m.side = s;
@@ -1402,6 +1389,8 @@ void upload(dmrg_hop& H, const dmrg_build_opts* opts) {
                 base_off[sd][k * B.n_sec + si] = reserve(B.dim[so], B.dim[si]);
             }
     }
+    H.op_pool_off[0] = base_off[0];
+    H.op_pool_off[1] = base_off[1];
     // which matrices are used by tasks
     std::vector<char> used(H.mats.size(), 0);
     for (const auto& t : H.tasks) { if (t.lm >= 0) used[t.lm] = 1; if (t.rm >= 0) used[t.rm] = 1; }

@@ -12,30 +12,18 @@
 
 #include "eigen.h"
 #include "hop.h"
+#include "renorm.h"
 
 using dmrg::BlockIn;
 using dmrg::Error;
 using dmrg::kSiteQn;
+using dmrg::RenormItem;
+using dmrg::RenormWork;
+using dmrg::EnlargedLayout;
 
-// ---------------------------------------------------------------- reduced density matrices
-namespace {
-// psi read as the matrix psi_{(l s_l),(s_r r)} (Section 2.1). Left side: enlarged-left sectors
-// q = qn(a) + qn(b), groups (a, b) in (a, b) order with the m_a states of sector a; right side:
-// enlarged-right sectors q = qn(c) + qn(d), groups (c, d) in (c, d) order with the m_d states of
-// sector d. Sectors ascend in (n_alpha, n_beta); groups that no psi block reaches are included (zero
-// rows). groups[i] holds (x, y, first row) with (x, y) = (a, b) or (c, d).
-struct RdmLayout {
-    std::vector<std::pair<int, int>> qn;
-    std::vector<int> dim;
-    std::vector<int64_t> off;                                  // n_sec + 1: dense dim x dim blocks
-    std::vector<std::vector<std::array<int, 3>>> groups;
-};
-
-RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
-    if (H.n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: density matrices are per problem");
+dmrg::EnlargedLayout dmrg::enlarged_layout(const BlockIn& B, bool right) {
     std::map<std::pair<int, int>, std::vector<std::array<int, 3>>> groups;
     std::map<std::pair<int, int>, int> dims;
-    const BlockIn& B = right ? H.right : H.left;
     auto add = [&](int x, int y, int sec, int site) {
         const std::pair<int, int> q{B.qa[sec] + kSiteQn[site][0], B.qb[sec] + kSiteQn[site][1]};
         int& d = dims[q];
@@ -51,7 +39,7 @@ RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
             for (int d = 0; d < B.n_sec; ++d)
                 if (B.dim[d] > 0) add(c, d, d, c);
     }
-    RdmLayout R;
+    EnlargedLayout R;
     R.off.push_back(0);
     for (auto& kv : groups) {
         const int d = dims[kv.first];
@@ -61,6 +49,17 @@ RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
         R.groups.push_back(kv.second);
     }
     return R;
+}
+
+// ---------------------------------------------------------------- reduced density matrices
+namespace {
+// psi read as the matrix psi_{(l s_l),(s_r r)} (Section 2.1): rows are the enlarged left block,
+// columns the enlarged right block, both in the layout of dmrg::enlarged_layout.
+using RdmLayout = dmrg::EnlargedLayout;
+
+RdmLayout rdm_layout(const dmrg_hop& H, bool right) {
+    if (H.n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: density matrices are per problem");
+    return dmrg::enlarged_layout(right ? H.right : H.left, right);
 }
 
 // psi blocks of one group, in the order of the other side's groups: left group (a, b) -> blocks
@@ -303,6 +302,47 @@ extern "C" dmrg_status dmrg_truncate(const double* rho, int32_t n_sec, const int
     }
 }
 
+dmrg::RenormWork dmrg::renorm_work(int32_t n_sec, const int32_t* dims, const int32_t* kept, const int64_t* o_off,
+                                   const double* O, int64_t o_len, int32_t n_blk, const int32_t* sec_out,
+                                   const int32_t* sec_in, const int64_t* a_off, const double* A, int64_t a_len,
+                                   const int64_t* out_off, double* out, int64_t out_len) {
+    RenormWork w;
+    if (n_sec < 0 || n_blk < 0) throw Error(DMRG_ERR_ARG, "n_sec and n_blk must be >= 0");
+    if (n_blk == 0) return w;
+    if (!dims || !kept || !o_off || !O || !sec_out || !sec_in || !a_off || !A || !out_off || !out)
+        throw Error(DMRG_ERR_ARG, "NULL argument");
+    for (int s = 0; s < n_sec; ++s) {
+        if (dims[s] < 0 || kept[s] < 0 || kept[s] > dims[s]) throw Error(DMRG_ERR_ARG, "need 0 <= kept <= dims");
+        if (o_off[s] < 0 || o_off[s] + (int64_t)dims[s] * kept[s] > o_len)
+            throw Error(DMRG_ERR_SHAPE, "renormalization matrix outside O");
+    }
+    for (int b = 0; b < n_blk; ++b) {
+        const int so = sec_out[b], si = sec_in[b];
+        if (so < 0 || so >= n_sec || si < 0 || si >= n_sec) throw Error(DMRG_ERR_ARG, "sector index out of range");
+        const int64_t rows = dims[so], cols = dims[si], ko = kept[so], ki = kept[si];
+        if (a_off[b] < 0 || a_off[b] + rows * cols > a_len) throw Error(DMRG_ERR_SHAPE, "operator block outside A");
+        if (out_off[b] < 0 || out_off[b] + ko * ki > out_len) throw Error(DMRG_ERR_SHAPE, "output block outside out");
+        if (rows * ki >= INT32_MAX || ko * ki >= INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "sector block too large");
+        if (ko == 0 || ki == 0) continue;                  // nothing kept on one side: empty block
+        RenormItem it{};
+        it.a_off = a_off[b];
+        it.t_off = w.t_len;
+        it.out_off = out_off[b];
+        it.oo_off = o_off[so];
+        it.oi_off = o_off[si];
+        it.rows = (int32_t)rows;
+        it.cols = (int32_t)cols;
+        it.k_out = (int32_t)ko;
+        it.k_in = (int32_t)ki;
+        w.items.push_back(it);
+        w.t_len += rows * ki;
+        w.max_t = std::max(w.max_t, rows * ki);
+        w.max_out = std::max(w.max_out, ko * ki);
+    }
+    if (w.items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many blocks");
+    return w;
+}
+
 extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t* dims, const int32_t* kept,
                                                const int64_t* o_off, const double* O, int64_t o_len, int32_t n_blk,
                                                const int32_t* sec_out, const int32_t* sec_in, const int64_t* a_off,
@@ -310,51 +350,19 @@ extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, co
                                                int64_t out_len, void* stream) {
     dmrg::clear_error();
     try {
-        if (n_sec < 0 || n_blk < 0) throw Error(DMRG_ERR_ARG, "n_sec and n_blk must be >= 0");
-        if (n_blk == 0) return DMRG_OK;
-        if (!dims || !kept || !o_off || !O || !sec_out || !sec_in || !a_off || !A || !out_off || !out)
-            throw Error(DMRG_ERR_ARG, "NULL argument");
-        for (int s = 0; s < n_sec; ++s) {
-            if (dims[s] < 0 || kept[s] < 0 || kept[s] > dims[s]) throw Error(DMRG_ERR_ARG, "need 0 <= kept <= dims");
-            if (o_off[s] < 0 || o_off[s] + (int64_t)dims[s] * kept[s] > o_len)
-                throw Error(DMRG_ERR_SHAPE, "renormalization matrix outside O");
-        }
-        std::vector<dmrg::RenormItem> items;
-        int64_t t_len = 0, max_t = 0, max_out = 0;
-        for (int b = 0; b < n_blk; ++b) {
-            const int so = sec_out[b], si = sec_in[b];
-            if (so < 0 || so >= n_sec || si < 0 || si >= n_sec) throw Error(DMRG_ERR_ARG, "sector index out of range");
-            const int64_t rows = dims[so], cols = dims[si], ko = kept[so], ki = kept[si];
-            if (a_off[b] < 0 || a_off[b] + rows * cols > a_len) throw Error(DMRG_ERR_SHAPE, "operator block outside A");
-            if (out_off[b] < 0 || out_off[b] + ko * ki > out_len) throw Error(DMRG_ERR_SHAPE, "output block outside out");
-            if (rows * ki >= INT32_MAX || ko * ki >= INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "sector block too large");
-            if (ko == 0 || ki == 0) continue;                  // nothing kept on one side: empty block
-            dmrg::RenormItem it{};
-            it.a_off = a_off[b];
-            it.t_off = t_len;
-            it.out_off = out_off[b];
-            it.oo_off = o_off[so];
-            it.oi_off = o_off[si];
-            it.rows = (int32_t)rows;
-            it.cols = (int32_t)cols;
-            it.k_out = (int32_t)ko;
-            it.k_in = (int32_t)ki;
-            items.push_back(it);
-            t_len += rows * ki;
-            max_t = std::max(max_t, rows * ki);
-            max_out = std::max(max_out, ko * ki);
-        }
+        const dmrg::RenormWork wk = dmrg::renorm_work(n_sec, dims, kept, o_off, O, o_len, n_blk, sec_out, sec_in,
+                                                      a_off, A, a_len, out_off, out, out_len);
+        const auto& items = wk.items;
         if (items.empty()) return DMRG_OK;
-        if (items.size() > (size_t)INT32_MAX) throw Error(DMRG_ERR_UNSUPPORTED, "too many blocks");
         HIPCHK(hipSetDevice(device));
         hipStream_t s = (hipStream_t)stream;
         void *d_items = nullptr, *d_t = nullptr;
         try {
             HIPCHK(hipMalloc(&d_items, items.size() * sizeof(dmrg::RenormItem)));
-            HIPCHK(hipMalloc(&d_t, (size_t)std::max<int64_t>(1, t_len) * sizeof(double)));
+            HIPCHK(hipMalloc(&d_t, (size_t)std::max<int64_t>(1, wk.t_len) * sizeof(double)));
             HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(dmrg::RenormItem), hipMemcpyHostToDevice, s));
-            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), max_t,
-                                            max_out, A, O, static_cast<double*>(d_t), out, s));
+            HIPCHK(dmrg::launch_renormalize(static_cast<const dmrg::RenormItem*>(d_items), (int)items.size(), wk.max_t,
+                                            wk.max_out, A, O, static_cast<double*>(d_t), out, s));
             HIPCHK(hipStreamSynchronize(s));   // the work list and T end here
         } catch (...) {
             (void)hipStreamSynchronize(s);
@@ -373,3 +381,166 @@ extern "C" dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, co
     }
 }
 
+
+// ---------------------------------------------------------------- growth and renormalization
+namespace {
+
+void check_side(int32_t side) {
+    if (side != 0 && side != 1) throw Error(DMRG_ERR_ARG, "side must be 0 (left block) or 1 (right block)");
+}
+
+}  // namespace
+
+extern "C" dmrg_status dmrg_block_grow_layout(const dmrg_block* block, int32_t side, int32_t* n_sec, int32_t* qn,
+                                              int32_t* dims) {
+    dmrg::clear_error();
+    try {
+        if (!n_sec) throw Error(DMRG_ERR_ARG, "NULL argument");
+        check_side(side);
+        const BlockIn B = dmrg::import_block(block, side == 0 ? "left" : "right");
+        const EnlargedLayout E = dmrg::enlarged_layout(B, side == 1);
+        *n_sec = (int32_t)E.dim.size();
+        for (size_t i = 0; i < E.dim.size(); ++i) {
+            if (qn) { qn[2 * i] = E.qn[i].first; qn[2 * i + 1] = E.qn[i].second; }
+            if (dims) dims[i] = E.dim[i];
+        }
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return dmrg::record_error(e);
+    } catch (const std::bad_alloc&) {
+        dmrg::last_error() = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
+extern "C" dmrg_status dmrg_block_grow(const dmrg_problem* p, const dmrg_block* block, int32_t side,
+                                       const int32_t* kept, const double* O, const dmrg_build_opts* opts,
+                                       dmrg_block** out) {
+    dmrg::clear_error();
+    if (!out) { dmrg::last_error() = "out is NULL"; return DMRG_ERR_ARG; }
+    *out = nullptr;
+    try {
+        if (!p || !p->h || !p->eri) throw Error(DMRG_ERR_ARG, "problem or its integrals are NULL");
+        if (p->n_orb < 2 || p->site < 0 || p->site > p->n_orb - 2)
+            throw Error(DMRG_ERR_ARG, "need n_orb >= 2 and 0 <= site <= n_orb - 2");
+        check_side(side);
+        if ((kept == nullptr) != (O == nullptr)) throw Error(DMRG_ERR_ARG, "kept and O must both be given or both NULL");
+        const int dev = opts ? opts->device : 0;
+        if (dev < 0) throw Error(DMRG_ERR_UNSUPPORTED, "block growth runs on a device");
+        hipStream_t s = (hipStream_t)(opts ? opts->stream : nullptr);
+        const int64_t L = p->n_orb;
+        std::vector<double> h(p->h, p->h + L * L), eri(p->eri, p->eri + L * L * L * L);
+        for (double v : h) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite one-electron integral");
+        for (double v : eri) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite two-electron integral");
+        const BlockIn B = dmrg::import_block(block, side == 0 ? "left" : "right");
+        const EnlargedLayout E = dmrg::enlarged_layout(B, side == 1);
+        std::vector<int> k(E.dim.size());
+        std::vector<double> Ov;
+        if (kept) {
+            int64_t len = 0;
+            for (size_t q = 0; q < E.dim.size(); ++q) {
+                k[q] = kept[q];
+                if (k[q] < 0 || k[q] > E.dim[q]) throw Error(DMRG_ERR_ARG, "need 0 <= kept <= enlarged sector dimension");
+                len += (int64_t)E.dim[q] * k[q];
+            }
+            Ov.assign(O, O + len);
+            for (double v : Ov) if (!std::isfinite(v)) throw Error(DMRG_ERR_NAN, "non-finite renormalization matrix");
+        } else {
+            for (size_t q = 0; q < E.dim.size(); ++q) {        // keep everything: O = identity
+                k[q] = E.dim[q];
+                const size_t o = Ov.size();
+                Ov.resize(o + (size_t)E.dim[q] * E.dim[q], 0.0);
+                for (int i = 0; i < E.dim[q]; ++i) Ov[o + (size_t)i * E.dim[q] + i] = 1.0;
+            }
+        }
+        HIPCHK(hipSetDevice(dev));
+        // the block's data as given (compact sector blocks at the caller's offsets)
+        std::vector<int64_t> off((size_t)B.ops.size() * B.n_sec, -1);
+        for (size_t o = 0; o < B.ops.size(); ++o)
+            for (int si = 0; si < B.n_sec; ++si) off[o * B.n_sec + si] = B.ops[o].off_of_in[si];
+        void* d_data = nullptr;
+        if (hipMalloc(&d_data, (size_t)std::max<int64_t>(1, B.n_data) * sizeof(double)) != hipSuccess)
+            throw Error(DMRG_ERR_NOMEM, "device allocation failed (block data)");
+        try {
+            if (B.n_data > 0)
+                HIPCHK(hipMemcpyAsync(d_data, B.data, (size_t)B.n_data * sizeof(double), hipMemcpyHostToDevice, s));
+            dmrg::Integrals I{(int)L, h.data(), eri.data()};
+            const int site = side == 0 ? p->site : p->site + 1;
+            *out = dmrg::grow_block(B, side == 1, site, I, static_cast<const double*>(d_data), B.n_data, off, false, k, Ov,
+                                    dev, s);
+        } catch (...) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(d_data);
+            throw;
+        }
+        (void)hipFree(d_data);
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return dmrg::record_error(e);
+    } catch (const std::bad_alloc&) {
+        dmrg::last_error() = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}
+
+extern "C" dmrg_status dmrg_renormalize(dmrg_hop* H, const double* psi, int32_t dir, int32_t m_max, dmrg_block** out,
+                                        double* discarded, void* stream) {
+    dmrg::clear_error();
+    if (!out) { dmrg::last_error() = "out is NULL"; return DMRG_ERR_ARG; }
+    *out = nullptr;
+    try {
+        if (!H || !psi) throw Error(DMRG_ERR_ARG, "NULL argument");
+        check_side(dir);
+        if (m_max < 1) throw Error(DMRG_ERR_ARG, "m_max must be >= 1");
+        if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
+        if (H->n_parts != 1) throw Error(DMRG_ERR_UNSUPPORTED, "merged handle: renormalization is per problem");
+        const bool right = dir == 1;
+        const RdmLayout R = rdm_layout(*H, right);
+        hipStream_t s = (hipStream_t)stream;
+        HIPCHK(hipSetDevice(H->device));
+        // 1. rho of the enlarged block (device), then the M-state cut (host)
+        std::vector<double> rho((size_t)R.off.back());
+        {
+            void* d_rho = nullptr;
+            if (hipMalloc(&d_rho, std::max<size_t>(1, rho.size()) * sizeof(double)) != hipSuccess)
+                throw Error(DMRG_ERR_NOMEM, "device allocation failed (density matrix)");
+            dmrg_status st = rdm_entry(H, right, psi, static_cast<double*>(d_rho), R.off.back(), stream);
+            if (st == DMRG_OK && !rho.empty() &&
+                hipMemcpy(rho.data(), d_rho, rho.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+                st = dmrg::record_error(Error(DMRG_ERR_DEVICE, "density matrix copy failed"));
+            (void)hipFree(d_rho);
+            if (st != DMRG_OK) return st;
+        }
+        const int nq = (int)R.dim.size();
+        std::vector<int32_t> dims(R.dim.begin(), R.dim.end()), kept(nq);
+        std::vector<double> evals;
+        for (int d : R.dim) evals.resize(evals.size() + d);
+        std::vector<double> vecs(rho.size());
+        double disc = 0.0;
+        dmrg_status st = dmrg_truncate(rho.data(), nq, dims.data(), R.off.data(), m_max, kept.data(), evals.data(),
+                                       vecs.data(), &disc);
+        if (st != DMRG_OK) return st;
+        // 2. O: the kept leading columns of each sector's eigenvectors, packed dims x kept
+        std::vector<int> k(kept.begin(), kept.end());
+        std::vector<double> Ov;
+        for (int q = 0; q < nq; ++q) {
+            const int d = R.dim[q];
+            for (int r = 0; r < d; ++r)
+                for (int c = 0; c < kept[q]; ++c) Ov.push_back(vecs[(size_t)R.off[q] + (size_t)r * d + c]);
+        }
+        // 3. the grown block's operators from the handle's device copy of the old block, Eq. renorm_mat
+        const BlockIn& B = right ? H->right : H->left;
+        dmrg::Integrals I{H->L, H->h.data(), H->eri.data()};
+        const int site = right ? H->site + 1 : H->site;
+        if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
+        *out = dmrg::grow_block(B, right, site, I, H->d_pool, H->pool_size, H->op_pool_off[right ? 1 : 0], true, k, Ov,
+                                H->device, s);
+        if (discarded) *discarded = disc;
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return dmrg::record_error(e);
+    } catch (const std::bad_alloc&) {
+        dmrg::last_error() = "host allocation failed";
+        return DMRG_ERR_NOMEM;
+    }
+}

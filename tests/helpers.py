@@ -33,3 +33,22 @@ def synth(L, M, sigma, seed, n_alpha=None, n_beta=None):
 
 def rel_err(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# Error model of the split-BF16 H.psi. Each operand x is held as x_hi + x_lo with 8 significant bits
+# each (round to nearest), so x - x_hi - x_lo is at most 2^-17 |x|, and a product a.b is formed as
+# a_hi b_hi + a_hi b_lo + a_lo b_hi: off by at most about (2 * 2^-17 + 2^-18) |a| |b|. A task chains
+# two such GEMMs (the intermediate is split again) and partial sums run in FP32 (2^-24 per add), so
+# every output element satisfies |y - y_ref| <= ~2^-15 * sum over its summands of |f| |A| |X| |B|^T
+# (the oracle's ``magnitude``). The bar is 2^-12 of that sum: an 8x margin over the model, while a
+# dropped task or a wrong row changes its elements by a whole summand (~1/#summands of the sum).
+SPLIT_BOUND = 2.0 ** -12
+
+
+def assert_split_bound(y, ref, mag, what=""):
+    """Every element of the split result within SPLIT_BOUND * magnitude of the oracle's value."""
+    ratio = np.abs(y - ref) / np.maximum(mag, 1e-300)
+    worst = float(ratio.max(initial=0.0))
+    print(f"[split bound] {what}: max |y - ref| / magnitude = {worst:.2e} (bar {SPLIT_BOUND:.2e})", flush=True)
+    assert worst <= SPLIT_BOUND, (what, worst)
+    return worst

@@ -2,16 +2,18 @@
 
 With every operator supplied, share mode builds the same combinations as the default mode, so
 H.psi must be identical bit for bit. With a subset of operators (the block Hamiltonians and some
-B/Q, A/P pairs) H.psi is the sum over the combinations that remain: it must still be symmetric
-(<x|Hy> = <Hx|y>, FP64, relative 1e-12) since the share keeps each combination together with its
-Hermitian partner, split and FP64 must agree to the split bound, and results must be deterministic.
+B/Q, A/P pairs) H.psi is the sum of the Hamiltonian terms whose block operators are supplied: it
+equals the oracle's share (FP64 within 1e-12 of max|y|, split within its error bound), is symmetric
+(<x|Hy> = <Hx|y>, FP64, relative 1e-12) since the share keeps each term together with its Hermitian
+partner, and is deterministic.
 """
 import numpy as np
 import pytest
 
 from dmrg_inputs import random_integrals, random_vector
 from dmrg_inputs.synthetic import share_ops, synthetic_block
-from helpers import rel_err, synth
+from helpers import assert_split_bound, rel_err, synth
+from oracle.hpsi import OracleHop
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -50,17 +52,20 @@ def share_hop():
     left = synthetic_block("left", L, na, nb, site, M, sigma, seed + 1000, ops=share_ops("left", L, site, 12))
     right = synthetic_block("right", L, na, nb, site, M, sigma, seed + 2000, ops=share_ops("right", L, site, 12))
     print(f"[share] L={L} M={M}: max sector {int(left.dim.max())}", flush=True)
-    return Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, share=True)
+    return (Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, share=True),
+            OracleHop(h, eri, left, right, na, nb, site, share=True))
 
 
 def test_share_subset_symmetric_and_split(share_hop):
-    hop = share_hop
-    # H_L, H_R and the two-site term (site operators only); B_XY Q_XY over ordered pairs (12 stored
-    # pairs, one diagonal: 2 * 12 - 1); A_PQ P_PQ and their adjoints (2 * 12); every other family
-    # needs an operator outside the share
-    assert hop.stats()["n_alpha"] == 3 + (2 * 12 - 1) + 2 * 12
+    hop, oh = share_hop
     x, z = random_vector(hop.n_coeff, 1), random_vector(hop.n_coeff, 2)
     hx, hz = _run(hop, x, PREC_FP64), _run(hop, z, PREC_FP64)
     assert abs(x @ hz - hx @ z) <= 1e-12 * np.linalg.norm(hx) * np.linalg.norm(z)
-    assert rel_err(_run(hop, x, PREC_SPLIT2), hx) < 5e-4
+    ysp = _run(hop, x, PREC_SPLIT2)
     assert np.array_equal(_run(hop, x, PREC_FP64), hx)
+    # the oracle's share (the same Hamiltonian terms, from its own term-by-term expansion)
+    ref = oh.apply(x)
+    err = rel_err(hx, ref)
+    print(f"[share] L=16 M=300 subset: {hop.stats()['n_alpha']} combinations, fp64 {err:.2e}", flush=True)
+    assert err < 1e-12
+    assert_split_bound(ysp, ref, oh.magnitude(x), "share")

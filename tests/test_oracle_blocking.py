@@ -171,3 +171,60 @@ def test_renormalization_step_carries_the_state(step, M):
     if M == 64:
         assert abs(disc) < 1e-12
         assert np.abs(nxt.apply(y) - step["e_fci"] * y).max() < 1e-9
+
+
+# ---------------------------------------------------------------- growth by the Fock-space route
+@pytest.mark.parametrize("trunc", [None, 5])
+def test_fock_route_growth_equals_stored_operator_route(step, trunc):
+    """Two derivations of the grown, renormalized left block agree: GrownLeft (from the block's stored
+    operators and the site matrices) and grown_block (exact operators of the grown orbital set in its
+    own Fock space, projected); on the exact block and on a randomly truncated one."""
+    from oracle.blocking import grown_block
+    from oracle.fock import random_bases, truncate
+    left = step["left"] if trunc is None else truncate(step["left"], random_bases(step["left"], trunc, 9))
+    _, edims = renorm.enlarged_left_basis(left)
+    rng = np.random.default_rng(2)
+    O = {q: np.linalg.qr(rng.normal(size=(d, d)))[0][:, :max(1, (2 * d) // 3)] for q, d in edims.items()}
+    a = GrownLeft(left, step["t"], step["w"], step["s1"]).renormalized_block(O)
+    b = grown_block("left", left, step["s1"], O, step["t"], step["w"])
+    assert a.qn.tolist() == b.qn.tolist() and a.dim.tolist() == b.dim.tolist()
+    n = 0
+    for op in a.ops:
+        ob = b.get(op.kind, op.i0, op.i1)
+        assert np.abs(_dense(a, op) - _dense(b, ob)).max() < 1e-13, op.key
+        n += 1
+    assert n > 50
+
+
+@pytest.fixture(scope="module")
+def back_step(step):
+    """The backward direction at the same bond: rho^R of the FCI ground state, and the right block
+    grown by the right site s2 = 3 into orbitals 3 .. 5 (the right block of the bond (1, 2))."""
+    rho = renorm.rdm_right(step["P"], step["na"], step["nb"])
+    left_prev = exact_block(list(range(step["s1"] - 1)), "left", step["t"], step["w"],
+                            [P for P in range(12) if P // 2 >= step["s1"] - 1])
+    return dict(rho=rho, left_prev=left_prev)
+
+
+def _prev_bond_energy(step, back, M):
+    from oracle.blocking import grown_block
+    O, kept, disc = renorm.select(back["rho"], M)
+    grown = grown_block("right", step["right"], step["s1"] + 1, O, step["t"], step["w"])
+    prv = OracleHop(step["h"], step["eri"], back["left_prev"], grown, step["na"], step["nb"], step["s1"] - 1)
+    Hm = prv.apply(np.eye(prv.layout.size))
+    assert np.abs(Hm - Hm.T).max() < 1e-11
+    return float(np.linalg.eigvalsh(Hm)[0]), disc
+
+
+def test_backward_step_full_M_keeps_the_fci_energy(step, back_step):
+    n = sum(r.shape[0] for r in back_step["rho"].values())
+    e, disc = _prev_bond_energy(step, back_step, n)
+    assert abs(disc) < 1e-12
+    assert abs(e - step["e_fci"]) < 1e-10
+
+
+def test_backward_step_truncated_is_variational_and_monotone(step, back_step):
+    es = [_prev_bond_energy(step, back_step, M)[0] for M in (4, 8, 16, 32)]
+    assert all(e >= step["e_fci"] - 1e-10 for e in es)
+    assert all(es[i + 1] <= es[i] + 1e-10 for i in range(len(es) - 1))
+    assert es[0] > step["e_fci"] + 1e-6
