@@ -238,6 +238,21 @@ dmrg_status dmrg_renormalize_blocks(int32_t device, int32_t n_sec, const int32_t
                                     const double* A, int64_t a_len, const int64_t* out_off, double* out,
                                     int64_t out_len, void* stream);
 
+/* dmrg_renormalize_blocks for callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid hipMalloc): same arguments, checks, kernels and
+ * results (bit for bit), but the work list and the intermediate T = A O_in live in a fixed device
+ * array of 64 MiB per GPU inside the library (held until the process ends) instead of fresh
+ * allocations; the call allocates nothing. Limit: 256-byte-rounded work list (40 B per block that
+ * keeps states on both sides) + 8 B x sum over those blocks of rows(sec_out) x kept(sec_in) must fit
+ * in 64 MiB, else DMRG_ERR_NOMEM (nothing is launched). Every call on one GPU shares that GPU's
+ * array: calls that overlap in time on the same GPU (other host threads or streams) race and must
+ * be serialized by the caller. Synchronizes `stream` before returning. */
+dmrg_status dmrg_renormalize_blocks_noalloc(int32_t device, int32_t n_sec, const int32_t* dims, const int32_t* kept,
+                                            const int64_t* o_off, const double* O, int64_t o_len, int32_t n_blk,
+                                            const int32_t* sec_out, const int32_t* sec_in, const int64_t* a_off,
+                                            const double* A, int64_t a_len, const int64_t* out_off, double* out,
+                                            int64_t out_len, void* stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Growth and renormalization of a block (Section 2.1: the operators of the enlarged block, its
  * truncation by the M eigenvectors of rho with the largest eigenvalues, Eq. renorm, Eq. renorm_mat;

@@ -106,6 +106,8 @@ lib.dmrg_renormalize_blocks.argtypes = [C.c_int32, C.c_int32, i32p, i32p, i64p, 
                                         i32p, i32p, i64p, C.c_void_p, C.c_int64, i64p, C.c_void_p, C.c_int64,
                                         C.c_void_p]
 lib.dmrg_renormalize_blocks.restype = C.c_int32
+lib.dmrg_renormalize_blocks_noalloc.argtypes = lib.dmrg_renormalize_blocks.argtypes
+lib.dmrg_renormalize_blocks_noalloc.restype = C.c_int32
 lib.dmrg_block_grow_layout.argtypes = [C.POINTER(BlockDesc), C.c_int32, i32p, i32p, i32p]
 lib.dmrg_block_grow_layout.restype = C.c_int32
 lib.dmrg_block_grow.argtypes = [C.POINTER(Problem), C.POINTER(BlockDesc), C.c_int32, i32p, f64p, C.POINTER(BuildOpts),
@@ -213,20 +215,23 @@ def _device_f64(t, device, what):
         raise ValueError(f"{what} must be contiguous")
 
 
-def renormalize_blocks(dims, kept, o_off, O, sec_out, sec_in, a_off, A, out_off, out, device=0, stream=None):
-    """dmrg_renormalize_blocks: index arrays on the host (numpy), O, A, out device tensors (float64)."""
+def renormalize_blocks(dims, kept, o_off, O, sec_out, sec_in, a_off, A, out_off, out, device=0, stream=None,
+                       noalloc=False):
+    """dmrg_renormalize_blocks (or, with noalloc, dmrg_renormalize_blocks_noalloc): index arrays on the
+    host (numpy), O, A, out device tensors (float64)."""
     dims, kept = np.ascontiguousarray(dims, dtype=np.int32), np.ascontiguousarray(kept, dtype=np.int32)
     o_off = np.ascontiguousarray(o_off, dtype=np.int64)
     sec_out, sec_in = np.ascontiguousarray(sec_out, dtype=np.int32), np.ascontiguousarray(sec_in, dtype=np.int32)
     a_off, out_off = np.ascontiguousarray(a_off, dtype=np.int64), np.ascontiguousarray(out_off, dtype=np.int64)
     for t, what in ((O, "O"), (A, "A"), (out, "out")):
         _device_f64(t, device, what)
-    _check(lib.dmrg_renormalize_blocks(int(device), int(dims.size), _ptr(dims, C.c_int32), _ptr(kept, C.c_int32),
-                                       _ptr(o_off, C.c_int64), C.c_void_p(O.data_ptr()), int(O.numel()),
-                                       int(sec_out.size), _ptr(sec_out, C.c_int32), _ptr(sec_in, C.c_int32),
-                                       _ptr(a_off, C.c_int64), C.c_void_p(A.data_ptr()), int(A.numel()),
-                                       _ptr(out_off, C.c_int64), C.c_void_p(out.data_ptr()), int(out.numel()),
-                                       _stream_ptr(stream)))
+    fn = lib.dmrg_renormalize_blocks_noalloc if noalloc else lib.dmrg_renormalize_blocks
+    _check(fn(int(device), int(dims.size), _ptr(dims, C.c_int32), _ptr(kept, C.c_int32),
+              _ptr(o_off, C.c_int64), C.c_void_p(O.data_ptr()), int(O.numel()),
+              int(sec_out.size), _ptr(sec_out, C.c_int32), _ptr(sec_in, C.c_int32),
+              _ptr(a_off, C.c_int64), C.c_void_p(A.data_ptr()), int(A.numel()),
+              _ptr(out_off, C.c_int64), C.c_void_p(out.data_ptr()), int(out.numel()),
+              _stream_ptr(stream)))
 
 
 _KIND_NAME = {v: k for k, v in _KIND.items()}

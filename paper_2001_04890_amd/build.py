@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "mlp.hip", "host.cpp", "mlp_host.cpp",
-           "renorm_host.cpp", "davidson.cpp", "eigen.cpp", "grow.hip", "grow.cpp",
+           "renorm_host.cpp", "davidson.cpp", "eigen.cpp", "noalloc.cpp", "grow.hip", "grow.cpp",
            "sweep.cpp"]
 
 

@@ -342,12 +342,20 @@ def test_renormalize_blocks_checks_arguments_before_any_device_work():
     dims, kept, o_off = [3, 4], [2, 4], [0, 6]
     ok = dict(dims=dims, kept=kept, o_off=o_off, O=Fake(22), sec_out=[0, 1], sec_in=[1, 0], a_off=[0, 12],
               A=Fake(24), out_off=[0, 8], out=Fake(16))
-    for change, status in (({"sec_out": [0, 2]}, -1), ({"kept": [4, 4]}, -1), ({"A": Fake(23)}, -2),
-                           ({"out": Fake(15)}, -2), ({"O": Fake(21)}, -2), ({"a_off": [-1, 12]}, -2)):
-        with pytest.raises(DmrgError) as e:
-            lib_mod.renormalize_blocks(**{**ok, **change})
-        assert e.value.status == status, change
-    lib_mod.renormalize_blocks(**{**ok, "sec_out": [], "sec_in": [], "a_off": [], "out_off": []})   # no blocks: no-op
+    for noalloc in (False, True):      # the allocation-free variant checks the same way
+        for change, status in (({"sec_out": [0, 2]}, -1), ({"kept": [4, 4]}, -1), ({"A": Fake(23)}, -2),
+                               ({"out": Fake(15)}, -2), ({"O": Fake(21)}, -2), ({"a_off": [-1, 12]}, -2)):
+            with pytest.raises(DmrgError) as e:
+                lib_mod.renormalize_blocks(**{**ok, **change}, noalloc=noalloc)
+            assert e.value.status == status, change
+        lib_mod.renormalize_blocks(**{**ok, "sec_out": [], "sec_in": [], "a_off": [], "out_off": []},
+                                   noalloc=noalloc)   # no blocks: no-op
+    # a request beyond the fixed 64 MiB scratch is refused before any device work
+    big = dict(dims=[3000], kept=[3000], o_off=[0], O=Fake(9_000_000), sec_out=[0], sec_in=[0], a_off=[0],
+               A=Fake(9_000_000), out_off=[0], out=Fake(9_000_000))
+    with pytest.raises(DmrgError) as e:
+        lib_mod.renormalize_blocks(**big, noalloc=True)
+    assert e.value.status == -3 and "scratch" in str(e.value)
 
 
 def test_header_is_plain_c():
