@@ -27,9 +27,9 @@ PEAK = {"fp64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                        # GB/s
 # HBM traffic of one FP64 H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the launches of one call, scaled by the factors of
-# a 1 GiB device copy in the same runs (profiles/hpsi_fp64_L24_M1024_kernel_trace.md); None until
-# measured for the current kernels.
-FP64_TRAFFIC_L24_M1024 = None
+# a 1 GiB device copy in the same runs (profiles/hpsi_fp64_L24_M1024_kernel_trace.md). Valid for that
+# workload and these kernels only.
+FP64_TRAFFIC_L24_M1024 = {"fetch_bytes": 48094.9 * 2**20, "write_bytes": 417.1 * 2**20}
 # HBM traffic of one split H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the k_pack_xt / k_zero_lds / k_hpsi_lds /
 # k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
@@ -475,6 +475,22 @@ def bench_renorm(args):
     ms_ren = wall(lambda: dm.renormalize_blocks(dims, kept, o_off[:-1], O, sec, sec, off[:-1], A, out_off[:-1], out,
                                                 stream=stream), reps)
     log(f"[bench] renorm: O^T A O {ms_ren:.3f} ms")
+    # the whole chained step (dmrg_renormalize): rho, the cut, every grown-block operator (both sides)
+    steps = {}
+    for name, direction in (("grow_left", 0), ("grow_right", 1)):
+        ts = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            hop.renormalize(xd, direction, M, stream=stream, keep=False)      # the C-ABI call alone
+            ts.append((time.perf_counter() - t) * 1e3)
+        blk, dw = hop.renormalize(xd, direction, M, stream=stream)
+        n_el = int(sum(m.size for op in blk.ops for m in op.blocks.values()))
+        steps[name] = {"ms": round(min(ts), 1), "operators": len(blk.ops), "stored_elements": n_el,
+                       "kept": int(blk.dim.sum()), "sectors": int(blk.n_sec), "discarded": dw}
+        log(f"[bench] renorm: dmrg_renormalize {name}: {min(ts):.1f} ms, {len(blk.ops)} operators, "
+            f"{n_el} elements")
+        del blk
     line = {"metric": "renormalization steps (rho^L, M-state cut, O^T A O), ms per call", "unit": "ms",
             "higher_is_better": False, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
             "config": {"workload": f"renormalization at the two-site bond, L={L} N={na + nb} ({na},{nb}) M={M}, "
@@ -484,7 +500,8 @@ def bench_renorm(args):
             "rho_left": {"ms": round(ms_rho, 4), "flops": fl_rho, "tflops": round(fl_rho / ms_rho / 1e9, 4)},
             "cut_host": {"ms": round(ms_cut, 2), "discarded": disc},
             "renorm_mat": {"ms": round(ms_ren, 4), "flops": fl_ren, "tflops": round(fl_ren / ms_ren / 1e9, 4),
-                           "blocks": int(len(dims))}}
+                           "blocks": int(len(dims))},
+            "renormalize_step": steps}
     print(json.dumps(line), flush=True)
 
 

@@ -478,15 +478,19 @@ class Hop:
         """rho^R = psi^T psi per sector (dmrg_rdm_right) into the device buffer rho."""
         self._rdm(lib.dmrg_rdm_right, psi, rho, stream)
 
-    def renormalize(self, psi, direction, m_max, stream=None):
+    def renormalize(self, psi, direction, m_max, stream=None, keep=True):
         """dmrg_renormalize: rho from psi, the m_max-state cut and the grown block's renormalized
-        operators. direction 0 grows the left block, 1 the right block. Returns (Block, discarded)."""
+        operators. direction 0 grows the left block, 1 the right block. Returns (Block, discarded);
+        keep=False releases the library's block right away and returns (None, discarded)."""
         _device_f64(psi, self.device, "psi")
         assert psi.numel() == self.n_coeff
         out = C.POINTER(BlockDesc)()
         disc = C.c_double()
         _check(lib.dmrg_renormalize(self._h, C.c_void_p(psi.data_ptr()), int(direction), int(m_max), C.byref(out),
                                     C.byref(disc), _stream_ptr(stream)))
+        if not keep:
+            lib.dmrg_block_free(out)
+            return None, disc.value
         orbitals = range(0, self.site + 1) if direction == 0 else range(self.site + 1, self.L)
         return _take_block(out, "left" if direction == 0 else "right", orbitals), disc.value
 

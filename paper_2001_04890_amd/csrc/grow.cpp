@@ -24,6 +24,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -382,6 +384,46 @@ struct DevFree {
     }
 };
 
+// Device -> host copy through two pinned 32 MB staging buffers: the DMA of chunk k + 1 overlaps the
+// host copy of chunk k (a pageable destination would be copied at a fraction of the link speed).
+void download(double* dst, const double* src, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    constexpr int64_t kChunk = (int64_t)4 << 20;        // doubles
+    const int64_t cs = std::min(n, kChunk);
+    double* stage[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    auto release = [&]() {
+        for (int b = 0; b < 2; ++b) {
+            if (stage[b]) (void)hipHostFree(stage[b]);
+            if (ev[b]) (void)hipEventDestroy(ev[b]);
+        }
+    };
+    try {
+        for (int b = 0; b < 2; ++b) {
+            HIPCHK(hipHostMalloc((void**)&stage[b], (size_t)cs * sizeof(double), hipHostMallocDefault));
+            HIPCHK(hipEventCreateWithFlags(&ev[b], hipEventDisableTiming));
+        }
+        const int64_t nch = (n + cs - 1) / cs;
+        auto issue = [&](int64_t c) {
+            const int64_t o = c * cs, len = std::min(cs, n - o);
+            HIPCHK(hipMemcpyAsync(stage[c & 1], src + o, (size_t)len * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipEventRecord(ev[c & 1], s));
+        };
+        issue(0);
+        for (int64_t c = 0; c < nch; ++c) {
+            if (c + 1 < nch) issue(c + 1);
+            HIPCHK(hipEventSynchronize(ev[c & 1]));
+            const int64_t o = c * cs, len = std::min(cs, n - o);
+            std::memcpy(dst + o, stage[c & 1], (size_t)len * sizeof(double));
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        release();
+        throw;
+    }
+    release();
+}
+
 template <class T>
 T* upload(DevFree& mem, const std::vector<T>& v, hipStream_t s) {
     T* d = mem.alloc<T>(v.size());
@@ -638,7 +680,23 @@ dmrg_block* grow_block(const BlockIn& B, bool right, int site, const Integrals& 
     }
     for (int32_t k : t_items)
         if (k < 0 || k >= (int32_t)items.size() || items[k].z_off < 0) throw Error(DMRG_ERR_SHAPE, "internal: pass-1 list");
-    // device work
+    // device work (DMRG_GROW_TRACE=1: synchronize after each phase and print its wall time)
+    const char* gt = std::getenv("DMRG_GROW_TRACE");
+    const bool trace = gt && gt[0] == '1';
+    double tp = now_seconds();
+    auto phase = [&](const char* what) {
+        if (!trace) return;
+        HIPCHK(hipStreamSynchronize(s));
+        const double t = now_seconds();
+        std::fprintf(stderr, "[dmrg grow] %-34s %9.3f ms\n", what, (t - tp) * 1e3);
+        tp = t;
+    };
+    if (trace)
+        std::fprintf(stderr, "[dmrg grow] %zu operators, %zu pre-sum blocks (%lld elements, %zu terms), %zu items "
+                     "(%zu with T, %lld T elements), %zu output blocks (%lld elements)\n", gen.defs.size(),
+                     pblocks.size(), (long long)zlen, pterms.size(), items.size(), t_items.size(), (long long)t_len,
+                     outs.size(), (long long)out_len);
+    phase("host term list and work lists");
     HIPCHK(hipSetDevice(device));
     {
         DevFree mem;
@@ -652,13 +710,15 @@ dmrg_block* grow_block(const BlockIn& B, bool right, int site, const Integrals& 
         const int32_t* d_ti = upload(mem, t_items, s);
         const GrowOut* d_outs = upload(mem, outs, s);
         try {
+            phase("uploads");
             HIPCHK(launch_grow_presum(d_pb, (int)pblocks.size(), zmax, d_pt, data, d_z, s));
+            phase("pre-sums");
             HIPCHK(launch_grow_renorm(d_items, d_ti, (int)t_items.size(), max_t, d_outs, (int)outs.size(), max_out, data,
                                       d_z, d_o, d_t, d_out, s));
+            phase("O^T Z O (two passes)");
             ob->data.resize((size_t)out_len);
-            if (out_len > 0)
-                HIPCHK(hipMemcpyAsync(ob->data.data(), d_out, (size_t)out_len * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
+            download(ob->data.data(), d_out, out_len, s);
+            phase("download");
         } catch (...) {
             (void)hipStreamSynchronize(s);
             throw;
