@@ -29,7 +29,7 @@ HBM_PEAK = 8000.0                        # GB/s
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the launches of one call, scaled by the factors of
 # a 1 GiB device copy in the same runs (profiles/hpsi_fp64_L24_M1024_kernel_trace.md). Valid for that
 # workload and these kernels only.
-FP64_TRAFFIC_L24_M1024 = {"fetch_bytes": 48094.9 * 2**20, "write_bytes": 417.1 * 2**20}
+FP64_TRAFFIC_L24_M1024 = {"fetch_bytes": 22901.0 * 2**20, "write_bytes": 1069.7 * 2**20}
 # HBM traffic of one split H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
 # rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the k_pack_xt / k_zero_lds / k_hpsi_lds /
 # k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
@@ -174,7 +174,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp64"], 4),
                 "traffic": (tr64["fetch_bytes"] + tr64["write_bytes"]) if tr64 else None,
-                "kernel": "FP64 H.psi sequence (k_pack, k_hpsi_f64 tile classes, k_big64 passes, k_reduce)",
+                "kernel": "FP64 H.psi sequence (k_hpsi_lds64 classes, k_hpsi_f64 tile classes for single-tile "
+                          "sources, k_big64 passes above 96 x 96, k_pack, k_pack_xt64, k_reduce, k_reduce_lds)",
                 "algorithmic_bytes": st["bytes"],
                 "hbm_frac": round(st["bytes"] / t64 / 1e9 / HBM_PEAK, 4)}
     achieved_sp = st["flops"] / tsp / 1e12

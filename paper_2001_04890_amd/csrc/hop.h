@@ -180,6 +180,12 @@ struct dmrg_hop {
     dmrg::BigPlan bplan64{};
     std::vector<dmrg::BigChunk> big_chunks64;
     double* xt64 = nullptr;                     // FP64 tiled X^T of one vector (plan allocation)
+    // FP64 LDS-staged kernel (hpsi_lds64.hip) for the targets within the 96-wide stages
+    int tune_lds64 = 1;                         // 0: those targets take the one-wave kernel
+    int tune_lds64_items = 32768;               // target number of its work items per H.psi
+    int tune_lds64_small = 0;                   // 1: it also takes tasks whose source is one 32 x 32 tile
+                                                // (0: those run in the one-wave kernel)
+    dmrg::LdsPlan64 lplan64{};
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)
     int vec_step = 1;                      // vectors per launch sequence (packed-input and partial buffers)

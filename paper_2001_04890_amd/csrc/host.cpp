@@ -534,7 +534,12 @@ double mat_bytes(const dmrg_hop& H, int m) { return m < 0 ? 0.0 : H.mats[m].byte
 //    tune_items items per matvec); a tile split over several chunks writes partial tiles that the
 //    phase's reduction adds in order.
 void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, bool split_bufs, dmrg::HpsiPlan& plan,
-                     std::vector<dmrg::HpsiLaunch>& launches_out, std::vector<dmrg::HpsiPhase>& phases_out) {
+                     std::vector<dmrg::HpsiLaunch>& launches_out, std::vector<dmrg::HpsiPhase>& phases_out,
+                     const std::vector<char>* task_only = nullptr) {
+    // tasks of this plan: those of the targets in `only` (all without it) that `task_only` keeps
+    auto keep = [&](size_t t) {
+        return (!only || (*only)[H.tasks[t].j]) && (!task_only || (*task_only)[t]);
+    };
     constexpr double kCacheBudget = 96.0 * 1024 * 1024;
     // packed input layout: every psi block padded to multiples of 32 in both directions
     std::vector<dmrg::PackBlock> packs;
@@ -550,8 +555,8 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
     std::map<std::pair<int, int>, int> pair_phase;
     {
         std::vector<std::pair<int, int>> pairs;
-        for (const auto& t : H.tasks)
-            if (!only || (*only)[t.j]) pairs.push_back({t.rm, t.lm});
+        for (size_t t = 0; t < H.tasks.size(); ++t)
+            if (keep(t)) pairs.push_back({H.tasks[t].rm, H.tasks[t].lm});
         std::sort(pairs.begin(), pairs.end());
         pairs.erase(std::unique(pairs.begin(), pairs.end()), pairs.end());
         std::vector<double> pb(pairs.size());
@@ -580,7 +585,7 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
         for (size_t j = 0; j < H.blk.size(); ++j) {
             for (auto& v : by_phase) v.clear();
             while (t < H.tasks.size() && H.tasks[t].j == (int)j) {
-                by_phase[pair_phase[{H.tasks[t].lm, H.tasks[t].rm}]].push_back(t);
+                if (keep(t)) by_phase[pair_phase[{H.tasks[t].lm, H.tasks[t].rm}]].push_back(t);
                 ++t;
             }
             for (int ph = 0; ph < np; ++ph) {
@@ -609,6 +614,7 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
     const int tile_cols = 16 * H.tune_max_tq;
     for (size_t j = 0; j < H.blk.size(); ++j) {
         if (only && !(*only)[j]) continue;
+        if (trange[j * np].first == trange[j * np + np - 1].second) continue;   // no task kept
         int mj = H.blk_ma[j], nj = H.blk_md[j];
         for (int r0 = 0; r0 < mj; r0 += dmrg::kTileRows)
             for (int c0 = 0; c0 < nj; c0 += tile_cols) {
@@ -1273,27 +1279,189 @@ void make_tiled_f64(dmrg_hop& H, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));   // the staging vector goes out of scope
 }
 
+// Launch plan of the FP64 LDS-staged kernel (hpsi_lds64.hip) for the target blocks whose own and
+// sources' padded dimensions are at most 96 (targets flagged in `large` are skipped, and so are tasks
+// whose source is a single 32 x 32 tile unless tune_lds64_small; `lds` marks the tasks taken). A
+// target's tasks (source order) go to the KT = 2 classes when the source has at most 32 rows, else to
+// KT = 6; each run is cut into items of bounded cost (the MFMA instructions of one wavefront plus a
+// per-step and per-task overhead), and a target covered by several items gets partial tiles that a
+// reduction adds in item order. The packed input has the geometry of the other FP64 plans (every psi
+// block padded to multiples of 32).
+void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large, std::vector<char>& lds) {
+    const size_t nb = H.blk.size();
+    lds.assign(H.tasks.size(), 0);
+    std::vector<int64_t> pk_off(nb);
+    int64_t psize = 0;
+    for (size_t i = 0; i < nb; ++i) {
+        pk_off[i] = psize;
+        psize += (int64_t)dmrg::ld_of(H.blk_ma[i]) * dmrg::ld_of(H.blk_md[i]);
+    }
+    auto ident = [&](int p) -> int64_t {
+        const int k = p / 32 - 1;
+        if (k < 0 || k >= (int)H.ident64_off.size() || H.ident64_off[k] < 0)
+            throw Error(DMRG_ERR_ARG, "internal: no FP64 tiled identity block");
+        return H.ident64_off[k];
+    };
+    // every operand block the kernel reads must be a pool block of the task's shape (rows in 16-row
+    // tiles, at least the rows read; columns exactly the source's padded dimension) or an identity block
+    std::unordered_map<int64_t, std::pair<int, int>> shape;   // offset -> (row tiles, 16-wide k tiles)
+    for (const auto& pb : H.pool_blocks) shape[pb.off] = {pb.r16, 2 * pb.k32};
+    for (size_t q = 0; q < H.ident64_off.size(); ++q)
+        if (H.ident64_off[q] >= 0) shape[H.ident64_off[q]] = {2 * (int)(q + 1), 2 * (int)(q + 1)};
+    auto check = [&](int64_t off, int rows16, int k16) {
+        auto it = shape.find(off);
+        if (it == shape.end() || it->second.first < rows16 || it->second.second != k16)
+            throw Error(DMRG_ERR_ARG, "internal: FP64 LDS task operand does not match its pool block");
+    };
+    // MFMA instructions of one wavefront (per source column tile: GEMM1 over ka16 k tiles, GEMM2 over
+    // tq column tiles) + per-step and per-task overhead
+    auto cost = [](const dmrg::LTask64& L, int tq) { return L.kd16 * (4.0 * (L.ka16 + tq) + 6.0) + 4.0; };
+    struct Run { int j, cls, tq; int32_t tb, te; };
+    std::vector<dmrg::LTask64> lt;
+    lt.reserve(H.tasks.size());
+    std::vector<Run> runs;
+    double total = 0.0;
+    size_t k = 0;
+    for (size_t j = 0; j < nb; ++j) {
+        const size_t kb = k;
+        while (k < H.tasks.size() && H.tasks[k].j == (int)j) ++k;
+        if (k == kb || large[j]) continue;
+        const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, tq = dmrg::rows_of(H.blk_md[j]) / 16;
+        if (nrt > dmrg::kLds64Waves || tq > 6) throw Error(DMRG_ERR_ARG, "internal: FP64 LDS target beyond 96 x 96");
+        const int qcls = tq <= 3 ? 0 : 1;
+        std::vector<dmrg::LTask64> v2, v6;
+        for (size_t t = kb; t < k; ++t) {
+            const auto& ht = H.tasks[t];
+            const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
+            const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
+            if (!H.tune_lds64_small && pa <= 32 && pd <= 32) continue;   // single-tile source: one-wave kernel
+            lds[t] = 1;
+            dmrg::LTask64 L;
+            L.x_off = pk_off[ht.i];
+            L.a_off = ht.lm >= 0 ? H.mats[ht.lm].pool_of_in[a] : ident(pa);
+            L.b_off = ht.rm >= 0 ? H.mats[ht.rm].pool_of_in[d] : ident(pd);
+            if (L.a_off < 0 || L.b_off < 0) throw Error(DMRG_ERR_ARG, "internal: operator block missing from the pool");
+            L.f = ht.f;
+            L.pa16 = (int16_t)(pa / 16);
+            L.pd16 = (int16_t)(pd / 16);
+            L.ka16 = (int16_t)((H.blk_ma[ht.i] + 15) / 16);
+            L.kd16 = (int16_t)((H.blk_md[ht.i] + 15) / 16);
+            if (L.pa16 > 6 || L.pd16 > 6 || L.x_off + (int64_t)pa * pd > psize)
+                throw Error(DMRG_ERR_ARG, "internal: FP64 LDS task beyond the 96-wide stages");
+            check(L.a_off, nrt, L.pa16);
+            check(L.b_off, tq, L.pd16);
+            (L.ka16 <= 2 ? v2 : v6).push_back(L);
+        }
+        for (int kc : {0, 1}) {
+            const auto& v = kc == 0 ? v2 : v6;
+            if (v.empty()) continue;
+            Run R{(int)j, 2 * kc + qcls, tq, (int32_t)lt.size(), 0};
+            for (const auto& L : v) { lt.push_back(L); total += cost(L, tq); }
+            R.te = (int32_t)lt.size();
+            runs.push_back(R);
+        }
+    }
+    H.lplan64 = dmrg::LdsPlan64{};
+    const double cmax = std::max(total / std::max(1, H.tune_lds64_items), 200.0);
+    struct It { dmrg::Item item; double cost; int cls; };
+    std::vector<It> its;
+    std::vector<dmrg::Reduce> reds;
+    int64_t part = 0;
+    int most = 1;
+    // the runs of one target (one per stage size) are consecutive; all their chunks share one
+    // reduction record, so that no two records of the one reduction launch add into the same tile
+    for (size_t r0 = 0, r1; r0 < runs.size(); r0 = r1) {
+        r1 = r0;
+        while (r1 < runs.size() && runs[r1].j == runs[r0].j) ++r1;
+        struct Chunk { int32_t b, e; double cost; int cls; };
+        std::vector<Chunk> chunks;
+        for (size_t r = r0; r < r1; ++r) {
+            const Run& R = runs[r];
+            int32_t b = R.tb;
+            double c = 0.0;
+            for (int32_t t = R.tb; t < R.te; ++t) {
+                const double tc = cost(lt[t], R.tq);
+                if (c + tc > cmax && t > b) { chunks.push_back({b, t, c, R.cls}); b = t; c = 0.0; }
+                c += tc;
+            }
+            chunks.push_back({b, R.te, c, R.cls});
+        }
+        const int j = runs[r0].j, tm = dmrg::rows_of(H.blk_ma[j]), tn = 16 * runs[r0].tq;
+        if (chunks.size() == 1) {
+            const Chunk& q = chunks[0];
+            its.push_back({{H.blk_off[j], -1, H.blk_ma[j], H.blk_md[j], 0, 0, q.b, q.e}, q.cost, q.cls});
+            continue;
+        }
+        reds.push_back({H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], 0, 0, tm, tn, (int32_t)chunks.size(), 0});
+        most = std::max(most, tm * tn);
+        for (const Chunk& q : chunks) {
+            its.push_back({{H.blk_off[j], part, H.blk_ma[j], H.blk_md[j], 0, 0, q.b, q.e}, q.cost, q.cls});
+            part += (int64_t)tm * tn;
+        }
+    }
+    // launch order: class, then heaviest item first
+    std::stable_sort(its.begin(), its.end(), [](const It& a, const It& b) {
+        if (a.cls != b.cls) return a.cls < b.cls;
+        return a.cost > b.cost;
+    });
+    std::vector<dmrg::Item> items;
+    items.reserve(its.size());
+    int cnt[dmrg::kLdsClasses] = {0};
+    for (const It& x : its) { items.push_back(x.item); cnt[x.cls]++; }
+    for (int c = 0; c < dmrg::kLdsClasses; ++c) H.lplan64.cls_begin[c + 1] = H.lplan64.cls_begin[c] + cnt[c];
+    dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
+    dmrg::LTask64* d_lt = plan_alloc<dmrg::LTask64>(H, lt.size());
+    dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
+    if (!items.empty())
+        HIPCHK(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(items[0]), hipMemcpyHostToDevice, s));
+    if (!lt.empty()) HIPCHK(hipMemcpyAsync(d_lt, lt.data(), lt.size() * sizeof(lt[0]), hipMemcpyHostToDevice, s));
+    if (!reds.empty()) HIPCHK(hipMemcpyAsync(d_red, reds.data(), reds.size() * sizeof(reds[0]), hipMemcpyHostToDevice, s));
+    H.lplan64.items = d_items;
+    H.lplan64.tasks = d_lt;
+    H.lplan64.reduces = d_red;
+    H.lplan64.n_reduces = (int)reds.size();
+    H.lplan64.red_chunks = (most + 255) / 256;
+    H.lplan64.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1));
+    H.lplan64.partial_size = part;
+    H.lplan64.n_items = (int)items.size();
+    if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
+        if (e[0] == '1') {
+            std::fprintf(stderr, "[dmrg lds64 plan] items %zu classes", items.size());
+            for (int c = 0; c < dmrg::kLdsClasses; ++c) std::fprintf(stderr, " %d", cnt[c]);
+            std::fprintf(stderr, " reduces %zu partial %.1f MB\n", reds.size(), part * 8e-6);
+        }
+    HIPCHK(hipStreamSynchronize(s));
+}
+
 void build_plan(dmrg_hop& H, hipStream_t s) {
     drop_graphs(H);
     for (void* p : H.plan_allocations) (void)hipFree(p);
     H.plan_allocations.clear();
     H.plan_bytes = 0;
-    // FP64: targets above the LDS stage size take the two-pass path, the others the one-wave kernel
+    // FP64: targets within the 96-wide LDS stages take the LDS-staged kernel; larger ones the
+    // two-pass path where it is cheaper, the one-wave kernel otherwise
     H.bplan64 = dmrg::BigPlan{};
     H.big_chunks64.clear();
+    H.lplan64 = dmrg::LdsPlan64{};
     H.xt64 = nullptr;
-    std::vector<char> big64;
-    bool any_big = false;
+    const size_t nb = H.blk.size();
+    std::vector<char> big64(nb, 0), lds64;   // targets of the two-pass path; tasks of the LDS kernel
+    bool any_big = false, any_lds = false;
     if (H.tune_big64) {
         big64 = fp64_big_targets(H, H.tune_big64);
         for (char b : big64) any_big |= b != 0;
     }
-    if (any_big) {
-        std::vector<char> rest(big64.size());
-        for (size_t j = 0; j < big64.size(); ++j) rest[j] = !big64[j];
-        build_plan_core(H, s, &rest, false, H.plan, H.launches, H.phases);
-        make_tiled_f64(H, s);
-        build_big_plan(H, s, big64, true);
+    if (H.tune_lds64 || any_big) make_tiled_f64(H, s);
+    if (H.tune_lds64) {
+        build_lds64_plan(H, s, large_targets(H), lds64);
+        for (char b : lds64) any_lds |= b != 0;
+    }
+    if (any_big || any_lds) {
+        std::vector<char> rest(nb), rest_tasks(H.tasks.size(), 1);
+        for (size_t j = 0; j < nb; ++j) rest[j] = !big64[j];
+        for (size_t t = 0; t < lds64.size(); ++t) rest_tasks[t] = !lds64[t];
+        build_plan_core(H, s, &rest, false, H.plan, H.launches, H.phases, &rest_tasks);
+        if (any_big) build_big_plan(H, s, big64, true);
         H.xt64 = plan_alloc<double>(H, (size_t)std::max<int64_t>(H.plan.packed_size, 1));
     } else {
         build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
@@ -1620,6 +1788,9 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS_W6")) H->tune_lds_w6 = std::atoi(e) & 0xA;
         if (const char* e = std::getenv("DMRG_BIG")) H->tune_big = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_BIG64")) H->tune_big64 = std::max(0, std::min(2, std::atoi(e)));
+        if (const char* e = std::getenv("DMRG_LDS64")) H->tune_lds64 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS64_ITEMS")) H->tune_lds64_items = std::max(64, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
@@ -1739,10 +1910,16 @@ void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t
         const double* xv = x + (int64_t)v0 * H->n_coeff;
         double* yv = y + (int64_t)v0 * H->n_coeff;
         if (precision == DMRG_PREC_FP64) {
+            // zeroes y, then the one-wave targets
             HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
-            for (int v = 0; v < nv && H->bplan64.n_chunks > 0; ++v)
-                HIPCHK(dmrg::launch_hpsi_big64(H->bplan64, H->d_tiled64, H->plan.packs, H->plan.n_packs,
-                                               xv + (int64_t)v * H->n_coeff, H->xt64, yv + (int64_t)v * H->n_coeff, s));
+            const bool lds = H->lplan64.n_items > 0, big = H->bplan64.n_chunks > 0;
+            for (int v = 0; v < nv && (lds || big); ++v) {
+                const double* x1 = xv + (int64_t)v * H->n_coeff;
+                double* y1 = yv + (int64_t)v * H->n_coeff;
+                HIPCHK(dmrg::launch_pack_xt64(H->plan.packs, H->plan.n_packs, x1, H->xt64, s));
+                if (lds) HIPCHK(dmrg::launch_hpsi_lds64(H->lplan64, H->d_tiled64, H->xt64, y1, s));
+                if (big) HIPCHK(dmrg::launch_hpsi_big64(H->bplan64, H->d_tiled64, nullptr, 0, x1, H->xt64, y1, s));
+            }
         } else {
             HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
             for (int v = 0; v < nv && H->bplan.n_chunks > 0; ++v)
@@ -1893,6 +2070,9 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
             }
         }
         C->tune_big64 = hops[0]->tune_big64;
+        C->tune_lds64 = hops[0]->tune_lds64;
+        C->tune_lds64_items = hops[0]->tune_lds64_items;
+        C->tune_lds64_small = hops[0]->tune_lds64_small;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
         C->tune_lds_w6 = hops[0]->tune_lds_w6;
@@ -1938,6 +2118,7 @@ extern "C" dmrg_status dmrg_hop_trim(dmrg_hop* H) {
         H->lplan = dmrg::LdsPlan{};
         H->bplan = dmrg::BigPlan{};
         H->bplan64 = dmrg::BigPlan{};
+        H->lplan64 = dmrg::LdsPlan64{};
         H->launches.clear(); H->phases.clear(); H->launches_fb.clear(); H->phases_fb.clear();
         H->big_chunks.clear(); H->big_chunks64.clear();
         H->n_fallback_targets = 0;

@@ -170,12 +170,13 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
         for (int jj = 0; jj < 4; ++jj) p[jj] = lds4(sp + (4 * wj + jj) * kTileD);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) q[rr] = lds4(sp + (8 + 4 * wr + rr) * kTileD);
+        // consecutive MFMAs accumulate into the same registers (the fast path of the matrix core)
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
-            for (int jj = 0; jj < 4; ++jj)
+            for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr)
+                for (int v = 0; v < 4; ++v)
                     acc[jj][rr] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[jj][v], q[rr][v], acc[jj][rr], 0, 0, 0);
         if (ngi != gi) store(cur);
         wait_vm();
@@ -249,11 +250,11 @@ __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items,
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) q[qq] = lds4(sp + (8 + 4 * wq + qq) * kTileD);
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
+        for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
+            for (int qq = 0; qq < 4; ++qq)
 #pragma unroll
-                for (int qq = 0; qq < 4; ++qq)
+                for (int v = 0; v < 4; ++v)
                     acc[rr][qq] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[rr][v], q[qq][v], acc[rr][qq], 0, 0, 0);
         wait_vm();
         __syncthreads();
@@ -303,10 +304,16 @@ __global__ void k_reduce_big64(const Reduce* __restrict__ red, const double* __r
     y[R.y_off + (int64_t)row * R.m_dp + col] += s;
 }
 
+hipError_t launch_pack_xt64(const PackBlock* packs, int n_packs, const double* x, double* xt, hipStream_t s) {
+    if (n_packs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_xt64, dim3(n_packs), dim3(256), 0, s, packs, x, xt);
+    return hipGetLastError();
+}
+
 hipError_t launch_hpsi_big64(const BigPlan& P, const double* pool_t, const PackBlock* packs, int n_packs,
                              const double* x, double* xt, double* y, hipStream_t s) {
     if (P.n_chunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_xt64, dim3(n_packs), dim3(256), 0, s, packs, x, xt);
+    if (packs && n_packs > 0) hipLaunchKernelGGL(k_pack_xt64, dim3(n_packs), dim3(256), 0, s, packs, x, xt);
     const double* tb = reinterpret_cast<const double*>(P.tbuf);
     for (int c = 0; c < P.n_chunks; ++c) {
         const BigChunk& C = P.chunks[c];

@@ -559,6 +559,13 @@ __global__ void k_reduce_lds(const Reduce* __restrict__ red, const double* __res
     yall[(int64_t)blockIdx.y * n_coeff + R.y_off + (int64_t)row * R.m_dp + col] += s;
 }
 
+hipError_t launch_reduce_partials(const Reduce* reduces, int n, int chunks, const double* partial, double* y,
+                                  hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_lds, dim3(n, 1, chunks), dim3(256), 0, s, reduces, partial, y, (int64_t)0, (int64_t)0);
+    return hipGetLastError();
+}
+
 __global__ void k_zero_lds(double* __restrict__ y, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         y[i] = 0.0;

@@ -1,0 +1,223 @@
+// LDS-staged FP64 sector GEMMs of Eq. dgemm (Section 2.2.1) for gfx950, on v_mfma_f64_16x16x4f64
+// with FP64 accumulation.
+//
+// One workgroup of six wavefronts owns a whole target psi block of at most 96 x 96 (every row and
+// column) and loops over a range of its tasks Y += f * A . X . B^T (sorted by source block); wave w
+// owns row tile w (waves past the target's rows only help with the copies). The tasks are cut into
+// steps, one per 16-wide column tile jc of the source (the tiles that hold data), and per step:
+//   GEMM1  T'(w, jc)^T = X^T(jc, :) . A(w, :)^T   A-operand: the X^T slice from LDS; B-operand: the
+//                                                  wave's A row tile, held in registers for the
+//                                                  whole task (read straight from the tiled pool)
+//   GEMM2  Y(w, :)   += f T'(w, jc) . B(:, jc)^T  A-operand: T' (the MFMA result layout of GEMM1 is
+//                                                  the tile format, i.e. the A-operand layout of
+//                                                  GEMM2); B-operand: the B slice from LDS
+// The step's X^T slice (at most KT tiles) and B slice (at most QT tiles) are copied into one of two
+// LDS slots with global_load_lds_dwordx4 (2 KB tiles, 1 KB per wave instruction), issued before the
+// previous step computes; every operand read is a contiguous 32 bytes per lane. All wavefronts share
+// each staged slice, so a task reads its X and B blocks once per workgroup rather than once per
+// output tile. The compiler cannot tell which LDS such a copy writes and makes the step's first LDS
+// read wait for the copies in flight, so the latency is hidden across workgroups rather than inside
+// one: a slot is (KT + QT) tiles, at most 24 KB, and two to four workgroups share a CU (measured:
+// staging through registers instead, which removes that wait, is slower at these sizes, as the extra
+// registers cost a workgroup per CU). The A rows of the next task are read during the last step's
+// GEMM2.
+// Consecutive MFMAs accumulate into the same registers, the fast path of the matrix core.
+//
+// Tile format (internal.h, hpsi_big64.hip): a 16 x 16 tile holds M[16 rt + li][16 kt + 4 v + g] in
+// lane (li, g) = (l % 16, l / 16), value v.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace dmrg {
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+constexpr int kTileD = 256;   // doubles per 16 x 16 tile
+
+__device__ __forceinline__ f64x4 ld4g(const double* p) { return *reinterpret_cast<const f64x4*>(p); }
+__device__ __forceinline__ f64x4 ld4s(const double* p) { return *reinterpret_cast<const f64x4*>(p); }
+__device__ __forceinline__ void wait_vm() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double unid(double v) {
+    return __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, v)));
+}
+
+// Task descriptor in scalar registers (offsets in doubles; pa16 / pd16: tile strides of the source's
+// rows / columns; ka16 / kd16: the tiles of them that hold data).
+struct TD { int64_t x, a, b; double f; int pa16, pd16, ka16, kd16; };
+__device__ __forceinline__ TD load_td(const LTask64* __restrict__ p) {
+    TD d;
+    d.x = uni64(p->x_off);
+    d.a = uni64(p->a_off);
+    d.b = uni64(p->b_off);
+    d.f = unid(p->f);
+    d.pa16 = uni(p->pa16);
+    d.pd16 = uni(p->pd16);
+    d.ka16 = uni(p->ka16);
+    d.kd16 = uni(p->kd16);
+    return d;
+}
+
+}  // namespace
+
+// KT: most k tiles (source rows in 16-wide tiles) of the item's tasks; QT: most column tiles of the
+// target.
+template <int KT, int QT>
+__global__ __launch_bounds__(kLds64Waves * 64) void k_hpsi_lds64(const Item* __restrict__ items,
+                                                                const LTask64* __restrict__ tasks,
+                                                                const double* __restrict__ pool_t,
+                                                                const double* __restrict__ xt,
+                                                                double* __restrict__ y, double* __restrict__ part) {
+    constexpr int SLOT = (KT + QT) * kTileD;   // doubles of one slot: X^T slice, then B slice
+    __shared__ __attribute__((aligned(16))) double lds[2 * SLOT];
+
+    const Item I = items[blockIdx.x];
+    const int64_t y_off = uni64(I.y_off), part_off = uni64(I.part_off);
+    const int m_ap = uni(I.m_ap), m_dp = uni(I.m_dp);
+    const int t_begin = uni(I.t_begin), t_end = uni(I.t_end);
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int li = lane & 15, g = lane >> 4;
+    const int nrt = (m_ap + 15) >> 4;
+    const int tq = min(QT, (m_dp + 15) >> 4);
+    const bool active = wave < nrt;
+
+    f64x4 acc[QT];
+#pragma unroll
+    for (int q = 0; q < QT; ++q) acc[q] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+    // the wave's A row tile of a task: tiles (wave, kt); outside the source (kt >= ka16) or past the
+    // target the block's first tile is read instead and never used (branch-free, so the loads stay
+    // in flight)
+    auto load_a = [&](const TD& T, f64x4 (&ar)[KT]) {
+#pragma unroll
+        for (int kt = 0; kt < KT; ++kt) {
+            const bool in = kt < T.ka16 && active;
+            const int64_t tile = in ? (int64_t)wave * T.pa16 + kt : 0;
+            ar[kt] = ld4g(pool_t + T.a + tile * kTileD + lane * 4);
+        }
+    };
+    // copy the operands of step (T, jc) into a slot: X^T tiles (jc, kt < ka16), contiguous in the
+    // tiled X^T, then B tiles (q < tq, jc), one per target column tile; half tiles dealt to the waves
+    auto stage = [&](const TD& T, int jc, int slot) {
+        double* d = lds + slot * SLOT;
+        const double* xs = xt + T.x + (int64_t)jc * T.pa16 * kTileD;
+        const int nx = 2 * T.ka16, n = nx + 2 * tq;
+        for (int h = wave; h < n; h += kLds64Waves) {
+            const double* src;
+            double* dst;
+            if (h < nx) {
+                src = xs + h * 128;
+                dst = d + h * 128;
+            } else {
+                const int q = (h - nx) >> 1, half = (h - nx) & 1;
+                src = pool_t + T.b + ((int64_t)q * T.pd16 + jc) * kTileD + half * 128;
+                dst = d + (KT + q) * kTileD + half * 128;
+            }
+            __builtin_amdgcn_global_load_lds((const void*)(src + lane * 2), (lds_ptr_t)dst, 16, 0, 0);
+        }
+    };
+
+    int t = t_begin, jc = 0, slot = 0;
+    TD T = load_td(tasks + t);
+    f64x4 ar[KT];
+    stage(T, 0, 0);
+    load_a(T, ar);
+    wait_vm();
+    __syncthreads();
+    for (;;) {
+        const bool more_cols = jc + 1 < T.kd16;
+        const bool new_task = !more_cols && t + 1 < t_end;
+        const bool has_next = more_cols || new_task;
+        TD Tn = T;
+        if (new_task) Tn = load_td(tasks + t + 1);
+        if (has_next) stage(Tn, more_cols ? jc + 1 : 0, slot ^ 1);   // last read before the previous barrier
+        const double* xs = lds + slot * SLOT;
+        const double* bs = xs + KT * kTileD;
+        f64x4 tt = f64x4{0.0, 0.0, 0.0, 0.0};
+        if (active) {
+#pragma unroll
+            for (int kt = 0; kt < KT; ++kt) {
+                if (kt < T.ka16) {
+                    const f64x4 xv = ld4s(xs + kt * kTileD + lane * 4);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        tt = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[v], ar[kt][v], tt, 0, 0, 0);
+                }
+            }
+        }
+        // tt[v] = T'[16 wave + li][16 jc + 4 v + g] (unscaled); the A rows are free now
+        if (new_task) load_a(Tn, ar);
+        if (active) {
+            tt *= T.f;
+#pragma unroll
+            for (int q = 0; q < QT; ++q) {
+                if (q < tq) {
+                    const f64x4 bv = ld4s(bs + q * kTileD + lane * 4);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(tt[v], bv[v], acc[q], 0, 0, 0);
+                }
+            }
+        }
+        wait_vm();
+        __syncthreads();
+        if (!has_next) break;
+        if (more_cols) {
+            ++jc;
+        } else {
+            ++t;
+            jc = 0;
+            T = Tn;
+        }
+        slot ^= 1;
+    }
+    if (!active) return;
+    // store: lane (li, g) holds Y[16 wave + g + 4 v][16 q + li]
+    const int tn = 16 * tq;
+#pragma unroll
+    for (int q = 0; q < QT; ++q) {
+        if (q >= tq) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * wave + g + 4 * v, col = 16 * q + li;
+            if (part_off < 0) {
+                if (row < m_ap && col < m_dp) y[y_off + (int64_t)row * m_dp + col] += acc[q][v];
+            } else {
+                part[part_off + (int64_t)row * tn + col] = acc[q][v];
+            }
+        }
+    }
+}
+
+hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s) {
+    if (P.n_items == 0) return hipSuccess;
+    for (int c = 0; c < kLdsClasses; ++c) {
+        const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
+        if (n <= 0) continue;
+        const dim3 grid(n), block(kLds64Waves * 64);
+#define DMRG_L64(KT_, QT_) \
+    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_>), grid, block, 0, s, P.items + b, P.tasks, pool_t, xt, y, P.partial)
+        switch (c) {
+            case 0: DMRG_L64(2, 3); break;
+            case 1: DMRG_L64(2, 6); break;
+            case 2: DMRG_L64(6, 3); break;
+            default: DMRG_L64(6, 6); break;
+        }
+#undef DMRG_L64
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess || P.n_reduces <= 0) return e;
+    return launch_reduce_partials(P.reduces, P.n_reduces, P.red_chunks, P.partial, y, s);
+}
+
+}  // namespace dmrg

@@ -178,6 +178,39 @@ struct LdsPlan {
                                         // two of the SIMDs (measured faster; (64,2) is not)
 };
 
+// Launch plan of the FP64 LDS-staged kernel (hpsi_lds64.hip): items (internal.h Item; r0 = c0 = 0)
+// each cover a whole target block of at most 96 x 96 and a range of its tasks, over the FP64 tiled
+// pool (identity factors point at its identity blocks) and the tiled FP64 X^T of the packed input
+// (offsets in doubles). Launch class c = 2 (KT == 6) + (QT == 6): KT = 2 when every task of the item
+// has at most 32 source rows, else 6; QT = 3 for targets of at most 48 columns, else 6.
+constexpr int kLds64Waves = 6;          // wavefronts per workgroup: one per target row tile
+struct LTask64 {
+    int64_t x_off, a_off, b_off;
+    double  f;
+    int16_t pa16, pd16;      // source rows / columns padded to 32, in 16-wide tiles (tile strides)
+    int16_t ka16, kd16;      // source rows / columns padded to 16: the k tiles and j tiles that hold
+                             // data (the others are zero padding and are skipped)
+};
+struct LdsPlan64 {
+    const Item* items = nullptr;        // device
+    const LTask64* tasks = nullptr;     // device
+    const Reduce* reduces = nullptr;    // device; one record per target cut into several items (its
+    int n_reduces = 0;                  // items of both stage sizes), so one launch adds them all
+    int red_chunks = 1;                 // 256-element chunks of the largest partial tile
+    int cls_begin[kLdsClasses + 1] = {0, 0, 0, 0, 0};
+    double* partial = nullptr;          // device, partial tiles of one vector
+    int64_t partial_size = 0;
+    int n_items = 0;
+};
+// y (one vector) += the plan's targets of f A X B^T; xt = that vector's tiled FP64 X^T
+// (launch_pack_xt64 with the FP64 packing geometry)
+hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s);
+// tiled FP64 X^T of every psi block (hpsi_big64.hip)
+hipError_t launch_pack_xt64(const PackBlock* packs, int n_packs, const double* x, double* xt, hipStream_t s);
+// y (one vector) += the partial tiles of each record, in order (hpsi_lds.hip)
+hipError_t launch_reduce_partials(const Reduce* reduces, int n, int chunks, const double* partial, double* y,
+                                  hipStream_t s);
+
 // ---------------------------------------------------------------- large blocks (hpsi_big.hip)
 // Targets whose blocks (or sources) exceed the 96-wide LDS stages take two passes per chunk of
 // targets: pass 1 writes T = f A X of every task into a tiled hi/lo buffer (tile (rt, jc) of the
@@ -274,7 +307,8 @@ hipError_t launch_hpsi_lds(const LdsPlan& plan, const uint16_t* pool_t, const do
 hipError_t launch_hpsi_big(const BigPlan& plan, const uint16_t* pool_t, const uint16_t* xt, double* y,
                            hipStream_t s);
 // FP64 large-block path (hpsi_big64.hip) for one vector: y += the large targets' part of H x, over the
-// FP64 tiled pool; packs x into xt (FP64 tiled X^T, packed_size doubles) first.
+// FP64 tiled pool; packs x into xt (FP64 tiled X^T, packed_size doubles) first unless packs is null
+// (xt already holds it).
 hipError_t launch_tile_f64(const double* pool, const PoolBlock* blocks, int n_blocks, double* tiled, hipStream_t s);
 hipError_t launch_hpsi_big64(const BigPlan& plan, const double* pool_t, const PackBlock* packs, int n_packs,
                              const double* x, double* xt, double* y, hipStream_t s);

@@ -205,17 +205,19 @@ __global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const It
                 f64x4 a4[TP];
 #pragma unroll
                 for (int p = 0; p < TP; ++p) a4[p] = f * ld4(A + (I.r0 + 16 * p + li) * pa + k0 + 4 * g);
+                double xv[4][TQ];
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double xv[TQ];
+                for (int v = 0; v < 4; ++v)
 #pragma unroll
-                    for (int q = 0; q < TQ; ++q) xv[q] = X[(k0 + 4 * g + v) * pd + I.c0 + 16 * q + li];
+                    for (int q = 0; q < TQ; ++q) xv[v][q] = X[(k0 + 4 * g + v) * pd + I.c0 + 16 * q + li];
+                // consecutive MFMAs accumulate into the same registers (the fast path of the matrix core)
 #pragma unroll
-                    for (int p = 0; p < TP; ++p)
+                for (int p = 0; p < TP; ++p)
 #pragma unroll
-                        for (int q = 0; q < TQ; ++q)
-                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[p][v], xv[q], acc[p][q], 0, 0, 0);
-                }
+                    for (int q = 0; q < TQ; ++q)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a4[p][v], xv[v][q], acc[p][q], 0, 0, 0);
             }
         } else if (T.a_off < 0) {
             // Y += f X B^T (left identity)
@@ -227,11 +229,11 @@ __global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const It
 #pragma unroll
                 for (int q = 0; q < TQ; ++q) b4[q] = ld4(B + (I.c0 + 16 * q + li) * pd + k0 + 4 * g);
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                for (int p = 0; p < TP; ++p)
 #pragma unroll
-                    for (int p = 0; p < TP; ++p)
+                    for (int q = 0; q < TQ; ++q)
 #pragma unroll
-                        for (int q = 0; q < TQ; ++q)
+                        for (int v = 0; v < 4; ++v)
                             acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(x4[p][v], b4[q][v], acc[p][q], 0, 0, 0);
             }
         } else {
@@ -246,13 +248,14 @@ __global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const It
                     f64x4 a4[TP];
 #pragma unroll
                     for (int p = 0; p < TP; ++p) a4[p] = ld4(A + (I.r0 + 16 * p + li) * pa + k0 + 4 * g);
+                    double xv[4];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const double xv = X[(k0 + 4 * g + v) * pd + j0 + pl];
+                    for (int v = 0; v < 4; ++v) xv[v] = X[(k0 + 4 * g + v) * pd + j0 + pl];
 #pragma unroll
-                        for (int p = 0; p < TP; ++p)
-                            tt[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv, a4[p][v], tt[p], 0, 0, 0);
-                    }
+                    for (int p = 0; p < TP; ++p)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            tt[p] = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[v], a4[p][v], tt[p], 0, 0, 0);
                 }
                 // tt[p][v] = T'[r0 + 16p + li][j0 + 4g + v]
                 f64x4 b4[TQ];
@@ -261,11 +264,11 @@ __global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const It
 #pragma unroll
                 for (int p = 0; p < TP; ++p) tt[p] *= f;
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
+                for (int p = 0; p < TP; ++p)
 #pragma unroll
-                    for (int p = 0; p < TP; ++p)
+                    for (int q = 0; q < TQ; ++q)
 #pragma unroll
-                        for (int q = 0; q < TQ; ++q)
+                        for (int v = 0; v < 4; ++v)
                             acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(tt[p][v], b4[q][v], acc[p][q], 0, 0, 0);
             }
         }
