@@ -25,17 +25,17 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "bf16": 2500.0}   # MI355X dense MFMA TFLOP/s
 HBM_PEAK = 8000.0                        # GB/s
-# HBM traffic of one FP64 H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the launches of one call, scaled by the factors of
-# a 1 GiB device copy in the same runs (profiles/hpsi_fp64_L24_M1024_kernel_trace.md). Valid for that
-# workload and these kernels only.
-FP64_TRAFFIC_L24_M1024 = {"fetch_bytes": 22901.0 * 2**20, "write_bytes": 1069.7 * 2**20}
-# HBM traffic of one split H.psi call at the default workload (L=24 M=1024 sigma 1.5 seed 1), from
-# rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE over the k_pack_xt / k_zero_lds / k_hpsi_lds /
-# k_hpsi_small / k_reduce_lds launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0
-# (factors read off a 1 GiB device copy in the same runs); summary and commands in
-# profiles/hpsi_split_L24_M1024_kernel_trace.md. Valid for that workload and these kernels only.
-SPLIT_TRAFFIC_L24_M1024 = {"fetch_bytes": 15306.2 * 2**20, "write_bytes": 376.0 * 2**20}
+# HBM traffic of one H.psi call at L=24 M=1024 (seed 1), from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE
+# over the launches of one call, FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0 (factors read off a
+# 1 GiB device copy in the same runs). Valid for these operators and these kernels only; summaries and
+# commands in profiles/hpsi_L24_M1024_swept_kernel_trace.md and
+# profiles/hpsi_{fp64,split}_L24_M1024_synthetic_kernel_trace.md.
+TRAFFIC_L24_M1024 = {
+    "synthetic": {"fp64": {"fetch_bytes": 22901.0 * 2**20, "write_bytes": 1069.7 * 2**20},
+                  "split": {"fetch_bytes": 15306.2 * 2**20, "write_bytes": 376.0 * 2**20}},
+    "swept": {"fp64": {"fetch_bytes": 21284.1 * 2**20, "write_bytes": 3280.9 * 2**20},
+              "split": {"fetch_bytes": 16600.9 * 2**20, "write_bytes": 5931.8 * 2**20}},
+}
 
 
 def log(*a):
@@ -63,6 +63,16 @@ def main():
     ap.add_argument("--pairs", type=int, default=1000,
                     help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
+    ap.add_argument("--operators", choices=["synthetic", "swept"], default="swept",
+                    help="precision workload: synthetic block operators (sector sizes from the sigma model) or "
+                         "the blocks that two-site sweeps (dmrg_sweep) over random integrals leave at the middle bond")
+    ap.add_argument("--sweep-m", type=str, default="256,1024",
+                    help="swept operators: bond dimension of each sweep (the last is the measured M)")
+    ap.add_argument("--sweep-tol", type=float, default=1e-5, help="swept operators: Davidson tolerance per bond")
+    ap.add_argument("--save-swept", type=str, default=None,
+                    help="swept operators: also write the swept blocks to this .npz file")
+    ap.add_argument("--load-swept", type=str, default=None,
+                    help="swept operators: read the blocks from a --save-swept file instead of sweeping")
     ap.add_argument("--profile-kernels", action="store_true",
                     help="profiling run: 3 H.psi calls per precision and a plain device copy of 1 GiB "
                          "(calibration of the traffic counters); prints per-call event timings")
@@ -89,8 +99,16 @@ def main():
     L, M = args.L, args.M
     na = nb = L // 2
     t0 = time.time()
-    h, eri, left, right, site = synthetic_problem(L, na, nb, M, args.sigma, args.seed)
-    log(f"[bench] inputs {time.time() - t0:.1f}s; building operator (L={L}, M={M}, sigma={args.sigma})")
+    sweep_info = None
+    if args.operators == "swept":
+        h, eri, left, right, site, sweep_info = swept_problem(args, L, na, nb)
+        M = int(max(left.dim.sum(), right.dim.sum()))
+        ops_desc = (f"swept block operators (dmrg_sweep, M per sweep {args.sweep_m}, random integrals seed "
+                    f"{args.seed})")
+    else:
+        h, eri, left, right, site = synthetic_problem(L, na, nb, M, args.sigma, args.seed)
+        ops_desc = f"synthetic block operators sigma={args.sigma}"
+    log(f"[bench] inputs {time.time() - t0:.1f}s; building operator (L={L}, M={M}, {ops_desc})")
     t0 = time.time()
     stream = torch.cuda.current_stream()
     hop = dm.Hop(h, eri, left, right, na, nb, site, device=0, want_split=True, stream=stream)
@@ -104,6 +122,8 @@ def main():
     y64 = torch.empty_like(x)
     ysp = torch.empty_like(x)
     if args.profile_kernels:
+        if sweep_info:
+            print(json.dumps({"sweep": sweep_info}), flush=True)
         return profile_kernels(args, hop, st, x, y64, ysp, stream)
 
     # --- kernel timing with events on the launch stream
@@ -168,9 +188,13 @@ def main():
 
     # --- roofline of the dominant kernel: the FP64 H.psi launch sequence (the headline precision);
     #     the split sequence's figures follow under "split_roofline"
-    default_shape = (L, M, args.sigma, args.seed) == (24, 1024, 1.5, 1)
+    if args.operators == "swept":
+        default_shape = (L, args.sweep_m, args.sweep_tol, args.seed) == (24, "256,1024", 1e-5, 1)
+    else:
+        default_shape = (L, M, args.sigma, args.seed) == (24, 1024, 1.5, 1)
+    traffic = TRAFFIC_L24_M1024[args.operators] if default_shape else None
     achieved = st["flops"] / t64 / 1e12
-    tr64 = FP64_TRAFFIC_L24_M1024 if default_shape else None
+    tr64 = traffic["fp64"] if traffic else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp64"], 4),
                 "traffic": (tr64["fetch_bytes"] + tr64["write_bytes"]) if tr64 else None,
@@ -179,11 +203,11 @@ def main():
                 "algorithmic_bytes": st["bytes"],
                 "hbm_frac": round(st["bytes"] / t64 / 1e9 / HBM_PEAK, 4)}
     achieved_sp = st["flops"] / tsp / 1e12
-    traffic_sp = (SPLIT_TRAFFIC_L24_M1024["fetch_bytes"] + SPLIT_TRAFFIC_L24_M1024["write_bytes"]) \
-        if default_shape else None
+    traffic_sp = (traffic["split"]["fetch_bytes"] + traffic["split"]["write_bytes"]) if traffic else None
     split_roofline = {"bound": "mfma", "achieved": round(achieved_sp, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
                       "frac": round(achieved_sp / PEAK["bf16"], 5), "traffic": traffic_sp,
-                      "kernel": "split H.psi sequence (k_hpsi_lds + k_hpsi_small + k_reduce_lds)",
+                      "kernel": "split H.psi sequence (k_hpsi_lds, k_hpsi_small, k_big_t + k_big_y above 96 x 96, "
+                                "k_pack_xt, k_reduce_lds, k_reduce_big)",
                       "mfma_products_per_flop": 3,
                       "algorithmic_bytes": st["bytes"] / 2,
                       "hbm_frac": round(st["bytes"] / 2 / tsp / 1e9 / HBM_PEAK, 4)}
@@ -199,7 +223,7 @@ def main():
         "ms_per_step": round(s_iter_64 * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"two-site H.psi + Davidson iteration, L={L} N={na + nb} ({na},{nb}) M={M} "
-                               f"middle bond, synthetic block operators sigma={args.sigma}",
+                               f"middle bond, {ops_desc}",
                    "n_coeff": n, "psi_blocks": hop.n_blocks, "n_alpha": st["n_alpha"], "n_tasks": st["n_tasks"],
                    "flops_per_matvec": st["flops"]},
         "fp64": {"tflops": round(value_64, 3), "ms_per_iter": round(s_iter_64 * 1e3, 3),
@@ -213,6 +237,7 @@ def main():
         "roofline": roofline,
         "split_roofline": split_roofline,
         "cpu_baseline": cpu,
+        **({"sweep": sweep_info} if sweep_info else {}),
     }
     print(json.dumps(out), flush=True)
 
@@ -504,6 +529,99 @@ def bench_renorm(args):
                            "blocks": int(len(dims))},
             "renormalize_step": steps}
     print(json.dumps(line), flush=True)
+
+
+def swept_problem(args, L, na, nb):
+    """Blocks of the middle bond after two-site sweeps over random integrals (dmrg_sweep, split
+    precision with an FP64 polish per bond), and a fit of the sigma of the synthetic sector-size model
+    to their sector dimensions."""
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_integrals
+    from dmrg_inputs.synthetic import sector_dims
+    h, eri = random_integrals(L, args.seed)
+    ms = [int(v) for v in args.sweep_m.split(",")]
+    site = L // 2 - 1
+    t = time.perf_counter()
+    if args.load_swept:
+        left, right, r = load_blocks(args.load_swept)
+    else:
+        r = dm.sweep(h, eri, na, nb, ms, m_warmup=ms[0], tol=args.sweep_tol, max_iter=400, max_sub=24,
+                     precision=dm.PREC_SPLIT2, fp64_polish=True, split_tol=3e-4, seed=args.seed, keep_site=site,
+                     verbose=True)
+        left, right = r["left"], r["right"]
+        if args.save_swept:
+            save_blocks(args.save_swept, left, right, r)
+    secs = time.perf_counter() - t
+    log(f"[bench] sweep {secs:.1f}s, {len(r['energies'])} solves, final E {r['energy']:.10f}, "
+        f"kept {left.dim.sum()} x {right.dim.sum()}, largest sectors {left.dim.max()} / {right.dim.max()}")
+
+    def fit_sigma(blk, k):
+        dims = {tuple(int(v) for v in q): int(d) for q, d in zip(blk.qn, blk.dim)}
+        m = int(blk.dim.sum())
+        best = None
+        for sg in np.arange(0.3, 4.01, 0.05):
+            qn, dd = sector_dims(k, na, nb, L, m, float(sg))
+            model = {tuple(int(v) for v in q): int(d) for q, d in zip(qn, dd)}
+            keys = set(dims) | set(model)
+            err = sum((dims.get(q, 0) - model.get(q, 0)) ** 2 for q in keys)
+            if best is None or err < best[1]:
+                best = (float(sg), err)
+        return round(best[0], 2), round(float(np.sqrt(best[1] / max(1, len(dims)))), 1)
+
+    sl, rms_l = fit_sigma(left, site)
+    sr, rms_r = fit_sigma(right, L - site - 2)
+    info = {"seconds": round(secs, 1), "m_per_sweep": ms, "solves": len(r["energies"]),
+            "final_energy": r["energy"], "not_converged": r["n_not_converged"],
+            "max_discarded_last_sweep": float(np.max(r["discarded"][-(2 * L - 4):])),
+            "left": {"kept": int(left.dim.sum()), "sectors": int(len(left.dim)), "largest": int(left.dim.max()),
+                     "fitted_sigma": sl, "fit_rms_states": rms_l,
+                     "qn_dims": [[int(q[0]), int(q[1]), int(d)] for q, d in zip(left.qn, left.dim)]},
+            "right": {"kept": int(right.dim.sum()), "sectors": int(len(right.dim)), "largest": int(right.dim.max()),
+                      "fitted_sigma": sr, "fit_rms_states": rms_r,
+                      "qn_dims": [[int(q[0]), int(q[1]), int(d)] for q, d in zip(right.qn, right.dim)]}}
+    log(f"[bench] sector-model fit: sigma left {sl} (rms {rms_l} states), right {sr} (rms {rms_r})")
+    return h, eri, left, right, site, info
+
+
+def save_blocks(path, left, right, r):
+    """The swept blocks (dmrg_inputs Blocks) and the sweep's summary in one .npz (no pickled objects)."""
+    arrays = {"energies": np.asarray(r["energies"]), "discarded": np.asarray(r["discarded"]),
+              "summary": np.array([r["energy"], float(r["n_not_converged"])])}
+    for tag, b in (("left", left), ("right", right)):
+        arrays[f"{tag}_orbitals"] = np.asarray(b.orbitals, dtype=np.int32)
+        arrays[f"{tag}_qn"], arrays[f"{tag}_dim"] = np.asarray(b.qn), np.asarray(b.dim)
+        head, data = [], []
+        kinds = "HCSUABPQ"
+        for op in b.ops:
+            for (so, si), m in op.blocks.items():
+                head.append((kinds.index(op.kind), op.i0, op.i1, so, si))
+                data.append(np.asarray(m, dtype=np.float64).ravel())
+            head.append((kinds.index(op.kind), op.i0, op.i1, -1, -1))        # end of the operator
+        arrays[f"{tag}_head"] = np.array(head, dtype=np.int32)
+        arrays[f"{tag}_data"] = np.concatenate(data) if data else np.zeros(0)
+    np.savez(path, **arrays)
+
+
+def load_blocks(path):
+    from dmrg_inputs.blocks import Block, Op
+    z = np.load(path)
+    out = []
+    for tag in ("left", "right"):
+        dim = z[f"{tag}_dim"]
+        data, pos, blocks, ops = z[f"{tag}_data"], 0, {}, []
+        for kind, i0, i1, so, si in z[f"{tag}_head"]:
+            if so < 0:
+                ops.append(Op("HCSUABPQ"[kind], int(i0), int(i1), blocks))
+                blocks = {}
+                continue
+            n = int(dim[so]) * int(dim[si])
+            blocks[(int(so), int(si))] = data[pos:pos + n].reshape(int(dim[so]), int(dim[si]))
+            pos += n
+        out.append(Block(side=tag, orbitals=tuple(int(v) for v in z[f"{tag}_orbitals"]), qn=z[f"{tag}_qn"], dim=dim,
+                         ops=ops))
+    r = {"energies": z["energies"], "discarded": z["discarded"], "energy": float(z["summary"][0]),
+         "n_not_converged": int(z["summary"][1])}
+    return out[0], out[1], r
 
 
 def _cpu_model():

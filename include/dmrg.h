@@ -411,6 +411,8 @@ typedef struct {
     int32_t        device;
     void*          stream;
     int32_t        verbose;        /* 1: one line per solve on stderr */
+    int32_t        keep_site;      /* 1 .. n_orb - 3: hand the blocks of the bond (keep_site, keep_site+1)
+                                      after the last sweep back in the result; 0: none */
 } dmrg_sweep_opts;
 
 typedef struct {
@@ -424,11 +426,16 @@ typedef struct {
     double   energy;               /* energy of the last solve */
     double   best_energy;          /* lowest energy of any solve */
     double   seconds;              /* wall time */
+    dmrg_block* left_block;        /* keep_site > 0: the left block (orbitals 0 .. keep_site - 1) and */
+    dmrg_block* right_block;       /* the right block (keep_site + 2 .. n_orb - 1) of that bond as the
+                                      last sweep left them (left from its forward pass, right from its
+                                      backward pass: the pair the last solve at that bond used); owned
+                                      by the caller (dmrg_block_free); NULL otherwise or on error */
 } dmrg_sweep_result;
 
 /* Run the warm-up and n_sweeps sweeps for `problem` (its site field is ignored). Returns
  * DMRG_NOT_CONVERGED when some Davidson solve reached max_iter (the sweep goes on with its best
- * pair), errors as the calls it makes. */
+ * pair), errors as the calls it makes; keep_site outside 0 .. n_orb - 3 is DMRG_ERR_ARG. */
 dmrg_status dmrg_sweep(const dmrg_problem* problem, const dmrg_sweep_opts* opts, dmrg_sweep_result* result);
 
 /* ---------------------------------------------------------------------------------------------

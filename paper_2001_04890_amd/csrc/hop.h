@@ -185,6 +185,7 @@ struct dmrg_hop {
     int tune_lds64_items = 32768;               // target number of its work items per H.psi
     int tune_lds64_small = 0;                   // 1: it also takes tasks whose source is one 32 x 32 tile
                                                 // (0: those run in the one-wave kernel)
+    int tune_lds64_w7 = 1;                      // 1: its 7-wavefront class held to 128 VGPRs (two per CU)
     dmrg::LdsPlan64 lplan64{};
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)

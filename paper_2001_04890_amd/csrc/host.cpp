@@ -1210,14 +1210,14 @@ void drop_graphs(dmrg_hop& H) {
     H.graphs.clear();
 }
 
-// Targets whose own or some source's padded dimension exceeds the 96-wide LDS stages.
-std::vector<char> large_targets(const dmrg_hop& H) {
+// Targets whose own or some source's dimension exceeds `limit` (the 96-wide LDS stages of the split
+// kernel; 112 for the FP64 LDS-staged kernel).
+std::vector<char> large_targets(const dmrg_hop& H, int limit = 96) {
     std::vector<int> smax(H.blk.size(), 0);
-    for (size_t j = 0; j < H.blk.size(); ++j) smax[j] = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
-    for (const auto& t : H.tasks)
-        smax[t.j] = std::max({smax[t.j], dmrg::ld_of(H.blk_ma[t.i]), dmrg::ld_of(H.blk_md[t.i])});
+    for (size_t j = 0; j < H.blk.size(); ++j) smax[j] = std::max(H.blk_ma[j], H.blk_md[j]);
+    for (const auto& t : H.tasks) smax[t.j] = std::max({smax[t.j], H.blk_ma[t.i], H.blk_md[t.i]});
     std::vector<char> big(H.blk.size(), 0);
-    for (size_t j = 0; j < H.blk.size(); ++j) big[j] = smax[j] > 96;
+    for (size_t j = 0; j < H.blk.size(); ++j) big[j] = smax[j] > limit;
     return big;
 }
 
@@ -1227,7 +1227,8 @@ std::vector<char> large_targets(const dmrg_hop& H) {
 // the FP64 MFMA rate it sustains (measured: two-pass ~0.65 of peak on its padded work, one-wavefront
 // ~0.3). mode 2: every target above the 96-wide LDS stages (as the split path).
 std::vector<char> fp64_big_targets(const dmrg_hop& H, int mode) {
-    std::vector<char> big = large_targets(H);
+    // with the LDS-staged kernel on, targets within its 112 x 112 tiles are its own
+    std::vector<char> big = large_targets(H, H.tune_lds64 ? 16 * dmrg::kLds64MaxTiles : 96);
     if (mode == 2) return big;
     auto up = [](double m, double q) { return std::ceil(m / q) * q; };
     std::vector<double> c_big(H.blk.size(), 0.0), c_one(H.blk.size(), 0.0);
@@ -1327,9 +1328,11 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
         while (k < H.tasks.size() && H.tasks[k].j == (int)j) ++k;
         if (k == kb || large[j]) continue;
         const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, tq = dmrg::rows_of(H.blk_md[j]) / 16;
-        if (nrt > dmrg::kLds64Waves || tq > 6) throw Error(DMRG_ERR_ARG, "internal: FP64 LDS target beyond 96 x 96");
+        constexpr int kMax = dmrg::kLds64MaxTiles;
+        if (nrt > kMax || tq > kMax) throw Error(DMRG_ERR_ARG, "internal: FP64 LDS target beyond 112 x 112");
+        const bool wide = nrt > 6 || tq > 6;      // the (7, 7, 7) class takes every task of the target
         const int qcls = tq <= 3 ? 0 : 1;
-        std::vector<dmrg::LTask64> v2, v6;
+        std::vector<dmrg::LTask64> v2, v6, v7;
         for (size_t t = kb; t < k; ++t) {
             const auto& ht = H.tasks[t];
             const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
@@ -1346,16 +1349,16 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
             L.pd16 = (int16_t)(pd / 16);
             L.ka16 = (int16_t)((H.blk_ma[ht.i] + 15) / 16);
             L.kd16 = (int16_t)((H.blk_md[ht.i] + 15) / 16);
-            if (L.pa16 > 6 || L.pd16 > 6 || L.x_off + (int64_t)pa * pd > psize)
-                throw Error(DMRG_ERR_ARG, "internal: FP64 LDS task beyond the 96-wide stages");
+            if (L.ka16 > kMax || L.kd16 > kMax || L.x_off + (int64_t)pa * pd > psize)
+                throw Error(DMRG_ERR_ARG, "internal: FP64 LDS task beyond 112-wide sources");
             check(L.a_off, nrt, L.pa16);
             check(L.b_off, tq, L.pd16);
-            (L.ka16 <= 2 ? v2 : v6).push_back(L);
+            (wide || L.ka16 > 6 ? v7 : L.ka16 <= 2 ? v2 : v6).push_back(L);
         }
-        for (int kc : {0, 1}) {
-            const auto& v = kc == 0 ? v2 : v6;
+        for (int kc : {0, 1, 2}) {
+            const auto& v = kc == 0 ? v2 : kc == 1 ? v6 : v7;
             if (v.empty()) continue;
-            Run R{(int)j, 2 * kc + qcls, tq, (int32_t)lt.size(), 0};
+            Run R{(int)j, kc == 2 ? 4 : 2 * kc + qcls, tq, (int32_t)lt.size(), 0};
             for (const auto& L : v) { lt.push_back(L); total += cost(L, tq); }
             R.te = (int32_t)lt.size();
             runs.push_back(R);
@@ -1406,9 +1409,9 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     });
     std::vector<dmrg::Item> items;
     items.reserve(its.size());
-    int cnt[dmrg::kLdsClasses] = {0};
+    int cnt[dmrg::kLds64Classes] = {0};
     for (const It& x : its) { items.push_back(x.item); cnt[x.cls]++; }
-    for (int c = 0; c < dmrg::kLdsClasses; ++c) H.lplan64.cls_begin[c + 1] = H.lplan64.cls_begin[c] + cnt[c];
+    for (int c = 0; c < dmrg::kLds64Classes; ++c) H.lplan64.cls_begin[c + 1] = H.lplan64.cls_begin[c] + cnt[c];
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::LTask64* d_lt = plan_alloc<dmrg::LTask64>(H, lt.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -1424,10 +1427,11 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     H.lplan64.partial = plan_alloc<double>(H, (size_t)std::max<int64_t>(part, 1));
     H.lplan64.partial_size = part;
     H.lplan64.n_items = (int)items.size();
+    H.lplan64.w7_min_waves = H.tune_lds64_w7 ? 4 : 1;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds64 plan] items %zu classes", items.size());
-            for (int c = 0; c < dmrg::kLdsClasses; ++c) std::fprintf(stderr, " %d", cnt[c]);
+            for (int c = 0; c < dmrg::kLds64Classes; ++c) std::fprintf(stderr, " %d", cnt[c]);
             std::fprintf(stderr, " reduces %zu partial %.1f MB\n", reds.size(), part * 8e-6);
         }
     HIPCHK(hipStreamSynchronize(s));
@@ -1453,7 +1457,7 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     }
     if (H.tune_lds64 || any_big) make_tiled_f64(H, s);
     if (H.tune_lds64) {
-        build_lds64_plan(H, s, large_targets(H), lds64);
+        build_lds64_plan(H, s, large_targets(H, 16 * dmrg::kLds64MaxTiles), lds64);
         for (char b : lds64) any_lds |= b != 0;
     }
     if (any_big || any_lds) {
@@ -1791,6 +1795,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64")) H->tune_lds64 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_ITEMS")) H->tune_lds64_items = std::max(64, std::atoi(e));
         if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS64_W7")) H->tune_lds64_w7 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
@@ -2073,6 +2078,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64 = hops[0]->tune_lds64;
         C->tune_lds64_items = hops[0]->tune_lds64_items;
         C->tune_lds64_small = hops[0]->tune_lds64_small;
+        C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
         C->tune_lds_w6 = hops[0]->tune_lds_w6;

@@ -1,8 +1,8 @@
 // LDS-staged FP64 sector GEMMs of Eq. dgemm (Section 2.2.1) for gfx950, on v_mfma_f64_16x16x4f64
 // with FP64 accumulation.
 //
-// One workgroup of six wavefronts owns a whole target psi block of at most 96 x 96 (every row and
-// column) and loops over a range of its tasks Y += f * A . X . B^T (sorted by source block); wave w
+// One workgroup of W wavefronts (6 or 7) owns a whole target psi block of at most 16 W x 16 W (every
+// row and column) and loops over a range of its tasks Y += f * A . X . B^T (sorted by source block); wave w
 // owns row tile w (waves past the target's rows only help with the copies). The tasks are cut into
 // steps, one per 16-wide column tile jc of the source (the tiles that hold data), and per step:
 //   GEMM1  T'(w, jc)^T = X^T(jc, :) . A(w, :)^T   A-operand: the X^T slice from LDS; B-operand: the
@@ -71,9 +71,11 @@ __device__ __forceinline__ TD load_td(const LTask64* __restrict__ p) {
 }  // namespace
 
 // KT: most k tiles (source rows in 16-wide tiles) of the item's tasks; QT: most column tiles of the
-// target.
-template <int KT, int QT>
-__global__ __launch_bounds__(kLds64Waves * 64) void k_hpsi_lds64(const Item* __restrict__ items,
+// target; W: wavefronts, at least the target's row tiles; MINW: wavefronts per SIMD the register
+// allocation must allow (4 holds the 7-wavefront class to 128 VGPRs, so that two of its workgroups
+// share a CU, at the price of a few spilled registers).
+template <int KT, int QT, int W, int MINW>
+__global__ __launch_bounds__(W * 64, MINW) void k_hpsi_lds64(const Item* __restrict__ items,
                                                                 const LTask64* __restrict__ tasks,
                                                                 const double* __restrict__ pool_t,
                                                                 const double* __restrict__ xt,
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(kLds64Waves * 64) void k_hpsi_lds64(const Item* __r
         double* d = lds + slot * SLOT;
         const double* xs = xt + T.x + (int64_t)jc * T.pa16 * kTileD;
         const int nx = 2 * T.ka16, n = nx + 2 * tq;
-        for (int h = wave; h < n; h += kLds64Waves) {
+        for (int h = wave; h < n; h += W) {
             const double* src;
             double* dst;
             if (h < nx) {
@@ -201,17 +203,22 @@ __global__ __launch_bounds__(kLds64Waves * 64) void k_hpsi_lds64(const Item* __r
 
 hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s) {
     if (P.n_items == 0) return hipSuccess;
-    for (int c = 0; c < kLdsClasses; ++c) {
+    for (int c = 0; c < kLds64Classes; ++c) {
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
         if (n <= 0) continue;
-        const dim3 grid(n), block(kLds64Waves * 64);
-#define DMRG_L64(KT_, QT_) \
-    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_>), grid, block, 0, s, P.items + b, P.tasks, pool_t, xt, y, P.partial)
+        const dim3 grid(n);
+#define DMRG_L64(KT_, QT_, W_, MINW_)                                                                        \
+    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_>), grid, dim3(W_ * 64), 0, s, P.items + b, P.tasks, pool_t, \
+                       xt, y, P.partial)
         switch (c) {
-            case 0: DMRG_L64(2, 3); break;
-            case 1: DMRG_L64(2, 6); break;
-            case 2: DMRG_L64(6, 3); break;
-            default: DMRG_L64(6, 6); break;
+            case 0: DMRG_L64(2, 3, 6, 1); break;
+            case 1: DMRG_L64(2, 6, 6, 1); break;
+            case 2: DMRG_L64(6, 3, 6, 1); break;
+            case 3: DMRG_L64(6, 6, 6, 1); break;
+            default:
+                if (P.w7_min_waves == 4) DMRG_L64(7, 7, 7, 4);
+                else DMRG_L64(7, 7, 7, 1);
+                break;
         }
 #undef DMRG_L64
     }

@@ -179,11 +179,14 @@ struct LdsPlan {
 };
 
 // Launch plan of the FP64 LDS-staged kernel (hpsi_lds64.hip): items (internal.h Item; r0 = c0 = 0)
-// each cover a whole target block of at most 96 x 96 and a range of its tasks, over the FP64 tiled
+// each cover a whole target block of at most 112 x 112 and a range of its tasks, over the FP64 tiled
 // pool (identity factors point at its identity blocks) and the tiled FP64 X^T of the packed input
-// (offsets in doubles). Launch class c = 2 (KT == 6) + (QT == 6): KT = 2 when every task of the item
-// has at most 32 source rows, else 6; QT = 3 for targets of at most 48 columns, else 6.
-constexpr int kLds64Waves = 6;          // wavefronts per workgroup: one per target row tile
+// (offsets in doubles). Launch classes (KT, QT, W): c = 2 (KT == 6) + (QT == 6) for targets of at most
+// 96 x 96 and sources of at most 96 rows (W = 6; KT = 2 when every task of the item has at most 32
+// source rows, else 6; QT = 3 for targets of at most 48 columns, else 6), c = 4 (7, 7, 7) for the
+// rest (a target or a source of 97 .. 112 rows or columns).
+constexpr int kLds64Classes = 5;
+constexpr int kLds64MaxTiles = 7;       // target rows / columns and source rows, in 16-wide tiles
 struct LTask64 {
     int64_t x_off, a_off, b_off;
     double  f;
@@ -197,10 +200,11 @@ struct LdsPlan64 {
     const Reduce* reduces = nullptr;    // device; one record per target cut into several items (its
     int n_reduces = 0;                  // items of both stage sizes), so one launch adds them all
     int red_chunks = 1;                 // 256-element chunks of the largest partial tile
-    int cls_begin[kLdsClasses + 1] = {0, 0, 0, 0, 0};
+    int cls_begin[kLds64Classes + 1] = {0, 0, 0, 0, 0, 0};
     double* partial = nullptr;          // device, partial tiles of one vector
     int64_t partial_size = 0;
     int n_items = 0;
+    int w7_min_waves = 1;               // 4: the (7, 7, 7) class held to 128 VGPRs (two workgroups per CU)
 };
 // y (one vector) += the plan's targets of f A X B^T; xt = that vector's tiled FP64 X^T
 // (launch_pack_xt64 with the FP64 packing geometry)

@@ -157,6 +157,9 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
         if (o->n_sweeps < 1 || !o->m_per_sweep || o->m_warmup < 1) throw Error(DMRG_ERR_ARG, "bad sweep schedule");
         for (int k = 0; k < o->n_sweeps; ++k)
             if (o->m_per_sweep[k] < 1) throw Error(DMRG_ERR_ARG, "bond dimensions must be >= 1");
+        res->left_block = res->right_block = nullptr;
+        if (o->keep_site < 0 || (o->keep_site > 0 && o->keep_site > L - 3))
+            throw Error(DMRG_ERR_ARG, "keep_site must be 0 (none) or 1 .. n_orb - 3");
         const double t0 = dmrg::now_seconds();
         hipStream_t s = (hipStream_t)o->stream;
         HIPCHK(hipSetDevice(o->device));
@@ -281,6 +284,14 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
         }
         hop.reset();
         HIPCHK(hipStreamSynchronize(s));
+        if (o->keep_site > 0) {
+            // left[keep_site]: last grown in the final forward pass; right[L - keep_site - 2]: in the
+            // final backward pass, before its solve at this bond
+            res->left_block = left[o->keep_site].p;
+            left[o->keep_site].p = nullptr;
+            res->right_block = right[L - o->keep_site - 2].p;
+            right[L - o->keep_site - 2].p = nullptr;
+        }
         res->n_solves = n_solves;
         res->best_energy = best;
         res->seconds = dmrg::now_seconds() - t0;

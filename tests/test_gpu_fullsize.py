@@ -1,7 +1,11 @@
-"""Full-size GPU parity: the benchmark's H.psi workload (L = 24, N = 24 (12, 12), M = 1024 middle
-bond, synthetic block operators sigma = 1.5, seed 1; 844 psi blocks, 3366 combinations), built and
-launched exactly as bench.py times it (eager dmrg_hpsi on the caller's stream, and the captured
-graph), checked on sampled output blocks that the oracle computes target by target.
+"""Full-size GPU parity: the benchmark's H.psi workloads at L = 24, N = 24 (12, 12), M = 1024, middle
+bond, built and launched exactly as bench.py times them (eager dmrg_hpsi on the caller's stream, and
+the captured graph), checked on sampled output blocks that the oracle computes target by target:
+
+* swept (the default workload): the blocks that two sweeps over random integrals (seed 1, M 256 then
+  1024, split precision with an FP64 polish, tolerance 1e-5) leave at the bond (11, 12); sectors up
+  to 107 states, so the FP64 LDS kernel's 7-wavefront class and the split two-pass path run;
+* synthetic: sector sizes from the sigma = 1.5 model, random operator values (844 psi blocks).
 
 Sample: the three largest blocks, the smallest, and four seeded random blocks. Bars: FP64 within
 1e-12 of the sample's max|y|, split element by element within its error bound
@@ -27,10 +31,26 @@ DEV = torch.device("cuda:0")
 L, NA, NB, M, SIGMA, SEED = 24, 12, 12, 1024, 1.5, 1
 
 
-@pytest.fixture(scope="module")
-def full():
-    h, eri, left, right, site = synthetic_problem(L, NA, NB, M, SIGMA, SEED)
-    print(f"[full] L={L} M={M}: building the GPU operator", flush=True)
+def swept_problem():
+    """The bench's default operators (bench.py swept_problem with its default options)."""
+    from dmrg_inputs import random_integrals
+    h, eri = random_integrals(L, SEED)
+    site = L // 2 - 1
+    r = lib_mod.sweep(h, eri, NA, NB, [256, 1024], m_warmup=256, tol=1e-5, max_iter=400, max_sub=24,
+                      precision=PREC_SPLIT2, fp64_polish=True, split_tol=3e-4, seed=SEED, keep_site=site)
+    print(f"[full] swept: {r['seconds']:.1f}s, E {r['energy']:.10f}, kept {r['left'].dim.sum()} x "
+          f"{r['right'].dim.sum()}, largest sectors {r['left'].dim.max()} / {r['right'].dim.max()}", flush=True)
+    return h, eri, r["left"], r["right"], site
+
+
+@pytest.fixture(scope="module", params=["swept", "synthetic"])
+def full(request):
+    if request.param == "swept":
+        print(f"[full] L={L} M={M}: sweeping", flush=True)
+        h, eri, left, right, site = swept_problem()
+    else:
+        h, eri, left, right, site = synthetic_problem(L, NA, NB, M, SIGMA, SEED)
+    print(f"[full] L={L} M={M} {request.param}: building the GPU operator", flush=True)
     stream = torch.cuda.current_stream()
     hop = Hop(h, eri, left, right, NA, NB, site, device=0, want_split=True, stream=stream)
     x = random_vector(hop.n_coeff, 7)

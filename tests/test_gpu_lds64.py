@@ -1,7 +1,7 @@
 """GPU parity of the FP64 LDS-staged H.psi kernel (hpsi_lds64.hip: targets whose own and source blocks
 fit the 96-wide stages) against the FP64 oracle, through the C-ABI.
 
-Problem: L = 14, M = 200, sigma = 0.6 (100 blocks, sectors of 1 .. 95 states): every target fits
+Problem 1: L = 14, M = 200, sigma = 0.6 (100 blocks, sectors of 1 .. 95 states): every target fits
 the 96 x 96 workgroup tile, targets of up to 3 and of 4 .. 6 column tiles, and most targets have
 sources of both k-tile bounds (at most 32 rows, and more), so their task lists run in two launch
 classes. Plan variants: the default; "cut" (cost bound at its floor: every long task list cut into
@@ -13,6 +13,11 @@ and the kernel switched off (every target on the one-wavefront kernel). The plan
 launch classes and reductions each variant produced, so the test checks that the paths it means to
 cover were taken. Bars: FP64 within 1e-12 of max|y| against the oracle on every element, plans
 within 1e-13 of each other, every plan deterministic bit for bit.
+
+Problem 2: L = 14, M = 240, sigma = 0.6 (sectors up to 111 states: seven row and column tiles, the
+last one ragged) for the 7-wavefront class, which takes every target with a dimension above 96 (and
+the tasks of other targets whose source has more than 96 rows); held to 128 VGPRs (two workgroups per
+CU, the default), without that cap, and cut into many items.
 """
 import os
 import re
@@ -41,7 +46,7 @@ VARIANTS = {
     "whole": {"DMRG_LDS64_ITEMS": "64", "DMRG_LDS64_SMALL": "1"},
     "off": {"DMRG_LDS64": "0"},
 }
-TRACE = re.compile(r"\[dmrg lds64 plan\] items (\d+) classes (\d+) (\d+) (\d+) (\d+) reduces (\d+)")
+TRACE = re.compile(r"\[dmrg lds64 plan\] items (\d+) classes (\d+) (\d+) (\d+) (\d+) (\d+) reduces (\d+)")
 
 
 @pytest.fixture(scope="module")
@@ -53,9 +58,9 @@ def problem():
     return p, x, oh.apply(x)
 
 
-def build(p, variant, capfd):
+def build(p, variant, capfd, variants=VARIANTS):
     h, eri, left, right, na, nb, site = p
-    env = dict(VARIANTS[variant], DMRG_PLAN_TRACE="1")
+    env = dict(variants[variant], DMRG_PLAN_TRACE="1")
     old = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -89,7 +94,8 @@ def test_lds64_matches_oracle(problem, variant, capfd):
     if variant == "off":
         assert plan is None
     else:
-        items, k2q3, k2q6, k6q3, k6q6, reduces = plan
+        items, k2q3, k2q6, k6q3, k6q6, k7, reduces = plan
+        assert k7 == 0
         assert items > 0
         if variant != "default":
             assert k2q3 + k2q6 > 0 and k6q3 + k6q6 > 0, "sources of both k-tile bounds"
@@ -108,3 +114,34 @@ def test_lds64_plans_agree(problem, capfd):
     ys = {v: run(build(p, v, capfd)[0], x) for v in ("cut", "whole", "off")}
     assert rel_err(ys["cut"], ys["whole"]) < 1e-13
     assert rel_err(ys["cut"], ys["off"]) < 1e-13
+
+
+VARIANTS7 = {
+    "default": {},
+    "w7_uncapped": {"DMRG_LDS64_W7": "0"},
+    "cut": {"DMRG_LDS64_ITEMS": "100000000"},
+}
+
+
+@pytest.fixture(scope="module")
+def problem112():
+    p = synth(14, 240, 0.6, 5)
+    print("[lds64] L=14 M=240: oracle", flush=True)
+    oh = OracleHop(*p)
+    x = random_vector(oh.layout.size, 62)
+    return p, x, oh.apply(x)
+
+
+@pytest.mark.parametrize("variant", sorted(VARIANTS7))
+def test_lds64_seven_tile_class_matches_oracle(problem112, variant, capfd):
+    p, x, ref = problem112
+    hop, plan = build(p, variant, capfd, VARIANTS7)
+    items, k2q3, k2q6, k6q3, k6q6, k7, reduces = plan
+    assert k7 > 0, "7-wavefront class"
+    if variant == "cut":
+        assert reduces > 0
+    y = run(hop, x)
+    err = rel_err(y, ref)
+    print(f"[lds64] 112 {variant}: rel err {err:.2e}", flush=True)
+    assert err < FP64_TOL, variant
+    assert np.array_equal(run(hop, x), y), "deterministic"

@@ -5,6 +5,10 @@ brute-force FCI (the oracle's determinant CI from the same integrals).
   L = 10: every solve of the last sweep equals E_FCI within 1e-8 (Davidson tolerance 1e-9).
 * Truncated M at L = 8 (M = 6, 12, 24): the final energy is variational (>= E_FCI), decreases with M,
   and the last sweep does not end above the first one.
+* The blocks a sweep hands back (keep_site): a new H.psi handle built from them at that bond gives
+  the energy the last backward sweep found there (same blocks, so the same two-site problem), equal
+  to E_FCI at full M and above it (by at most the sweep's own error) when truncated; the blocks have
+  the orbitals, sectors and kept dimension of that bond. keep_site out of range is an argument error.
 """
 import numpy as np
 import pytest
@@ -54,3 +58,32 @@ def test_truncated_sweeps_are_variational_and_monotone_in_m(l8):
         finals.append(r["best_energy"])
     assert finals[0] >= finals[1] - 1e-9 >= finals[2] - 2e-9
     assert finals[0] > e_fci + 1e-6
+
+
+@pytest.mark.parametrize("M", [256, 6])
+def test_kept_bond_blocks_reproduce_the_sweep_energy(l8, M):
+    h, eri, e_fci = l8
+    L, site = 8, 3
+    r = lib_mod.sweep(h, eri, 4, 4, [M, M], m_warmup=M, tol=1e-10, max_iter=500, seed=3, keep_site=site)
+    left, right = r["left"], r["right"]
+    assert tuple(left.orbitals) == tuple(range(0, site)) and tuple(right.orbitals) == tuple(range(site + 2, L))
+    assert left.dim.sum() <= M and right.dim.sum() <= M
+    # the solve of the last (backward) sweep at this bond used exactly these blocks
+    idx = [i for i, s_ in enumerate(r["sites"]) if s_ == site][-1]
+    e_sweep = r["energies"][idx]
+    hop = lib_mod.Hop(h, eri, left, right, 4, 4, site, device=0)
+    x = torch.as_tensor(np.random.default_rng(5).standard_normal(hop.n_coeff), device="cuda:0")
+    dav = hop.davidson(x, tol=1e-10, max_iter=500)
+    print(f"[sweep] kept bond ({site},{site + 1}) M={M}: dims {left.dim.sum()} x {right.dim.sum()}, "
+          f"E {dav['energy']:.12f}, sweep {e_sweep:.12f}, FCI {e_fci:.12f}", flush=True)
+    assert abs(dav["energy"] - e_sweep) < 1e-8
+    if M == 256:
+        assert abs(dav["energy"] - e_fci) < 1e-8
+    else:
+        assert dav["energy"] > e_fci + 1e-7
+
+
+def test_keep_site_out_of_range_is_an_argument_error(l8):
+    h, eri, _ = l8
+    with pytest.raises(lib_mod.DmrgError):
+        lib_mod.sweep(h, eri, 4, 4, [4], m_warmup=4, keep_site=6)
