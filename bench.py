@@ -31,10 +31,10 @@ HBM_PEAK = 8000.0                        # GB/s
 # commands in profiles/hpsi_L24_M1024_swept_kernel_trace.md and
 # profiles/hpsi_{fp64,split}_L24_M1024_synthetic_kernel_trace.md.
 TRAFFIC_L24_M1024 = {
-    "synthetic": {"fp64": {"fetch_bytes": 22901.0 * 2**20, "write_bytes": 1069.7 * 2**20},
+    "synthetic": {"fp64": None,       # counters taken before single-tile sources moved into k_hpsi_lds64
                   "split": {"fetch_bytes": 15306.2 * 2**20, "write_bytes": 376.0 * 2**20}},
-    "swept": {"fp64": {"fetch_bytes": 21284.1 * 2**20, "write_bytes": 3280.9 * 2**20},
-              "split": {"fetch_bytes": 16600.9 * 2**20, "write_bytes": 5931.8 * 2**20}},
+    "swept": {"fp64": {"fetch_bytes": 21445.0 * 2**20, "write_bytes": 2858.2 * 2**20},
+              "split": {"fetch_bytes": 13754.6 * 2**20, "write_bytes": 3039.9 * 2**20}},
 }
 
 
@@ -195,6 +195,7 @@ def main():
     traffic = TRAFFIC_L24_M1024[args.operators] if default_shape else None
     achieved = st["flops"] / t64 / 1e12
     tr64 = traffic["fp64"] if traffic else None
+    trsp = traffic["split"] if traffic else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp64"], 4),
                 "traffic": (tr64["fetch_bytes"] + tr64["write_bytes"]) if tr64 else None,
@@ -203,7 +204,7 @@ def main():
                 "algorithmic_bytes": st["bytes"],
                 "hbm_frac": round(st["bytes"] / t64 / 1e9 / HBM_PEAK, 4)}
     achieved_sp = st["flops"] / tsp / 1e12
-    traffic_sp = (traffic["split"]["fetch_bytes"] + traffic["split"]["write_bytes"]) if traffic else None
+    traffic_sp = (trsp["fetch_bytes"] + trsp["write_bytes"]) if trsp else None
     split_roofline = {"bound": "mfma", "achieved": round(achieved_sp, 3), "peak": PEAK["bf16"], "unit": "TFLOP/s",
                       "frac": round(achieved_sp / PEAK["bf16"], 5), "traffic": traffic_sp,
                       "kernel": "split H.psi sequence (k_hpsi_lds, k_hpsi_small, k_big_t + k_big_y above 96 x 96, "

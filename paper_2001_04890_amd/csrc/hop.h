@@ -172,6 +172,9 @@ struct dmrg_hop {
     std::vector<dmrg::BigChunk> big_chunks;
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
+    int tune_split_task_route = 1;              // 1: a target within the split LDS stages keeps its tasks
+                                                // with sources that fit them; 0: any larger source sends
+                                                // the whole target to the two-pass path
     // FP64 two-pass path (hpsi_big64.hip) for the same large targets
     int tune_big64 = 1;                         // FP64 two-pass path: 0 off, 1 where cheaper, 2 every target above 96
     double* d_tiled64 = nullptr;                // FP64 tiled operators + identity blocks (made on first use)
@@ -183,7 +186,7 @@ struct dmrg_hop {
     // FP64 LDS-staged kernel (hpsi_lds64.hip) for the targets within the 96-wide stages
     int tune_lds64 = 1;                         // 0: those targets take the one-wave kernel
     int tune_lds64_items = 32768;               // target number of its work items per H.psi
-    int tune_lds64_small = 0;                   // 1: it also takes tasks whose source is one 32 x 32 tile
+    int tune_lds64_small = 1;                   // 1: it also takes tasks whose source is one 32 x 32 tile
                                                 // (0: those run in the one-wave kernel)
     int tune_lds64_w7 = 1;                      // 1: its 7-wavefront class held to 128 VGPRs (two per CU)
     dmrg::LdsPlan64 lplan64{};

@@ -784,10 +784,14 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
 // source order. Row-mode items cover the whole target (all rows and columns), task-mode items a row
 // block of one or two row tiles; each list is cut into items of bounded cost, and a target row block
 // covered by several items of one kind gets partial tiles that a reduction adds in item order.
-// Targets with larger blocks are flagged in `fallback` for the one-wave kernel.
-void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
+// Targets with larger blocks (own, or every source with tune_split_task_route = 0) are flagged in
+// `fallback`, and with them the tasks in `fb_task`: those the other paths (two-pass or one-wave) run.
+// With tune_split_task_route, a target within the stages keeps its tasks whose source fits them too
+// and only those with a larger source fall back, so one target can take both paths (each adds into y).
+void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std::vector<char>& fb_task) {
     const size_t nb = H.blk.size();
     fallback.assign(nb, 0);
+    fb_task.assign(H.tasks.size(), 0);
     std::vector<int64_t> pk_off(nb);
     std::vector<dmrg::PackBlock> packs;
     int64_t psize = 0;
@@ -817,17 +821,28 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
         size_t kb = k;
         while (k < H.tasks.size() && H.tasks[k].j == (int)j) ++k;
         if (k == kb) continue;
-        int smax = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
-        for (size_t t = kb; t < k; ++t) {
+        const int own = std::max(dmrg::ld_of(H.blk_ma[j]), dmrg::ld_of(H.blk_md[j]));
+        auto src_dim = [&](size_t t) {
             const int i = H.tasks[t].i;
-            smax = std::max({smax, dmrg::ld_of(H.blk_ma[i]), dmrg::ld_of(H.blk_md[i])});
+            return std::max(dmrg::ld_of(H.blk_ma[i]), dmrg::ld_of(H.blk_md[i]));
+        };
+        int smax = own;
+        for (size_t t = kb; t < k; ++t) smax = std::max(smax, src_dim(t));
+        if (own > 96 || (smax > 96 && !H.tune_split_task_route)) {
+            fallback[j] = 1;
+            for (size_t t = kb; t < k; ++t) fb_task[t] = 1;
+            continue;
         }
-        if (smax > 96) { fallback[j] = 1; continue; }
+        if (smax > 96) {                              // per-task routing: the larger sources fall back
+            fallback[j] = 1;
+            for (size_t t = kb; t < k; ++t) fb_task[t] = src_dim(t) > 96;
+        }
         const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16, tq = dmrg::rows_of(H.blk_md[j]) / 16;
         std::vector<dmrg::LTask> big, small;
         int big_s = 32;
         std::vector<size_t> order;
-        for (size_t t = kb; t < k; ++t) order.push_back(t);
+        for (size_t t = kb; t < k; ++t)
+            if (!fb_task[t]) order.push_back(t);
         if (H.tune_lds_task_order == 1)   // operator-pair order (same across targets) instead of source order
             std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) {
                 const auto &a = H.tasks[x], &b = H.tasks[y];
@@ -1045,7 +1060,9 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback) {
 // 128 T columns), consecutive groups packed into workgroups of about tune_big_stages1 k steps, and
 // pass 2 one item per (target, 8 row tiles, 8 column tiles, task range), the task lists cut into
 // items of about tune_big_stages k steps whose partial tiles a reduction adds in order.
-void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bool fp64) {
+void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bool fp64,
+                    const std::vector<char>* task_keep = nullptr) {
+    auto kept = [&](size_t k) { return !task_keep || (*task_keep)[k]; };
     const int unit = fp64 ? 16 : 32;                 // k-tile width
     const int64_t esc = fp64 ? 1 : 2;                // tiled-array elements per pool element
     const int64_t tile_el = fp64 ? 256 : dmrg::kTileU16;
@@ -1147,10 +1164,12 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
         const int nrt = dmrg::rows_of(H.blk_ma[j]) / 16;
         int64_t need = 0;
         for (size_t k = trange[j].first; k < trange[j].second; ++k)
-            need += (int64_t)nrt * (dmrg::ld_of(H.blk_md[H.tasks[k].i]) / unit) * tile_el;
+            if (kept(k)) need += (int64_t)nrt * (dmrg::ld_of(H.blk_md[H.tasks[k].i]) / unit) * tile_el;
+        if (need == 0) continue;                  // every task of the target runs elsewhere
         if (tsize > 0 && tsize + need > kBigTBudget) close_chunk();
         const int32_t b0 = (int32_t)t2.size();
         for (size_t k = trange[j].first; k < trange[j].second; ++k) {
+            if (!kept(k)) continue;
             const auto& ht = H.tasks[k];
             const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
             const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
@@ -1475,16 +1494,16 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     H.phases_fb.clear();
     H.n_fallback_targets = 0;
     if (!H.has_split) return;
-    std::vector<char> fb;
-    build_lds_plan(H, s, fb);
+    std::vector<char> fb, fb_task;
+    build_lds_plan(H, s, fb, fb_task);
     H.bplan = dmrg::BigPlan{};
     if (H.n_fallback_targets > 0) {
         if (H.tune_big) {
-            build_big_plan(H, s, fb, false);
+            build_big_plan(H, s, fb, false, &fb_task);
             H.n_fallback_targets = 0;
         } else {
             if (!H.d_hi) throw Error(DMRG_ERR_ARG, "internal: row-major split operators missing");
-            build_plan_core(H, s, &fb, true, H.plan_fb, H.launches_fb, H.phases_fb);
+            build_plan_core(H, s, &fb, true, H.plan_fb, H.launches_fb, H.phases_fb, &fb_task);
         }
     }
 }
@@ -1796,6 +1815,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64_ITEMS")) H->tune_lds64_items = std::max(64, std::atoi(e));
         if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_W7")) H->tune_lds64_w7 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_SPLIT_TASK_ROUTE")) H->tune_split_task_route = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
@@ -2079,6 +2099,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64_items = hops[0]->tune_lds64_items;
         C->tune_lds64_small = hops[0]->tune_lds64_small;
         C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
+        C->tune_split_task_route = hops[0]->tune_split_task_route;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
         C->tune_lds_w6 = hops[0]->tune_lds_w6;

@@ -8,7 +8,9 @@ Plan variants: every target above the LDS stages on the two-pass path in both pr
 by default the FP64 path takes it only where its cost model says it is cheaper); a cut plan of the
 same (16 MB T budget: several chunks; 4-step pass-1 workgroups: many groups per workgroup; 4-step
 pass-2 items: task lists cut into partial tiles that ordered reductions add); the default choice
-("auto"); and the large-block path switched off (one-wavefront kernels). Bars as for
+("auto"); the large-block path switched off (one-wavefront kernels); and "target_route": a target
+with any source above the stages sends all its tasks to the large-block path (by default only those
+tasks do, the rest of the target stays in the LDS-staged kernel), with the FP64 LDS kernel off. Bars as for
 every H.psi: FP64 within 1e-12 of max|y|, split element by element within its error bound
 (helpers.assert_split_bound); split plans that move FP32 run boundaries agree within 2e-6; every
 plan is deterministic bit for bit.
@@ -38,6 +40,7 @@ VARIANTS = {
     "cut": {"DMRG_BIG64": "2", "DMRG_BIG_STAGES": "4", "DMRG_BIG_STAGES1": "4", "DMRG_BIG_TBUDGET_MB": "16"},
     "auto": {},
     "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0"},
+    "target_route": {"DMRG_SPLIT_TASK_ROUTE": "0", "DMRG_LDS64": "0"},
 }
 
 
