@@ -33,8 +33,8 @@ HBM_PEAK = 8000.0                        # GB/s
 TRAFFIC_L24_M1024 = {
     "synthetic": {"fp64": None,       # counters taken before single-tile sources moved into k_hpsi_lds64
                   "split": {"fetch_bytes": 15306.2 * 2**20, "write_bytes": 376.0 * 2**20}},
-    "swept": {"fp64": {"fetch_bytes": 21445.0 * 2**20, "write_bytes": 2858.2 * 2**20},
-              "split": {"fetch_bytes": 13754.6 * 2**20, "write_bytes": 3039.9 * 2**20}},
+    "swept": {"fp64": {"fetch_bytes": 21710.4 * 2**20, "write_bytes": 2875.3 * 2**20},
+              "split": {"fetch_bytes": 13751.8 * 2**20, "write_bytes": 3039.9 * 2**20}},
 }
 
 

@@ -164,6 +164,8 @@ struct dmrg_hop {
     int tune_lds_split64 = 1;                   // 1: tasks fitting 64-wide stages run in the S = 64 classes
     int tune_lds_pf = 0x4;                      // row-mode classes with a prefetch wavefront (bit mask)
     int tune_lds_w6 = 0x8;                      // (S, 2) row-mode classes run as six one-row-tile wavefronts
+    int tune_lds_cw = 0;                        // row-mode classes with a copy wavefront (bit mask; measured
+                                                // slower for the split kernels, whose tasks are short)
     int tune_big = 1;                           // 1: targets above the LDS stages take the two-pass GEMM path
     int tune_big_stages = 64;                   // pass-2 item size in 32-wide k steps
     int tune_big_stages1 = 16;                  // pass-1 workgroup size in 32-wide k steps
@@ -189,6 +191,7 @@ struct dmrg_hop {
     int tune_lds64_small = 1;                   // 1: it also takes tasks whose source is one 32 x 32 tile
                                                 // (0: those run in the one-wave kernel)
     int tune_lds64_w7 = 1;                      // 1: its 7-wavefront class held to 128 VGPRs (two per CU)
+    int tune_lds64_cw = 1;                      // 1: a copy wavefront per workgroup issues every LDS copy
     dmrg::LdsPlan64 lplan64{};
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)

@@ -1041,6 +1041,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
     H.lplan.xt = plan_alloc<uint16_t>(H, (size_t)2 * psize * H.vec_step);
     H.lplan.prefetch_mask = H.tune_lds_pf;
     H.lplan.six_wave_mask = H.tune_lds_w6;
+    H.lplan.copy_wave_mask = H.tune_lds_cw;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds plan] items %zu row classes", items.size());
@@ -1447,6 +1448,7 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     H.lplan64.partial_size = part;
     H.lplan64.n_items = (int)items.size();
     H.lplan64.w7_min_waves = H.tune_lds64_w7 ? 4 : 1;
+    H.lplan64.copy_wave = H.tune_lds64_cw;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds64 plan] items %zu classes", items.size());
@@ -1815,6 +1817,8 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64_ITEMS")) H->tune_lds64_items = std::max(64, std::atoi(e));
         if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_W7")) H->tune_lds64_w7 = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS64_CW")) H->tune_lds64_cw = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS_CW")) H->tune_lds_cw = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_SPLIT_TASK_ROUTE")) H->tune_split_task_route = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
@@ -2099,10 +2103,12 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64_items = hops[0]->tune_lds64_items;
         C->tune_lds64_small = hops[0]->tune_lds64_small;
         C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
+        C->tune_lds64_cw = hops[0]->tune_lds64_cw;
         C->tune_split_task_route = hops[0]->tune_split_task_route;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
         C->tune_lds_w6 = hops[0]->tune_lds_w6;
+        C->tune_lds_cw = hops[0]->tune_lds_cw;
         build_plan(*C, s);
         *out = C;
         return DMRG_OK;

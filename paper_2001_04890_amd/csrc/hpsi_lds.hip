@@ -180,8 +180,11 @@ __global__ void k_pack_xt(const PackBlock* __restrict__ packs, const double* __r
 // compute waves one task later, find their lines in L2.
 // NW compute wavefronts (16 TP rows each): kLdsWaves, or 3 for the (96, 2) class with a prefetch
 // wavefront, whose targets have at most 96 rows, so the workgroup stays at four wavefronts.
-template <int S, int TP, int PF, int NW = kLdsWaves>
-__global__ __launch_bounds__(NW * 64 + PF * 64) void k_hpsi_lds(const Item* __restrict__ items,
+// CW = 1 (with PF = 0): the extra wavefront is a copy wavefront instead, which issues every LDS copy
+// of the item one task ahead, so the compute wavefronts never wait for copies in flight (the compiler
+// makes the first LDS read after a global-to-LDS copy wait for it, per wavefront).
+template <int S, int TP, int PF, int NW = kLdsWaves, int CW = 0>
+__global__ __launch_bounds__(NW * 64 + PF * 64 + CW * 64) void k_hpsi_lds(const Item* __restrict__ items,
                                                              const LTask* __restrict__ tasks,
                                                              const uint16_t* __restrict__ pool_t,
                                                              const uint16_t* __restrict__ xtall,
@@ -283,15 +286,53 @@ __global__ __launch_bounds__(NW * 64 + PF * 64) void k_hpsi_lds(const Item* __re
                     wave, lane);
     };
 
+    static_assert(CW == 0 || PF == 0, "the extra wavefront copies or prefetches, not both");
+    // per-task barrier: without a copy wavefront each wave waits for its own copies first; with one,
+    // the compute waves only read LDS (their reads are consumed before the barrier) and the copy
+    // wave waits for its copies
+    auto task_barrier = [&]() {
+        if constexpr (CW == 0) {
+            wait_vm();
+            __syncthreads();
+        } else {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        }
+    };
     int t = I.t_begin;
     TD T = load_td(tasks + t);
     int st = 0, xsl = 0;
     int64_t xcur = T.x;
     TD Tn = t + 1 < I.t_end ? load_td(tasks + t + 1) : T;   // descriptors are read one task ahead of use
-    stage(T, 0, 0, true);
+    if constexpr (CW == 1) {
+        if (wave == NW) {
+            auto stage1 = [&](const TD P, int st1, int xsl1, bool load_x) {
+                if (load_x) copy_to_lds<1>(xt + P.x, lds + xsl1 * XS, P.pd32 * P.pa32 * 256, 0, lane);
+                copy_to_lds<1>(pool_t + P.b + (int64_t)qt0 * P.pd32 * kTileU16, lds + 2 * XS + st1 * BS,
+                               tq * P.pd32 * 128, 0, lane);
+            };
+            stage1(T, 0, 0, true);
+            wait_vm();
+            task_barrier();
+            for (; t + 1 < I.t_end; ++t) {
+                const bool nx = Tn.x != xcur;
+                if (nx) xsl ^= 1;
+                stage1(Tn, st ^ 1, xsl, nx);          // that stage was last read before the previous barrier
+                wait_vm();
+                task_barrier();
+                st ^= 1;
+                xcur = Tn.x;
+                Tn = t + 2 < I.t_end ? load_td(tasks + t + 2) : Tn;
+            }
+            task_barrier();                           // the compute waves' barrier after their last task
+            return;
+        }
+    }
+    if constexpr (CW == 0) stage(T, 0, 0, true);
     load_a(T, ah, al);
-    wait_vm();
-    __syncthreads();
+    if constexpr (CW == 0) wait_vm();
+    task_barrier();
     int since_flush = 0;
     for (;;) {
         const bool has_next = t + 1 < I.t_end;
@@ -301,7 +342,7 @@ __global__ __launch_bounds__(NW * 64 + PF * 64) void k_hpsi_lds(const Item* __re
         if (has_next) {
             const bool nx = Tn.x != xcur;
             if (nx) xsl_n ^= 1;
-            stage(Tn, st ^ 1, xsl_n, nx);
+            if constexpr (CW == 0) stage(Tn, st ^ 1, xsl_n, nx);
             load_a(Tn, nh, nl);
         }
         if (active) {
@@ -359,8 +400,7 @@ __global__ __launch_bounds__(NW * 64 + PF * 64) void k_hpsi_lds(const Item* __re
                     }
             }
         }
-        wait_vm();
-        __syncthreads();
+        task_barrier();
         if (!has_next) break;
         ++t;
         T = Tn;
@@ -585,9 +625,29 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
         if (n <= 0) continue;
         const dim3 grid(n, nvec), block(kLdsWaves * 64), block_pf(kLdsWaves * 64 + 64);
-        const bool pf = (P.prefetch_mask >> c) & 1;
+        const bool cw = (P.copy_wave_mask >> c) & 1;     // a copy wavefront (replaces the prefetch one)
+        const bool pf = !cw && ((P.prefetch_mask >> c) & 1);
         const bool w6 = (P.six_wave_mask >> c) & 1;      // (S, 2) classes as six one-row-tile wavefronts
         const dim3 block6(6 * 64), block6_pf(7 * 64);
+        if (cw) {
+#define DMRG_LDS_CW(S_, TP_, NW_)                                                                          \
+    hipLaunchKernelGGL((k_hpsi_lds<S_, TP_, 0, NW_, 1>), grid, dim3((NW_ + 1) * 64), 0, s, P.items + b, P.tasks, \
+                       pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss)
+            switch (c) {
+                case 0: DMRG_LDS_CW(64, 1, kLdsWaves); break;
+                case 1:
+                    if (w6) DMRG_LDS_CW(64, 1, 6);
+                    else DMRG_LDS_CW(64, 2, kLdsWaves);
+                    break;
+                case 2: DMRG_LDS_CW(96, 1, kLdsWaves); break;
+                default:
+                    if (w6) DMRG_LDS_CW(96, 1, 6);
+                    else DMRG_LDS_CW(96, 2, kLdsWaves);
+                    break;
+            }
+#undef DMRG_LDS_CW
+            continue;
+        }
         switch (c) {
             case 0:
                 if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,

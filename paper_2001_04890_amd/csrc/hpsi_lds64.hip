@@ -74,8 +74,8 @@ __device__ __forceinline__ TD load_td(const LTask64* __restrict__ p) {
 // target; W: wavefronts, at least the target's row tiles; MINW: wavefronts per SIMD the register
 // allocation must allow (4 holds the 7-wavefront class to 128 VGPRs, so that two of its workgroups
 // share a CU, at the price of a few spilled registers).
-template <int KT, int QT, int W, int MINW>
-__global__ __launch_bounds__(W * 64, MINW) void k_hpsi_lds64(const Item* __restrict__ items,
+template <int KT, int QT, int W, int MINW, int CW>
+__global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* __restrict__ items,
                                                                 const LTask64* __restrict__ tasks,
                                                                 const double* __restrict__ pool_t,
                                                                 const double* __restrict__ xt,
@@ -109,12 +109,12 @@ __global__ __launch_bounds__(W * 64, MINW) void k_hpsi_lds64(const Item* __restr
         }
     };
     // copy the operands of step (T, jc) into a slot: X^T tiles (jc, kt < ka16), contiguous in the
-    // tiled X^T, then B tiles (q < tq, jc), one per target column tile; half tiles dealt to the waves
-    auto stage = [&](const TD& T, int jc, int slot) {
+    // tiled X^T, then B tiles (q < tq, jc), one per target column tile; half tiles h0, h0 + hs, ...
+    auto stage = [&](const TD& T, int jc, int slot, int h0, int hs) {
         double* d = lds + slot * SLOT;
         const double* xs = xt + T.x + (int64_t)jc * T.pa16 * kTileD;
         const int nx = 2 * T.ka16, n = nx + 2 * tq;
-        for (int h = wave; h < n; h += W) {
+        for (int h = h0; h < n; h += hs) {
             const double* src;
             double* dst;
             if (h < nx) {
@@ -129,20 +129,63 @@ __global__ __launch_bounds__(W * 64, MINW) void k_hpsi_lds64(const Item* __restr
         }
     };
 
+    // barrier of the step loop: CW = 0, every wave copies (waits for its copies, then the barrier);
+    // CW = 1, the compute waves only read LDS (whose values the MFMAs have consumed by then), so a
+    // bare barrier, while the copy wave waits for its copies before it
+    auto step_barrier = [&]() {
+        if constexpr (CW == 0) {
+            wait_vm();
+            __syncthreads();
+        } else {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_barrier();
+            asm volatile("" ::: "memory");
+        }
+    };
     int t = t_begin, jc = 0, slot = 0;
     TD T = load_td(tasks + t);
+    if constexpr (CW == 1) {
+        if (wave == W) {
+            // the copy wavefront: every copy of the item, one step ahead of the compute wavefronts,
+            // which then never wait for a copy in flight (the wait before an LDS read that the
+            // compiler puts after a global-to-LDS copy is per wavefront)
+            stage(T, 0, 0, 0, 1);
+            wait_vm();
+            step_barrier();
+            for (;;) {
+                const bool more_cols = jc + 1 < T.kd16;
+                const bool new_task = !more_cols && t + 1 < t_end;
+                if (!more_cols && !new_task) break;
+                const TD Tn = new_task ? load_td(tasks + t + 1) : T;
+                stage(Tn, more_cols ? jc + 1 : 0, slot ^ 1, 0, 1);   // last read before the previous barrier
+                wait_vm();
+                step_barrier();
+                if (more_cols) {
+                    ++jc;
+                } else {
+                    ++t;
+                    jc = 0;
+                    T = Tn;
+                }
+                slot ^= 1;
+            }
+            step_barrier();                           // the compute waves' barrier after their last step
+            return;
+        }
+    }
     f64x4 ar[KT];
-    stage(T, 0, 0);
+    if constexpr (CW == 0) stage(T, 0, 0, wave, W);
     load_a(T, ar);
-    wait_vm();
-    __syncthreads();
+    if constexpr (CW == 0) wait_vm();
+    step_barrier();
     for (;;) {
         const bool more_cols = jc + 1 < T.kd16;
         const bool new_task = !more_cols && t + 1 < t_end;
         const bool has_next = more_cols || new_task;
         TD Tn = T;
         if (new_task) Tn = load_td(tasks + t + 1);
-        if (has_next) stage(Tn, more_cols ? jc + 1 : 0, slot ^ 1);   // last read before the previous barrier
+        if constexpr (CW == 0)
+            if (has_next) stage(Tn, more_cols ? jc + 1 : 0, slot ^ 1, wave, W);   // last read before the previous barrier
         const double* xs = lds + slot * SLOT;
         const double* bs = xs + KT * kTileD;
         f64x4 tt = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -171,8 +214,7 @@ __global__ __launch_bounds__(W * 64, MINW) void k_hpsi_lds64(const Item* __restr
                 }
             }
         }
-        wait_vm();
-        __syncthreads();
+        step_barrier();
         if (!has_next) break;
         if (more_cols) {
             ++jc;
@@ -207,9 +249,14 @@ hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const dou
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
         if (n <= 0) continue;
         const dim3 grid(n);
-#define DMRG_L64(KT_, QT_, W_, MINW_)                                                                        \
-    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_>), grid, dim3(W_ * 64), 0, s, P.items + b, P.tasks, pool_t, \
-                       xt, y, P.partial)
+#define DMRG_L64C(KT_, QT_, W_, MINW_, CW_)                                                               \
+    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_, CW_>), grid, dim3((W_ + CW_) * 64), 0, s, P.items + b, \
+                       P.tasks, pool_t, xt, y, P.partial)
+#define DMRG_L64(KT_, QT_, W_, MINW_)                   \
+    do {                                                \
+        if (P.copy_wave) DMRG_L64C(KT_, QT_, W_, MINW_, 1); \
+        else DMRG_L64C(KT_, QT_, W_, MINW_, 0);             \
+    } while (0)
         switch (c) {
             case 0: DMRG_L64(2, 3, 6, 1); break;
             case 1: DMRG_L64(2, 6, 6, 1); break;
@@ -220,6 +267,7 @@ hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const dou
                 else DMRG_L64(7, 7, 7, 1);
                 break;
         }
+#undef DMRG_L64C
 #undef DMRG_L64
     }
     const hipError_t e = hipGetLastError();

@@ -172,6 +172,8 @@ struct LdsPlan {
                                         // prefetch wavefront: (96,1) (one workgroup per CU anyway);
                                         // the S = 64 classes would lose their second workgroup per
                                         // CU (measured slower); (96,2) runs 3 compute wavefronts then
+    int copy_wave_mask = 0;             // row-mode classes (bit c) with a copy wavefront that issues every
+                                        // LDS copy (no prefetch wavefront then)
     int six_wave_mask = 0x8;            // (S, 2) classes (bits 1, 3) run as six wavefronts of one row
                                         // tile each (targets of 65..96 rows) instead of four of two:
                                         // (96,2), whose one workgroup per CU then has two wavefronts on
@@ -205,6 +207,7 @@ struct LdsPlan64 {
     int64_t partial_size = 0;
     int n_items = 0;
     int w7_min_waves = 1;               // 4: the (7, 7, 7) class held to 128 VGPRs (two workgroups per CU)
+    int copy_wave = 1;                  // 1: one more wavefront per workgroup issues every LDS copy
 };
 // y (one vector) += the plan's targets of f A X B^T; xt = that vector's tiled FP64 X^T
 // (launch_pack_xt64 with the FP64 packing geometry)

@@ -10,7 +10,9 @@ same (16 MB T budget: several chunks; 4-step pass-1 workgroups: many groups per 
 pass-2 items: task lists cut into partial tiles that ordered reductions add); the default choice
 ("auto"); the large-block path switched off (one-wavefront kernels); and "target_route": a target
 with any source above the stages sends all its tasks to the large-block path (by default only those
-tasks do, the rest of the target stays in the LDS-staged kernel), with the FP64 LDS kernel off. Bars as for
+tasks do, the rest of the target stays in the LDS-staged kernel), with the FP64 LDS kernel off; and
+"copy_wave": the split row-mode classes with a copy wavefront (four and two row tiles per compute
+wavefront). Bars as for
 every H.psi: FP64 within 1e-12 of max|y|, split element by element within its error bound
 (helpers.assert_split_bound); split plans that move FP32 run boundaries agree within 2e-6; every
 plan is deterministic bit for bit.
@@ -41,6 +43,7 @@ VARIANTS = {
     "auto": {},
     "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0"},
     "target_route": {"DMRG_SPLIT_TASK_ROUTE": "0", "DMRG_LDS64": "0"},
+    "copy_wave": {"DMRG_LDS_CW": "15", "DMRG_LDS_W6": "0"},
 }
 
 
