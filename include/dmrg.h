@@ -366,6 +366,37 @@ dmrg_status dmrg_hop_trim(dmrg_hop* hop);
  * n_coeff). A handle from dmrg_build_blocks has one part. */
 dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first_coeff);
 
+/* Davidson for the lowest eigenpair of every part of a merged handle (dmrg_hop_combine; a plain
+ * handle is one part), all parts in lockstep with the whole iteration on the device (Sections 2.1,
+ * 2.2.1 for the method): the merged H.psi, per-part dot products, Gram-Schmidt (twice) and norms, the
+ * Rayleigh-Ritz step of every part (cyclic Jacobi on its k x k matrix in one workgroup), Ritz vector,
+ * residual, diagonal preconditioner, and the restart at max_sub (to the Ritz vector and the previous
+ * one), so no host synchronization is needed inside an iteration. With opts->use_graph = 1 the launch
+ * sequence of each subspace size is captured once as a hipGraph and replayed (the graphs live for the
+ * call); 0 launches the same sequence directly (same results bit for bit). The host reads the parts'
+ * status every 4 iterations and stops when none is active. A part stops when its residual norm is
+ * <= tol, or when its correction lies in its subspace (stalled). psi (device, n_coeff doubles): in,
+ * the start vectors (each part's segment nonzero), out, the Ritz vectors. Split precision with
+ * fp64_polish runs every part to max(split_tol, tol) with split matvecs, then restarts every part in
+ * FP64 from its Ritz vector. opts->precond must be DMRG_PRECOND_DIAG; max_sub 3 .. 64. Per-part
+ * results go into the caller's arrays (capacity >= n_parts, NULL to skip); status: 0 converged, 1 not
+ * converged in max_iter, 2 stalled. Returns DMRG_NOT_CONVERGED when some part did not converge,
+ * DMRG_ERR_NAN on a non-finite residual, errors as dmrg_davidson. Synchronizes the stream. */
+typedef struct {
+    int32_t  capacity;
+    double*  energy;
+    double*  resid;
+    int32_t* iters;
+    int32_t* status;
+    int32_t  n_parts;
+    int32_t  n_converged;
+    int32_t  matvecs;       /* merged H.psi launches */
+    int32_t  graphs;        /* iteration graphs captured */
+    double   t_total;       /* wall time of the call */
+} dmrg_dav_batch_result;
+dmrg_status dmrg_davidson_batch(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts, dmrg_dav_batch_result* result,
+                                void* stream);
+
 /* Autotuner of the H.psi launch plan for `precision`: times candidate settings on the device, `reps`
  * timed calls each, and keeps the fastest. FP64 (one-wavefront kernel): widest output tile (2, 4, 8
  * MFMA tiles of 16 columns) x work items (8k, 32k, 64k) x launch order (heaviest first / cache-aware).

@@ -62,6 +62,12 @@ class DavResult(C.Structure):
                 ("precond_fallback_iter", C.c_int32)]
 
 
+class DavBatchResult(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("energy", f64p), ("resid", f64p), ("iters", i32p), ("status", i32p),
+                ("n_parts", C.c_int32), ("n_converged", C.c_int32), ("matvecs", C.c_int32), ("graphs", C.c_int32),
+                ("t_total", C.c_double)]
+
+
 class SweepOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int32), ("m_per_sweep", i32p), ("m_warmup", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32), ("fp64_polish", C.c_int32),
@@ -123,6 +129,8 @@ lib.dmrg_sweep.argtypes = [C.POINTER(Problem), C.POINTER(SweepOpts), C.POINTER(S
 lib.dmrg_sweep.restype = C.c_int32
 lib.dmrg_davidson.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavResult), C.c_void_p]
 lib.dmrg_davidson.restype = C.c_int32
+lib.dmrg_davidson_batch.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(DavOpts), C.POINTER(DavBatchResult), C.c_void_p]
+lib.dmrg_davidson_batch.restype = C.c_int32
 lib.dmrg_hop_export_tasks.argtypes = [C.c_void_p, i64p, i32p, f64p, i64p, i32p, f64p]
 lib.dmrg_hop_export_tasks.restype = C.c_int32
 lib.dmrg_hop_combine.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]
@@ -514,6 +522,23 @@ class Hop:
         st = _check(lib.dmrg_davidson(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),
                                       _stream_ptr(stream)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
         return _dav_result(r, st)
+
+    def davidson_batch(self, psi, tol=1e-8, max_iter=200, max_sub=24, precision=PREC_FP64, fp64_polish=False,
+                       split_tol=1e-5, use_graph=True, stream=None):
+        """dmrg_davidson_batch: every part of this (merged) handle solved in lockstep on the device; psi
+        (device, n_coeff doubles) in: start vectors, out: Ritz vectors. Returns per-part arrays
+        (energy, resid, iters, status: 0 converged, 1 not converged, 2 stalled) and the run's counts."""
+        _device_f64(psi, self.device, "psi")
+        assert psi.numel() == self.n_coeff
+        P = len(self.part_coeff) - 1
+        o = _dav_opts(tol, max_iter, max_sub, precision, fp64_polish, split_tol, None, use_graph)
+        e, rr = np.zeros(P), np.zeros(P)
+        it, stt = np.zeros(P, dtype=np.int32), np.zeros(P, dtype=np.int32)
+        r = DavBatchResult(P, _ptr(e, C.c_double), _ptr(rr, C.c_double), _ptr(it, C.c_int32), _ptr(stt, C.c_int32))
+        st = _check(lib.dmrg_davidson_batch(self._h, C.c_void_p(psi.data_ptr()), C.byref(o), C.byref(r),
+                                            _stream_ptr(stream)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
+        return dict(energy=e, resid=rr, iters=it, status=stt, n_converged=r.n_converged, matvecs=r.matvecs,
+                    graphs=r.graphs, t_total=r.t_total, converged=st == DMRG_OK)
 
     def export_tasks(self):
         """Host-side task list and matrix definitions (introspection of the term generator)."""

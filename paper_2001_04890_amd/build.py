@@ -19,7 +19,7 @@ COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "hpsi_lds64.hip", "mlp.hip", "host.cpp", "mlp_host.cpp",
            "renorm_host.cpp", "davidson.cpp", "eigen.cpp", "noalloc.cpp", "grow.hip", "grow.cpp",
-           "sweep.cpp"]
+           "sweep.cpp", "davidson_batch.hip", "davidson_batch.cpp"]
 
 
 def _run(cmd):

@@ -105,6 +105,10 @@ dmrg_block* grow_block(const BlockIn& B, bool right, int site, const Integrals& 
                        int64_t data_len, const std::vector<int64_t>& op_off, bool padded, const std::vector<int>& kept,
                        const std::vector<double>& O, int device, hipStream_t s);
 
+// The launch sequence of one H.psi on stream s (arguments checked; no host synchronization, so it can
+// be captured into a graph).
+void hpsi_enqueue(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s);
+
 }  // namespace dmrg
 
 struct dmrg_hop {

@@ -1988,6 +1988,11 @@ void launch_hpsi_graph(dmrg_hop* H, const double* x, double* y, int32_t nvec, in
 
 }  // namespace
 
+void dmrg::hpsi_enqueue(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s) {
+    check_hpsi_args(H, x, y, nvec, precision);
+    enqueue_hpsi(H, x, y, nvec, precision, s);
+}
+
 extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision,
                                  void* stream) {
     g_err.clear();
