@@ -374,7 +374,9 @@ dmrg_status dmrg_hop_parts(const dmrg_hop* hop, int32_t* n_parts, int64_t* first
  * one), so no host synchronization is needed inside an iteration. With opts->use_graph = 1 the launch
  * sequence of each subspace size is captured once as a hipGraph and replayed (the graphs live for the
  * call); 0 launches the same sequence directly (same results bit for bit). The host reads the parts'
- * status every 4 iterations and stops when none is active. A part stops when its residual norm is
+ * status every 4 iterations and stops when none is active. Parts that have stopped cost no further
+ * work: their H.psi records and vector chunks are skipped (environment DMRG_BATCH_PART_MASK=0 runs
+ * their H.psi work to the end, with the same results). A part stops when its residual norm is
  * <= tol, or when its correction lies in its subspace (stalled). psi (device, n_coeff doubles): in,
  * the start vectors (each part's segment nonzero), out, the Ritz vectors. Split precision with
  * fp64_polish runs every part to max(split_tol, tol) with split matvecs, then restarts every part in

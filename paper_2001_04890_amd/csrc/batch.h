@@ -7,6 +7,9 @@
 // every part. Reductions run over a table of chunks, each inside one part, summed per part in chunk
 // order (deterministic). Per part p the device holds its status, its Rayleigh-Ritz matrix G_p
 // (K x K), its Ritz value and coefficient vector, and a row of dot products (kDotSlots).
+// Parts that have left the active set (converged, stalled, non-finite) are skipped by every kernel
+// below except bcopy with all_parts: their vectors and dot products keep stale values, and their
+// Ritz pair stays that of the iteration at which they left.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,16 +50,16 @@ struct BatchDev {
     int32_t* iters;            // n_parts: iterations while active
 };
 
-// dots[p][slot + j] = <V[j], x> over part p, j < nv (nv <= K + kDotTail - slot)
+// dots[p][slot + j] = <V[j], x> over part p, j < nv (nv <= K + kDotTail - slot), active parts
 hipError_t bdots(const BatchDev& B, const double* V, int nv, const double* x, int slot, hipStream_t s);
 // out = beta out + sum_j coef[p][j] V[j] on the active parts (coef rows of length K)
 hipError_t bcombine(const BatchDev& B, const double* V, int nv, const double* coef, double* out, double beta,
                     hipStream_t s);
-// x -= sum_j dots[p][j] V[j], j < nv, on every part
+// x -= sum_j dots[p][j] V[j], j < nv, on the active parts
 hipError_t bproject(const BatchDev& B, const double* V, int nv, double* x, hipStream_t s);
-// x /= sqrt(dots[p][K + slot]) where positive
+// x /= sqrt(dots[p][K + slot]) where positive, on the active parts
 hipError_t bscale(const BatchDev& B, double* x, int slot, hipStream_t s);
-// t = r / (theta_p - d) on active parts, 0 elsewhere
+// t = r / (theta_p - d) on the active parts
 hipError_t bprecond(const BatchDev& B, const double* r, const double* d, double* t, hipStream_t s);
 // dst = src on the parts whose status is active (all parts: all_parts)
 hipError_t bcopy(const BatchDev& B, const double* src, double* dst, bool all_parts, hipStream_t s);

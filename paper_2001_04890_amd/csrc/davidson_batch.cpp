@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <map>
 #include <vector>
 
@@ -32,6 +33,14 @@ struct Dev {
         HIPCHK(hipMemsetAsync(p, 0, std::max<size_t>(n, 1) * sizeof(T), s));   // not inside a graph
         return static_cast<T*>(p);
     }
+};
+
+// The parts' status array doubles as the part mask of the merged H.psi launches (see kPartActive),
+// so that parts that have converged cost no H.psi work; the handle drops it on every exit.
+static_assert(dmrg::kActive == dmrg::kPartActive, "part status and part mask use one active value");
+struct MaskGuard {
+    dmrg_hop* H;
+    ~MaskGuard() { H->d_active = nullptr; }
 };
 
 struct Graphs {
@@ -109,6 +118,9 @@ extern "C" dmrg_status dmrg_davidson_batch(dmrg_hop* H, double* psi, const dmrg_
         double* prev = d.get<double>(n, s);
         double* S = d.get<double>((size_t)4 * n, s);
         HIPCHK(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+        MaskGuard mask_guard{H};
+        const char* mk = std::getenv("DMRG_BATCH_PART_MASK");   // "0": every part's H.psi work runs to the end
+        if (!(mk && mk[0] == '0') && P <= 32767) H->d_active = B.status;   // pass-1 groups hold 16-bit part numbers
         int matvecs = 0, n_graphs = 0;
         int prec = o->precision;
         auto matvec = [&](const double* x, double* y, hipStream_t st) {
@@ -150,7 +162,7 @@ extern "C" dmrg_status dmrg_davidson_batch(dmrg_hop* H, double* psi, const dmrg_
             }
             HIPCHK(dmrg::bcopy(B, u, prev, false, st));
             double* vk = V + (size_t)kk * n;
-            HIPCHK(dmrg::bcopy(B, t, vk, true, st));
+            HIPCHK(dmrg::bcopy(B, t, vk, false, st));
             orth_norm(vk, kk, st);
             matvec(vk, W + (size_t)kk * n, st);
             HIPCHK(dmrg::bdots(B, V, kk + 1, W + (size_t)kk * n, 0, st));

@@ -26,6 +26,7 @@ __device__ __forceinline__ int status_of(const BatchDev& B, int p) { return B.st
 __global__ __launch_bounds__(256) void k_bdots(BatchDev B, const double* __restrict__ V, int nv,
                                                const double* __restrict__ x, int slot) {
     const BChunk c = B.chunks[blockIdx.x];
+    if (status_of(B, c.part) != kActive) return;
     const int j0 = blockIdx.y * kDotGroup;
     const int nj = min(kDotGroup, nv - j0);
     double acc[kDotGroup];
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(256) void k_bdots(BatchDev B, const double* __restr
 
 __global__ void k_bdots_finish(BatchDev B, int nv, int slot) {
     const int p = blockIdx.x;
+    if (status_of(B, p) != kActive) return;
     const int ld = B.K + kDotTail;
     const int c0 = B.part_chunk[p], c1 = B.part_chunk[p + 1];
     for (int j = threadIdx.x; j < nv; j += blockDim.x) {
@@ -80,6 +82,7 @@ __global__ __launch_bounds__(256) void k_bcombine(BatchDev B, const double* __re
 __global__ __launch_bounds__(256) void k_bproject(BatchDev B, const double* __restrict__ V, int nv,
                                                   double* __restrict__ x) {
     const BChunk c = B.chunks[blockIdx.x];
+    if (status_of(B, c.part) != kActive) return;
     __shared__ double cf[kRR];
     const int ld = B.K + kDotTail;
     for (int j = threadIdx.x; j < nv; j += blockDim.x) cf[j] = B.dots[(int64_t)c.part * ld + j];
@@ -93,6 +96,7 @@ __global__ __launch_bounds__(256) void k_bproject(BatchDev B, const double* __re
 
 __global__ __launch_bounds__(256) void k_bscale(BatchDev B, double* __restrict__ x, int slot) {
     const BChunk c = B.chunks[blockIdx.x];
+    if (status_of(B, c.part) != kActive) return;
     const double nn = B.dots[(int64_t)c.part * (B.K + kDotTail) + B.K + slot];
     if (!(nn > 0.0)) return;
     const double f = 1.0 / sqrt(nn);
@@ -102,10 +106,9 @@ __global__ __launch_bounds__(256) void k_bscale(BatchDev B, double* __restrict__
 __global__ __launch_bounds__(256) void k_bprecond(BatchDev B, const double* __restrict__ r,
                                                   const double* __restrict__ d, double* __restrict__ t) {
     const BChunk c = B.chunks[blockIdx.x];
-    const bool on = status_of(B, c.part) == kActive;
+    if (status_of(B, c.part) != kActive) return;
     const double th = B.theta[c.part];
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) {
-        if (!on) { t[i] = 0.0; continue; }
         double den = th - d[i];
         if (fabs(den) < 1e-8) den = den < 0.0 ? -1e-8 : 1e-8;
         t[i] = r[i] / den;

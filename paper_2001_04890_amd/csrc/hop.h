@@ -178,6 +178,8 @@ struct dmrg_hop {
     std::vector<dmrg::BigChunk> big_chunks;
     std::vector<std::pair<int32_t, int32_t>> big_t2_range;
     int tune_small_nq = 2;                      // task mode: least column-tile bound (2, 4 or 6)
+    int tune_part_items = 1;                    // merged handles: 1 item cost caps per merged problem (from
+                                                // its own total), 0 one cap from the whole handle's total
     int tune_split_task_route = 1;              // 1: a target within the split LDS stages keeps its tasks
                                                 // with sources that fit them; 0: any larger source sends
                                                 // the whole target to the two-pass path
@@ -204,6 +206,8 @@ struct dmrg_hop {
     int64_t n_alpha = 0;
     int n_parts = 1;                       // problems merged into this handle (dmrg_hop_combine)
     std::vector<int64_t> part_coeff;       // first coefficient of each merged problem (+ end)
+    const int32_t* d_active = nullptr;     // device part mask of every H.psi launch (null: all parts); set only
+                                           // inside dmrg_davidson_batch, whose part status array it is
     int n_items = 0;
     int64_t n_dev_tasks = 0;
     int tune_max_tq = 8;       // widest output tile, in 16-column MFMA tiles (1..8)

@@ -512,6 +512,31 @@ T* dev_alloc(dmrg_hop& H, size_t n) {
     return static_cast<T*>(p);
 }
 
+// Merged problem (dmrg_hop_combine) that holds coefficient `off`.
+int32_t part_of(const dmrg_hop& H, int64_t off) {
+    return (int32_t)(std::upper_bound(H.part_coeff.begin(), H.part_coeff.end(), off) - H.part_coeff.begin()) - 1;
+}
+// Tag work records (items, reductions) with the merged problem of their target, for part masks.
+template <class R>
+void tag_parts(const dmrg_hop& H, std::vector<R>& recs) {
+    for (auto& r : recs) r.part = H.n_parts > 1 ? part_of(H, r.y_off) : 0;
+}
+
+// Cost caps of work items. A plan cuts the task list of a tile into items of at most `cap` cost
+// units, with cap = total / (target item count). A merged handle sets the cap of each problem from
+// that problem's own total (tune_part_items), as its own handle would: when a part mask leaves only
+// a few problems running, their items are as fine as in their own plans and still fill the GPU.
+struct CostCaps {
+    const dmrg_hop& H;
+    std::vector<double> total;
+    explicit CostCaps(const dmrg_hop& h) : H(h), total(h.n_parts > 1 && h.tune_part_items ? h.n_parts : 1, 0.0) {}
+    size_t slot(int j) const { return total.size() > 1 ? (size_t)part_of(H, H.blk_off[j]) : 0; }
+    void add(int j, double c) { total[slot(j)] += c; }
+    double cap(int j, int items, double floor) const {
+        return std::max(total[slot(j)] / std::max(1, items), floor);
+    }
+};
+
 template <class T>
 T* plan_alloc(dmrg_hop& H, size_t n) {
     void* p = nullptr;
@@ -610,7 +635,8 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
     };
     struct Tile { int j, r0, c0, tp, tq; };
     std::vector<Tile> tiles;
-    double total = 0.0, max_task = 0.0;
+    double max_task = 0.0;
+    CostCaps caps(H);
     const int tile_cols = 16 * H.tune_max_tq;
     for (size_t j = 0; j < H.blk.size(); ++j) {
         if (only && !(*only)[j]) continue;
@@ -622,13 +648,12 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
                 int tq = (std::min(tile_cols, nj - c0) + 15) / 16;
                 for (int32_t t = trange[j * np].first; t < trange[j * np + np - 1].second; ++t) {
                     double tc = task_cost(dtasks[t], tp, tq);
-                    total += tc;
+                    caps.add((int)j, tc);
                     max_task = std::max(max_task, tc);
                 }
                 tiles.push_back({(int)j, r0, c0, tp, tq});
             }
     }
-    const double cmax = std::max({total / std::max(1, H.tune_items), max_task, 256.0});
     std::vector<dmrg::Item> all_items;
     std::vector<dmrg::Reduce> all_red;
     launches_out.clear();
@@ -648,6 +673,7 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
             std::vector<double> ccost;
             int32_t b = tr.first;
             double c = 0.0;
+            const double cmax = std::max(caps.cap(j, H.tune_items, 256.0), max_task);
             for (int32_t t = tr.first; t < tr.second; ++t) {
                 double tc = task_cost(dtasks[t], T.tp, T.tq);
                 if (c + tc > cmax && t > b) { chunks.push_back({b, t}); ccost.push_back(c); b = t; c = 0.0; }
@@ -748,6 +774,8 @@ void build_plan_core(dmrg_hop& H, hipStream_t s, const std::vector<char>* only, 
         if (e[0] == '1')
             std::fprintf(stderr, "[dmrg plan] phases %d items %zu launches %zu reduces %zu partial %.1f MB packed %.1f MB\n",
                          np, all_items.size(), H.launches.size(), all_red.size(), part_max * 8e-6, psize * 8e-6);
+    tag_parts(H, all_items);
+    tag_parts(H, all_red);
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, all_items.size());
     dmrg::Task* d_tasks = plan_alloc<dmrg::Task>(H, dtasks.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, all_red.size());
@@ -815,7 +843,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
         return 3.0 * L.pd32 * (2.0 * L.pa32 * tp + tq * tp) + 24.0 + (new_src ? 2.0 * L.pd32 * L.pa32 : 0.0);
     };
     auto small_cost = [](int nr, int tq) { return 3.0 * (2.0 * nr + nr * tq) + 24.0; };
-    double total = 0.0;
+    CostCaps caps(H);
     size_t k = 0;
     for (size_t j = 0; j < nb; ++j) {
         size_t kb = k;
@@ -875,7 +903,11 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
                 if (v.empty()) continue;
                 Run R{(int)j, S == 64 ? 0 : 1, (S == 64 ? 0 : 2) + (tp - 1), 0, 0, nrt, tq, (int32_t)lt.size(), 0};
                 int64_t px = -1;
-                for (const auto& L : v) { lt.push_back(L); total += row_cost(L, tp, tq, L.x_off != px); px = L.x_off; }
+                for (const auto& L : v) {
+                    lt.push_back(L);
+                    caps.add((int)j, row_cost(L, tp, tq, L.x_off != px));
+                    px = L.x_off;
+                }
                 R.te = (int32_t)lt.size();
                 runs.push_back(R);
             }
@@ -892,12 +924,11 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
                 for (int c = 0; c < tq; c += NQ) {
                     const int nr = std::min(NR, nrt - r), nq = std::min(NQ, tq - c);
                     runs.push_back({(int)j, 2, cls, 16 * r, 16 * c, nr, nq, tb, te});
-                    total += (te - tb) * small_cost(nr, nq);
+                    caps.add((int)j, (te - tb) * small_cost(nr, nq));
                 }
         }
     }
     H.lplan = dmrg::LdsPlan{};
-    const double cmax = std::max(total / std::max(1, H.tune_lds_items), 600.0);
     struct It { dmrg::Item item; double cost; int kind, cls; };
     std::vector<It> its;
     std::vector<dmrg::Reduce> reds_k[dmrg::kReduceKinds];
@@ -909,6 +940,7 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
         int32_t b = R.tb;
         double c = 0.0;
         int64_t px = -1;
+        const double cmax = caps.cap(R.j, H.tune_lds_items, 600.0);
         for (int32_t t = R.tb; t < R.te; ++t) {
             const double tc = R.kind < 2 ? row_cost(lt[t], tp, R.tq, lt[t].x_off != px || t == b) : small_cost(R.nr, R.tq);
             px = lt[t].x_off;
@@ -1020,6 +1052,8 @@ void build_lds_plan(dmrg_hop& H, hipStream_t s, std::vector<char>& fallback, std
         reds.insert(reds.end(), reds_k[kk].begin(), reds_k[kk].end());
         H.lplan.red_begin[kk + 1] = (int)reds.size();
     }
+    tag_parts(H, items);
+    tag_parts(H, reds);
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::LTask* d_lt = plan_alloc<dmrg::LTask>(H, lt.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -1111,7 +1145,11 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
             int c = 0;
             t1_ranges.push_back(g_first);
             for (int32_t gidx = g_first; gidx < (int32_t)t1.size(); ++gidx) {
-                if (c >= H.tune_big_stages1) { t1_ranges.push_back(gidx); c = 0; }
+                // a workgroup's groups belong to one merged problem (part masks skip whole workgroups)
+                if (c >= H.tune_big_stages1 || (gidx > g_first && t1[gidx].part != t1[gidx - 1].part)) {
+                    t1_ranges.push_back(gidx);
+                    c = 0;
+                }
                 c += t1[gidx].pa32;
             }
             cur.t1_end = (int)t1_ranges.size();   // workgroups [t1_begin, t1_end); ranges has one more entry
@@ -1169,6 +1207,8 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
         if (need == 0) continue;                  // every task of the target runs elsewhere
         if (tsize > 0 && tsize + need > kBigTBudget) close_chunk();
         const int32_t b0 = (int32_t)t2.size();
+        const size_t g_t1 = t1.size();
+        const int32_t part_j = H.n_parts > 1 ? part_of(H, H.blk_off[j]) : 0;
         for (size_t k = trange[j].first; k < trange[j].second; ++k) {
             if (!kept(k)) continue;
             const auto& ht = H.tasks[k];
@@ -1186,6 +1226,7 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
             t2.push_back({t_off, b_off, pd / unit, 0});
         }
         H.big_t2_range[j] = {b0, (int32_t)t2.size()};
+        for (size_t g = g_t1; g < t1.size(); ++g) t1[g].part = (int16_t)part_j;
         chunk_targets.push_back((int)j);
     }
     close_chunk();
@@ -1195,6 +1236,8 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
     HIPCHK(hipMemcpyAsync(d_t1r, t1_ranges.data(), t1_ranges.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     plan.t1_ranges = d_t1r;
     dmrg::BigT2* d_t2 = plan_alloc<dmrg::BigT2>(H, t2.size());
+    tag_parts(H, items);
+    tag_parts(H, reds);
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
     HIPCHK(hipMemcpyAsync(d_t1, t1.data(), t1.size() * sizeof(t1[0]), hipMemcpyHostToDevice, s));
@@ -1341,7 +1384,7 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     std::vector<dmrg::LTask64> lt;
     lt.reserve(H.tasks.size());
     std::vector<Run> runs;
-    double total = 0.0;
+    CostCaps caps(H);
     size_t k = 0;
     for (size_t j = 0; j < nb; ++j) {
         const size_t kb = k;
@@ -1379,13 +1422,15 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
             const auto& v = kc == 0 ? v2 : kc == 1 ? v6 : v7;
             if (v.empty()) continue;
             Run R{(int)j, kc == 2 ? 4 : 2 * kc + qcls, tq, (int32_t)lt.size(), 0};
-            for (const auto& L : v) { lt.push_back(L); total += cost(L, tq); }
+            for (const auto& L : v) {
+                lt.push_back(L);
+                caps.add((int)j, cost(L, tq));
+            }
             R.te = (int32_t)lt.size();
             runs.push_back(R);
         }
     }
     H.lplan64 = dmrg::LdsPlan64{};
-    const double cmax = std::max(total / std::max(1, H.tune_lds64_items), 200.0);
     struct It { dmrg::Item item; double cost; int cls; };
     std::vector<It> its;
     std::vector<dmrg::Reduce> reds;
@@ -1402,6 +1447,7 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
             const Run& R = runs[r];
             int32_t b = R.tb;
             double c = 0.0;
+            const double cmax = caps.cap(R.j, H.tune_lds64_items, 200.0);
             for (int32_t t = R.tb; t < R.te; ++t) {
                 const double tc = cost(lt[t], R.tq);
                 if (c + tc > cmax && t > b) { chunks.push_back({b, t, c, R.cls}); b = t; c = 0.0; }
@@ -1432,6 +1478,8 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     int cnt[dmrg::kLds64Classes] = {0};
     for (const It& x : its) { items.push_back(x.item); cnt[x.cls]++; }
     for (int c = 0; c < dmrg::kLds64Classes; ++c) H.lplan64.cls_begin[c + 1] = H.lplan64.cls_begin[c] + cnt[c];
+    tag_parts(H, items);
+    tag_parts(H, reds);
     dmrg::Item* d_items = plan_alloc<dmrg::Item>(H, items.size());
     dmrg::LTask64* d_lt = plan_alloc<dmrg::LTask64>(H, lt.size());
     dmrg::Reduce* d_red = plan_alloc<dmrg::Reduce>(H, reds.size());
@@ -1820,6 +1868,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64_CW")) H->tune_lds64_cw = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS_CW")) H->tune_lds_cw = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_SPLIT_TASK_ROUTE")) H->tune_split_task_route = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_PART_ITEMS")) H->tune_part_items = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_VEC_STEP")) H->vec_step = std::max(1, std::min(dmrg::kPartialVecs, std::atoi(e)));
         if (const char* e = std::getenv("DMRG_BIG_STAGES")) H->tune_big_stages = std::max(4, std::atoi(e));
         if (const char* e = std::getenv("DMRG_BIG_STAGES1")) H->tune_big_stages1 = std::max(4, std::atoi(e));
@@ -1934,28 +1983,29 @@ void check_hpsi_args(dmrg_hop* H, const double* x, double* y, int32_t nvec, int3
 // The launch sequence of one H.psi (no host synchronization, so it can be captured).
 void enqueue_hpsi(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision, hipStream_t s) {
     const int step = H->vec_step;   // packed-input and partial buffers hold this many vectors
+    const int32_t* act = H->d_active;
     for (int v0 = 0; v0 < nvec; v0 += step) {
         const int nv = std::min(step, nvec - v0);
         const double* xv = x + (int64_t)v0 * H->n_coeff;
         double* yv = y + (int64_t)v0 * H->n_coeff;
         if (precision == DMRG_PREC_FP64) {
             // zeroes y, then the one-wave targets
-            HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s));
+            HIPCHK(dmrg::launch_hpsi_f64(H->plan, H->d_pool, xv, yv, H->n_coeff, nv, s, act));
             const bool lds = H->lplan64.n_items > 0, big = H->bplan64.n_chunks > 0;
             for (int v = 0; v < nv && (lds || big); ++v) {
                 const double* x1 = xv + (int64_t)v * H->n_coeff;
                 double* y1 = yv + (int64_t)v * H->n_coeff;
                 HIPCHK(dmrg::launch_pack_xt64(H->plan.packs, H->plan.n_packs, x1, H->xt64, s));
-                if (lds) HIPCHK(dmrg::launch_hpsi_lds64(H->lplan64, H->d_tiled64, H->xt64, y1, s));
-                if (big) HIPCHK(dmrg::launch_hpsi_big64(H->bplan64, H->d_tiled64, nullptr, 0, x1, H->xt64, y1, s));
+                if (lds) HIPCHK(dmrg::launch_hpsi_lds64(H->lplan64, H->d_tiled64, H->xt64, y1, s, act));
+                if (big) HIPCHK(dmrg::launch_hpsi_big64(H->bplan64, H->d_tiled64, nullptr, 0, x1, H->xt64, y1, s, act));
             }
         } else {
-            HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s));
+            HIPCHK(dmrg::launch_hpsi_lds(H->lplan, H->d_tiled, xv, yv, H->n_coeff, nv, true, s, act));
             for (int v = 0; v < nv && H->bplan.n_chunks > 0; ++v)
                 HIPCHK(dmrg::launch_hpsi_big(H->bplan, H->d_tiled, H->lplan.xt + (int64_t)v * H->lplan.xt_size,
-                                             yv + (int64_t)v * H->n_coeff, s));
+                                             yv + (int64_t)v * H->n_coeff, s, act));
             if (H->n_fallback_targets > 0)
-                HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s));
+                HIPCHK(dmrg::launch_hpsi_split_acc(H->plan_fb, H->d_hi, H->d_lo, xv, yv, H->n_coeff, nv, s, act));
         }
     }
 }
@@ -2110,6 +2160,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
         C->tune_lds64_cw = hops[0]->tune_lds64_cw;
         C->tune_split_task_route = hops[0]->tune_split_task_route;
+        C->tune_part_items = hops[0]->tune_part_items;
         C->vec_step = hops[0]->vec_step;
         C->tune_lds_pf = hops[0]->tune_lds_pf;
         C->tune_lds_w6 = hops[0]->tune_lds_w6;

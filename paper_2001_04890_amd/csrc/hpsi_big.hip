@@ -74,9 +74,10 @@ __device__ __forceinline__ void copy_stage(const uint16_t* __restrict__ p_base, 
 // tiles x 4 column chunks) as one pipeline of k steps; at the end of a group its T tiles are stored.
 __global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, const int32_t* __restrict__ ranges,
                                                const uint16_t* __restrict__ pool_t, const uint16_t* __restrict__ xt,
-                                               uint16_t* __restrict__ tbuf) {
+                                               uint16_t* __restrict__ tbuf, const int32_t* __restrict__ mask) {
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kStageU16];
     const int g_begin = uni(ranges[blockIdx.x]), g_end = uni(ranges[blockIdx.x + 1]);
+    if (mask && mask[work[g_begin].part] != kPartActive) return;   // a workgroup's groups share one part
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wj = wave & 1, wr = wave >> 1;   // wave: chunks jb + 2 wj + {0,1}, row tiles rb + 4 wr + {0..3}
     struct G { int64_t x, a, t; float f; int pa32, pd32, nrt, rb, jb; };
@@ -189,9 +190,10 @@ __global__ __launch_bounds__(256) void k_big_t(const BigT1* __restrict__ work, c
 __global__ __launch_bounds__(256) void k_big_y(const Item* __restrict__ items, const BigT2* __restrict__ tasks,
                                                const uint16_t* __restrict__ pool_t,
                                                const uint16_t* __restrict__ tbuf, double* __restrict__ y,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, const int32_t* __restrict__ mask) {
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * kStageU16];
     const Item* ip = items + blockIdx.x;
+    if (mask && mask[ip->part] != kPartActive) return;
     const int64_t y_off = uni64(ip->y_off), part_off = uni64(ip->part_off);
     const int m_ap = uni(ip->m_ap), m_dp = uni(ip->m_dp), r0 = uni(ip->r0), c0 = uni(ip->c0);
     const int t_begin = uni(ip->t_begin), t_end = uni(ip->t_end);
@@ -299,8 +301,10 @@ __global__ __launch_bounds__(256) void k_big_y(const Item* __restrict__ items, c
     }
 }
 
-__global__ void k_reduce_big(const Reduce* __restrict__ red, const double* __restrict__ part, double* __restrict__ y) {
+__global__ void k_reduce_big(const Reduce* __restrict__ red, const double* __restrict__ part, double* __restrict__ y,
+                             const int32_t* __restrict__ mask) {
     const Reduce R = red[blockIdx.x];
+    if (mask && mask[R.part] != kPartActive) return;
     const int n = R.tm * R.tn;
     const int e = blockIdx.y * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -312,18 +316,19 @@ __global__ void k_reduce_big(const Reduce* __restrict__ red, const double* __res
     y[R.y_off + (int64_t)row * R.m_dp + col] += s;
 }
 
-hipError_t launch_hpsi_big(const BigPlan& P, const uint16_t* pool_t, const uint16_t* xt, double* y, hipStream_t s) {
+hipError_t launch_hpsi_big(const BigPlan& P, const uint16_t* pool_t, const uint16_t* xt, double* y, hipStream_t s,
+                           const int32_t* active) {
     for (int c = 0; c < P.n_chunks; ++c) {
         const BigChunk& C = P.chunks[c];
         if (C.t1_end > C.t1_begin)
             hipLaunchKernelGGL(k_big_t, dim3(C.t1_end - C.t1_begin), dim3(256), 0, s, P.t1, P.t1_ranges + C.t1_begin,
-                               pool_t, xt, P.tbuf);
+                               pool_t, xt, P.tbuf, active);
         if (C.item_end > C.item_begin)
             hipLaunchKernelGGL(k_big_y, dim3(C.item_end - C.item_begin), dim3(256), 0, s, P.items + C.item_begin, P.t2,
-                               pool_t, P.tbuf, y, P.partial);
+                               pool_t, P.tbuf, y, P.partial, active);
         if (C.red_end > C.red_begin)
             hipLaunchKernelGGL(k_reduce_big, dim3(C.red_end - C.red_begin, P.red_chunks), dim3(256), 0, s,
-                               P.reduces + C.red_begin, P.partial, y);
+                               P.reduces + C.red_begin, P.partial, y, active);
     }
     return hipGetLastError();
 }

@@ -98,9 +98,10 @@ __global__ void k_pack_xt64(const PackBlock* __restrict__ packs, const double* _
 // + {0..3}, row tiles rb + 4 wr + {0..3}: 16 accumulator tiles.
 __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work, const int32_t* __restrict__ ranges,
                                                  const double* __restrict__ pool_t, const double* __restrict__ xt,
-                                                 double* __restrict__ tbuf) {
+                                                 double* __restrict__ tbuf, const int32_t* __restrict__ mask) {
     __shared__ __attribute__((aligned(16))) double lds[2 * kStageD];
     const int g_begin = uni(ranges[blockIdx.x]), g_end = uni(ranges[blockIdx.x + 1]);
+    if (mask && mask[work[g_begin].part] != kPartActive) return;   // a workgroup's groups share one part
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wj = wave & 1, wr = wave >> 1;
     struct G { int64_t x, a, t; double f; int pa, pd, nrt, rb, jb; };
@@ -190,9 +191,11 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
 // ------------------------------------------------------------------ pass 2: Y += sum T B^T per tile
 __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items, const BigT2* __restrict__ tasks,
                                                  const double* __restrict__ pool_t, const double* __restrict__ tbuf,
-                                                 double* __restrict__ y, double* __restrict__ part) {
+                                                 double* __restrict__ y, double* __restrict__ part,
+                                                 const int32_t* __restrict__ mask) {
     __shared__ __attribute__((aligned(16))) double lds[2 * kStageD];
     const Item* ip = items + blockIdx.x;
+    if (mask && mask[ip->part] != kPartActive) return;
     const int64_t y_off = uni64(ip->y_off), part_off = uni64(ip->part_off);
     const int m_ap = uni(ip->m_ap), m_dp = uni(ip->m_dp), r0 = uni(ip->r0), c0 = uni(ip->c0);
     const int t_begin = uni(ip->t_begin), t_end = uni(ip->t_end);
@@ -291,8 +294,10 @@ __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items,
         }
 }
 
-__global__ void k_reduce_big64(const Reduce* __restrict__ red, const double* __restrict__ part, double* __restrict__ y) {
+__global__ void k_reduce_big64(const Reduce* __restrict__ red, const double* __restrict__ part, double* __restrict__ y,
+                               const int32_t* __restrict__ mask) {
     const Reduce R = red[blockIdx.x];
+    if (mask && mask[R.part] != kPartActive) return;
     const int n = R.tm * R.tn;
     const int e = blockIdx.y * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -311,7 +316,7 @@ hipError_t launch_pack_xt64(const PackBlock* packs, int n_packs, const double* x
 }
 
 hipError_t launch_hpsi_big64(const BigPlan& P, const double* pool_t, const PackBlock* packs, int n_packs,
-                             const double* x, double* xt, double* y, hipStream_t s) {
+                             const double* x, double* xt, double* y, hipStream_t s, const int32_t* active) {
     if (P.n_chunks == 0) return hipSuccess;
     if (packs && n_packs > 0) hipLaunchKernelGGL(k_pack_xt64, dim3(n_packs), dim3(256), 0, s, packs, x, xt);
     const double* tb = reinterpret_cast<const double*>(P.tbuf);
@@ -319,13 +324,13 @@ hipError_t launch_hpsi_big64(const BigPlan& P, const double* pool_t, const PackB
         const BigChunk& C = P.chunks[c];
         if (C.t1_end > C.t1_begin)
             hipLaunchKernelGGL(k_big64_t, dim3(C.t1_end - C.t1_begin), dim3(256), 0, s, P.t1, P.t1_ranges + C.t1_begin,
-                               pool_t, xt, reinterpret_cast<double*>(P.tbuf));
+                               pool_t, xt, reinterpret_cast<double*>(P.tbuf), active);
         if (C.item_end > C.item_begin)
             hipLaunchKernelGGL(k_big64_y, dim3(C.item_end - C.item_begin), dim3(256), 0, s, P.items + C.item_begin, P.t2,
-                               pool_t, tb, y, P.partial);
+                               pool_t, tb, y, P.partial, active);
         if (C.red_end > C.red_begin)
             hipLaunchKernelGGL(k_reduce_big64, dim3(C.red_end - C.red_begin, P.red_chunks), dim3(256), 0, s,
-                               P.reduces + C.red_begin, P.partial, y);
+                               P.reduces + C.red_begin, P.partial, y, active);
     }
     return hipGetLastError();
 }

@@ -189,7 +189,9 @@ __global__ __launch_bounds__(NW * 64 + PF * 64 + CW * 64) void k_hpsi_lds(const 
                                                              const uint16_t* __restrict__ pool_t,
                                                              const uint16_t* __restrict__ xtall,
                                                              double* __restrict__ yall, double* __restrict__ partall,
-                                                             int64_t n_coeff, int64_t xt_size, int64_t slot_stride) {
+                                                             int64_t n_coeff, int64_t xt_size, int64_t slot_stride,
+                                                             const int32_t* __restrict__ mask) {
+    if (mask && mask[items[blockIdx.x].part] != kPartActive) return;   // whole workgroup, before any barrier
     constexpr int KS = S / 32;          // max k tiles (and j chunks) of a source
     constexpr int QS = S / 16;          // max column tiles of the target
     constexpr int XS = KS * 2 * KS * kTileU16;
@@ -451,7 +453,8 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
                                                    const uint16_t* __restrict__ pool_t,
                                                    const uint16_t* __restrict__ xtall, double* __restrict__ yall,
                                                    double* __restrict__ partall, int64_t n_coeff, int64_t xt_size,
-                                                   int64_t slot_stride) {
+                                                   int64_t slot_stride, const int32_t* __restrict__ mask) {
+    if (mask && mask[items[blockIdx.x].part] != kPartActive) return;
     const ID I = load_item(items + blockIdx.x);
     const uint16_t* __restrict__ xt = xtall + (int64_t)blockIdx.y * xt_size;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
@@ -585,8 +588,10 @@ __global__ __launch_bounds__(64) void k_hpsi_small(const Item* __restrict__ item
 // y_tile += sum of its partial tiles, in item order; block (record, 256-element chunk), one element
 // per thread
 __global__ void k_reduce_lds(const Reduce* __restrict__ red, const double* __restrict__ partall,
-                             double* __restrict__ yall, int64_t n_coeff, int64_t part_stride) {
+                             double* __restrict__ yall, int64_t n_coeff, int64_t part_stride,
+                             const int32_t* __restrict__ mask) {
     const Reduce R = red[blockIdx.x];
+    if (mask && mask[R.part] != kPartActive) return;
     const int n = R.tm * R.tn;
     const int e = blockIdx.z * blockDim.x + threadIdx.x;
     if (e >= n) return;
@@ -600,9 +605,10 @@ __global__ void k_reduce_lds(const Reduce* __restrict__ red, const double* __res
 }
 
 hipError_t launch_reduce_partials(const Reduce* reduces, int n, int chunks, const double* partial, double* y,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int32_t* active) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reduce_lds, dim3(n, 1, chunks), dim3(256), 0, s, reduces, partial, y, (int64_t)0, (int64_t)0);
+    hipLaunchKernelGGL(k_reduce_lds, dim3(n, 1, chunks), dim3(256), 0, s, reduces, partial, y, (int64_t)0, (int64_t)0,
+                       active);
     return hipGetLastError();
 }
 
@@ -612,7 +618,7 @@ __global__ void k_zero_lds(double* __restrict__ y, int64_t n) {
 }
 
 hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const double* x, double* y, int64_t n_coeff,
-                           int nvec, bool zero_y, hipStream_t s) {
+                           int nvec, bool zero_y, hipStream_t s, const int32_t* active) {
     if (zero_y) {
         int64_t n = n_coeff * nvec, blocks = (n + 255) / 256;
         if (blocks > 8192) blocks = 8192;
@@ -632,7 +638,7 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         if (cw) {
 #define DMRG_LDS_CW(S_, TP_, NW_)                                                                          \
     hipLaunchKernelGGL((k_hpsi_lds<S_, TP_, 0, NW_, 1>), grid, dim3((NW_ + 1) * 64), 0, s, P.items + b, P.tasks, \
-                       pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss)
+                       pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss, active)
             switch (c) {
                 case 0: DMRG_LDS_CW(64, 1, kLdsWaves); break;
                 case 1:
@@ -651,33 +657,33 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         switch (c) {
             case 0:
                 if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
-                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else hipLaunchKernelGGL((k_hpsi_lds<64, 1, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
-                                        y, P.partial, n_coeff, P.xt_size, ss);
+                                        y, P.partial, n_coeff, P.xt_size, ss, active);
                 break;
             case 1:
                 if (w6) hipLaunchKernelGGL((k_hpsi_lds<64, 1, 0, 6>), grid, block6, 0, s, P.items + b, P.tasks, pool_t,
-                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else if (pf) hipLaunchKernelGGL((k_hpsi_lds<64, 2, 1>), grid, block_pf, 0, s, P.items + b, P.tasks,
-                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else hipLaunchKernelGGL((k_hpsi_lds<64, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
-                                        y, P.partial, n_coeff, P.xt_size, ss);
+                                        y, P.partial, n_coeff, P.xt_size, ss, active);
                 break;
             case 2:
                 if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 1>), grid, block_pf, 0, s, P.items + b, P.tasks, pool_t,
-                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                           P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else hipLaunchKernelGGL((k_hpsi_lds<96, 1, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
-                                        y, P.partial, n_coeff, P.xt_size, ss);
+                                        y, P.partial, n_coeff, P.xt_size, ss, active);
                 break;
             default:   // with prefetch: 3 compute wavefronts (targets of at most 96 rows) + the prefetch one
                 if (w6 && pf) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 1, 6>), grid, block6_pf, 0, s, P.items + b,
-                                                 P.tasks, pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                                 P.tasks, pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else if (w6) hipLaunchKernelGGL((k_hpsi_lds<96, 1, 0, 6>), grid, block6, 0, s, P.items + b, P.tasks,
-                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else if (pf) hipLaunchKernelGGL((k_hpsi_lds<96, 2, 1, 3>), grid, block, 0, s, P.items + b, P.tasks,
-                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss);
+                                                pool_t, P.xt, y, P.partial, n_coeff, P.xt_size, ss, active);
                 else hipLaunchKernelGGL((k_hpsi_lds<96, 2, 0>), grid, block, 0, s, P.items + b, P.tasks, pool_t, P.xt,
-                                        y, P.partial, n_coeff, P.xt_size, ss);
+                                        y, P.partial, n_coeff, P.xt_size, ss, active);
                 break;
         }
     }
@@ -686,7 +692,7 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         if (n <= 0) continue;
         const dim3 grid(n, nvec), block(64);
 #define DMRG_SMALL(NR, NQ) hipLaunchKernelGGL((k_hpsi_small<NR, NQ>), grid, block, 0, s, P.items + b, P.tasks, pool_t, \
-                                              P.xt, y, P.partial, n_coeff, P.xt_size, ss)
+                                              P.xt, y, P.partial, n_coeff, P.xt_size, ss, active)
         switch (c) {
             case 0: DMRG_SMALL(1, 2); break;
             case 1: DMRG_SMALL(2, 2); break;
@@ -699,7 +705,7 @@ hipError_t launch_hpsi_lds(const LdsPlan& P, const uint16_t* pool_t, const doubl
         const int nr = P.red_begin[k + 1] - P.red_begin[k];
         if (nr > 0)
             hipLaunchKernelGGL(k_reduce_lds, dim3(nr, nvec, P.red_chunks[k]), dim3(256), 0, s, P.reduces + P.red_begin[k],
-                               P.partial, y, n_coeff, P.partial_size);
+                               P.partial, y, n_coeff, P.partial_size, active);
     }
     return hipGetLastError();
 }

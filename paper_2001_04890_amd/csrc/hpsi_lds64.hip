@@ -79,7 +79,9 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
                                                                 const LTask64* __restrict__ tasks,
                                                                 const double* __restrict__ pool_t,
                                                                 const double* __restrict__ xt,
-                                                                double* __restrict__ y, double* __restrict__ part) {
+                                                                double* __restrict__ y, double* __restrict__ part,
+                                                                const int32_t* __restrict__ mask) {
+    if (mask && mask[items[blockIdx.x].part] != kPartActive) return;   // whole workgroup, before any barrier
     constexpr int SLOT = (KT + QT) * kTileD;   // doubles of one slot: X^T slice, then B slice
     __shared__ __attribute__((aligned(16))) double lds[2 * SLOT];
 
@@ -243,7 +245,8 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
     }
 }
 
-hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s) {
+hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s,
+                             const int32_t* active) {
     if (P.n_items == 0) return hipSuccess;
     for (int c = 0; c < kLds64Classes; ++c) {
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
@@ -251,7 +254,7 @@ hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const dou
         const dim3 grid(n);
 #define DMRG_L64C(KT_, QT_, W_, MINW_, CW_)                                                               \
     hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_, CW_>), grid, dim3((W_ + CW_) * 64), 0, s, P.items + b, \
-                       P.tasks, pool_t, xt, y, P.partial)
+                       P.tasks, pool_t, xt, y, P.partial, active)
 #define DMRG_L64(KT_, QT_, W_, MINW_)                   \
     do {                                                \
         if (P.copy_wave) DMRG_L64C(KT_, QT_, W_, MINW_, 1); \
@@ -272,7 +275,7 @@ hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const dou
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess || P.n_reduces <= 0) return e;
-    return launch_reduce_partials(P.reduces, P.n_reduces, P.red_chunks, P.partial, y, s);
+    return launch_reduce_partials(P.reduces, P.n_reduces, P.red_chunks, P.partial, y, s, active);
 }
 
 }  // namespace dmrg

@@ -41,6 +41,8 @@ struct Item {
     int32_t m_ap, m_dp;
     int32_t r0, c0;
     int32_t t_begin, t_end;
+    int32_t part = 0;        // merged problem of the target (dmrg_hop_combine), see kPartActive
+    int32_t pad = 0;
 };
 constexpr int kTileRows = 32;                  // max rows of a tile (TP <= 2)
 constexpr int kPartialVecs = 4;                // vectors per launch
@@ -52,8 +54,12 @@ struct Reduce {
     int32_t r0, c0;
     int32_t tm, tn;          // tile extent
     int32_t n_parts;
-    int32_t pad;
+    int32_t part;            // merged problem of the target
 };
+// Part mask of a merged handle: launchers take an optional device array with one entry per merged
+// problem; the records (items, reductions, pass-1 groups) of a problem whose entry is not
+// kPartActive are skipped, which leaves its part of y unspecified. A null mask runs every record.
+constexpr int32_t kPartActive = 1;
 
 // ---------------------------------------------------------------- tiled split-BF16 operands
 // Split-BF16 operands of the LDS-staged sector-GEMM kernel are stored pre-tiled in MFMA fragment
@@ -211,12 +217,13 @@ struct LdsPlan64 {
 };
 // y (one vector) += the plan's targets of f A X B^T; xt = that vector's tiled FP64 X^T
 // (launch_pack_xt64 with the FP64 packing geometry)
-hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s);
+hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const double* xt, double* y, hipStream_t s,
+                             const int32_t* active = nullptr);
 // tiled FP64 X^T of every psi block (hpsi_big64.hip)
 hipError_t launch_pack_xt64(const PackBlock* packs, int n_packs, const double* x, double* xt, hipStream_t s);
 // y (one vector) += the partial tiles of each record, in order (hpsi_lds.hip)
 hipError_t launch_reduce_partials(const Reduce* reduces, int n, int chunks, const double* partial, double* y,
-                                  hipStream_t s);
+                                  hipStream_t s, const int32_t* active = nullptr);
 
 // ---------------------------------------------------------------- large blocks (hpsi_big.hip)
 // Targets whose blocks (or sources) exceed the 96-wide LDS stages take two passes per chunk of
@@ -231,7 +238,7 @@ struct BigT1 {             // pass-1 group: one task, rows [16 rb, 16 rb + 128),
     int16_t pa32, pd32;    // source rows / cols in 32-element k tiles
     int16_t nrt;           // row tiles of the target block
     int16_t rb, jb;        // first row tile, first 32-column chunk
-    int16_t pad;
+    int16_t part;          // merged problem of the target (masks use part < 32768)
 };
 struct BigT2 {             // pass-2 task: T of the task and its B block
     int64_t t, b;
@@ -260,9 +267,9 @@ hipError_t launch_presum(const PresumBlock* blocks, int n_blocks, const PresumTe
                          double* pool, hipStream_t s);
 hipError_t launch_split(const double* pool, int64_t n, uint16_t* hi, uint16_t* lo, hipStream_t s);
 hipError_t launch_hpsi_f64(const HpsiPlan& plan, const double* pool, const double* x, double* y,
-                           int64_t n_coeff, int nvec, hipStream_t s);
+                           int64_t n_coeff, int nvec, hipStream_t s, const int32_t* active = nullptr);
 hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
-                             double* y, int64_t n_coeff, int nvec, hipStream_t s);
+                             double* y, int64_t n_coeff, int nvec, hipStream_t s, const int32_t* active = nullptr);
 hipError_t launch_diag(const DiagBlock* blocks, int n_blocks, const DiagTask* tasks,
                        const double* pool, double* d, hipStream_t s);
 // Davidson vector kernels (FP64).
@@ -308,19 +315,20 @@ hipError_t launch_renormalize(const RenormItem* items, int n_items, int64_t max_
 hipError_t launch_split_tiled(const double* pool, const PoolBlock* blocks, int n_blocks, uint16_t* tiled, hipStream_t s);
 // y (+)= H x over the LDS plan's targets; zero_y: clear y first (else accumulate into it).
 hipError_t launch_hpsi_lds(const LdsPlan& plan, const uint16_t* pool_t, const double* x, double* y, int64_t n_coeff,
-                           int nvec, bool zero_y, hipStream_t s);
+                           int nvec, bool zero_y, hipStream_t s, const int32_t* active = nullptr);
 // Large-block split path (hpsi_big.hip) for one vector: y += the large targets' part of H x;
 // xt = that vector's tiled X^T (packed by launch_hpsi_lds).
 hipError_t launch_hpsi_big(const BigPlan& plan, const uint16_t* pool_t, const uint16_t* xt, double* y,
-                           hipStream_t s);
+                           hipStream_t s, const int32_t* active = nullptr);
 // FP64 large-block path (hpsi_big64.hip) for one vector: y += the large targets' part of H x, over the
 // FP64 tiled pool; packs x into xt (FP64 tiled X^T, packed_size doubles) first unless packs is null
 // (xt already holds it).
 hipError_t launch_tile_f64(const double* pool, const PoolBlock* blocks, int n_blocks, double* tiled, hipStream_t s);
 hipError_t launch_hpsi_big64(const BigPlan& plan, const double* pool_t, const PackBlock* packs, int n_packs,
-                             const double* x, double* xt, double* y, hipStream_t s);
+                             const double* x, double* xt, double* y, hipStream_t s, const int32_t* active = nullptr);
 // Old-kernel split path over a plan without clearing y first.
 hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
-                                 double* y, int64_t n_coeff, int nvec, hipStream_t s);
+                                 double* y, int64_t n_coeff, int nvec, hipStream_t s,
+                                 const int32_t* active = nullptr);
 }  // namespace dmrg
 #endif

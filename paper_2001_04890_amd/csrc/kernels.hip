@@ -143,8 +143,9 @@ __device__ __forceinline__ void store_tile(const Item& I, double* __restrict__ y
 
 // y_tile += sum of its partial tiles, in item order
 __global__ void k_reduce(const Reduce* __restrict__ red, const double* __restrict__ partall, double* __restrict__ yall,
-                         int64_t n_coeff, int64_t part_stride) {
+                         int64_t n_coeff, int64_t part_stride, const int32_t* __restrict__ active) {
     const Reduce R = red[blockIdx.x];
+    if (active && active[R.part] != kPartActive) return;
     const double* __restrict__ part = partall + (int64_t)blockIdx.y * part_stride + R.part_off;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
     const int n = R.tm * R.tn;
@@ -169,8 +170,10 @@ template <int TP, int TQ>
 __global__ __launch_bounds__(64, min_waves_f64(TP, TQ)) void k_hpsi_f64(const Item* __restrict__ items, const Task* __restrict__ tasks,
                                                  const double* __restrict__ pool, const double* __restrict__ xpall,
                                                  double* __restrict__ yall, double* __restrict__ partall,
-                                                 int64_t n_coeff, int64_t psize, int64_t slot_stride) {
+                                                 int64_t n_coeff, int64_t psize, int64_t slot_stride,
+                                                 const int32_t* __restrict__ active) {
     const Item I = items[blockIdx.x];
+    if (active && active[I.part] != kPartActive) return;
     const double* __restrict__ xp = xpall + (int64_t)blockIdx.y * psize;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
     double* __restrict__ part = partall + (int64_t)blockIdx.y * slot_stride;
@@ -291,7 +294,7 @@ static hipError_t launch_pack(const HpsiPlan& plan, const double* x, int64_t n_c
 // y = 0, then phase by phase: the item launches of every tile class, then the phase's reductions
 template <class F>
 static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, int nvec, hipStream_t s, F&& launch_one,
-                             bool zero_y = true) {
+                             bool zero_y, const int32_t* active) {
     int64_t n = n_coeff * nvec, blocks = (n + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (zero_y) hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, s, y, n);
@@ -304,7 +307,7 @@ static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, i
         const int nr = P.reduce_end - P.reduce_begin;
         if (nr > 0)
             hipLaunchKernelGGL(k_reduce, dim3(nr, nvec), dim3(256), 0, s, plan.reduces + P.reduce_begin, plan.partial,
-                               y, n_coeff, plan.partial_size);
+                               y, n_coeff, plan.partial_size, active);
     }
     return hipGetLastError();
 }
@@ -330,14 +333,14 @@ static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, i
     }
 
 hipError_t launch_hpsi_f64(const HpsiPlan& plan, const double* pool, const double* x, double* y, int64_t n_coeff,
-                           int nvec, hipStream_t s) {
+                           int nvec, hipStream_t s, const int32_t* active) {
     hipError_t e = launch_pack(plan, x, n_coeff, nvec, 0, s);
     if (e != hipSuccess) return e;
     const int64_t ss = plan.partial_size;
     return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
         DMRG_CLASS_SWITCH(k_hpsi_f64, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, pool, plan.xp, y,
-                          plan.partial, n_coeff, plan.packed_size, ss)
-    });
+                          plan.partial, n_coeff, plan.packed_size, ss, active)
+    }, true, active);
 }
 
 // ------------------------------------------------------------------ split-BF16 sector GEMMs
@@ -363,8 +366,9 @@ __global__ __launch_bounds__(64, min_waves_split(TP, TQ)) void k_hpsi_split(cons
                                                    const uint16_t* __restrict__ xrl, const uint16_t* __restrict__ xth,
                                                    const uint16_t* __restrict__ xtl, double* __restrict__ yall,
                                                    double* __restrict__ partall, int64_t n_coeff, int64_t psize,
-                                                   int64_t slot_stride) {
+                                                   int64_t slot_stride, const int32_t* __restrict__ active) {
     const Item I = items[blockIdx.x];
+    if (active && active[I.part] != kPartActive) return;
     const int64_t vo = (int64_t)blockIdx.y * psize;
     double* __restrict__ y = yall + (int64_t)blockIdx.y * n_coeff;
     double* __restrict__ part = partall + (int64_t)blockIdx.y * slot_stride;
@@ -497,25 +501,27 @@ __global__ __launch_bounds__(64, min_waves_split(TP, TQ)) void k_hpsi_split(cons
 }
 
 static hipError_t hpsi_split_impl(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
-                                  double* y, int64_t n_coeff, int nvec, hipStream_t s, bool zero_y) {
+                                  double* y, int64_t n_coeff, int nvec, hipStream_t s, bool zero_y,
+                                  const int32_t* active) {
     hipError_t e = launch_pack(plan, x, n_coeff, nvec, 1, s);
     if (e != hipSuccess) return e;
     const int64_t ss = plan.partial_size;
     return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
         DMRG_CLASS_SWITCH(k_hpsi_split, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, hi, lo, plan.xp,
-                          plan.xr_hi, plan.xr_lo, plan.xt_hi, plan.xt_lo, y, plan.partial, n_coeff, plan.packed_size, ss)
-    }, zero_y);
+                          plan.xr_hi, plan.xr_lo, plan.xt_hi, plan.xt_lo, y, plan.partial, n_coeff, plan.packed_size, ss,
+                          active)
+    }, zero_y, active);
 }
 
 hipError_t launch_hpsi_split(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x, double* y,
-                             int64_t n_coeff, int nvec, hipStream_t s) {
-    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, true);
+                             int64_t n_coeff, int nvec, hipStream_t s, const int32_t* active) {
+    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, true, active);
 }
 
 hipError_t launch_hpsi_split_acc(const HpsiPlan& plan, const uint16_t* hi, const uint16_t* lo, const double* x,
-                                 double* y, int64_t n_coeff, int nvec, hipStream_t s) {
+                                 double* y, int64_t n_coeff, int nvec, hipStream_t s, const int32_t* active) {
     if (plan.n_phases == 0) return hipSuccess;
-    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, false);
+    return hpsi_split_impl(plan, hi, lo, x, y, n_coeff, nvec, s, false, active);
 }
 
 // ------------------------------------------------------------------ diag(H)

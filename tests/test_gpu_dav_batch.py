@@ -9,7 +9,14 @@
   same energies; the graph-captured launch sequence gives the eager one's results bit for bit.
 * Split precision with an FP64 polish: energies within 1e-8 of the FP64 ones.
 * Errors: max_sub < 3 is rejected; a part with a zero start vector is an argument error.
+* Part mask: the merged H.psi skips the work of parts that have left the active set; parts whose
+  sectors take every H.psi route (up to 139 states: the two-pass large-block kernels and the
+  LDS-staged ones, next to one-wavefront problems), in plans with cut items (partial tiles and their
+  reductions) and with the large-block and FP64 LDS-staged paths off, give the same energies and Ritz
+  vectors bit for bit with the mask as without it (DMRG_BATCH_PART_MASK=0).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -121,3 +128,59 @@ def test_argument_errors(exact):
     psi[comb.part_coeff[1]:comb.part_coeff[2]] = 0.0
     with pytest.raises(lib_mod.DmrgError):
         comb.davidson_batch(psi)
+
+
+MASK_PLANS = {
+    "default": {},
+    "cut": {"DMRG_BIG64": "2", "DMRG_BIG_STAGES": "4", "DMRG_BIG_STAGES1": "4", "DMRG_BIG_TBUDGET_MB": "16",
+            "DMRG_LDS_ITEMS": "64", "DMRG_LDS64_ITEMS": "64", "DMRG_ITEMS": "256"},
+    "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0", "DMRG_LDS64": "0"},
+}
+
+
+def with_env(env, fn):
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return fn()
+    finally:
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+@pytest.fixture(scope="module")
+def mixed_problems():
+    # (L, M, sigma, seed): sectors up to 139 states (L = 14, M = 300), up to about 110, and small ones
+    return [synth(L, M, sg, sd) for L, M, sg, sd in ((14, 300, 0.6, 5), (12, 50, 1.0, 311), (14, 200, 0.8, 9),
+                                                     (10, 40, 1.2, 312))]
+
+
+@pytest.mark.parametrize("plan", sorted(MASK_PLANS))
+def test_part_mask_bitwise(mixed_problems, plan):
+    def build():
+        hops = [Hop(*p, device=0, want_split=True) for p in mixed_problems]
+        return Hop.combine(hops)
+    comb = with_env(MASK_PLANS[plan], build)
+    out = {}
+    for mask in ("1", "0"):
+        psi = start(comb, 51)
+        r = with_env({"DMRG_BATCH_PART_MASK": mask},
+                     lambda: comb.davidson_batch(psi, tol=1e-8, max_iter=600, max_sub=16, precision=PREC_SPLIT2,
+                                                 fp64_polish=True, split_tol=1e-4))
+        print(f"[dav batch] mask {mask}, plan {plan}: iters {r['iters']}, energies {r['energy']}", flush=True)
+        assert r["converged"]
+        out[mask] = (r, psi.cpu().numpy())
+    (r1, v1), (r0, v0) = out["1"], out["0"]
+    assert len(set(r1["iters"].tolist())) > 1          # parts leave the active set at different iterations
+    assert np.array_equal(r1["energy"], r0["energy"]) and np.array_equal(r1["iters"], r0["iters"])
+    assert np.array_equal(v1, v0)
+    # every plan converges to the same energies (FP64 polish to 1e-8)
+    for other, e in _MASK_ENERGIES.items():
+        assert np.allclose(r1["energy"], e, rtol=0, atol=1e-9 * np.abs(e).max()), (plan, other)
+    _MASK_ENERGIES[plan] = r1["energy"]
+
+
+_MASK_ENERGIES = {}
