@@ -312,8 +312,12 @@ def bench_batch(args):
     for hp in hops:
         hp.trim()
     comb = dm.Hop.combine(hops, stream=stream)
-    tune = comb.autotune(dm.PREC_SPLIT2, reps=2, stream=stream)
-    log(f"[bench] combined: |psi|={comb.n_coeff} flops/matvec={flops:.3e} autotune={tune}")
+    t = time.perf_counter()
+    os.environ["DMRG_AUTOTUNE_TRACE"] = "1"   # one line per candidate plan
+    tune = {"split": comb.autotune(dm.PREC_SPLIT2, reps=2, stream=stream),
+            "fp64": comb.autotune(dm.PREC_FP64, reps=2, stream=stream)}
+    log(f"[bench] combined: |psi|={comb.n_coeff} flops/matvec={flops:.3e} autotune ({time.perf_counter() - t:.1f} s)"
+        f"={tune}")
     out = {}
     for name, prec in (("split", dm.PREC_SPLIT2), ("fp64", dm.PREC_FP64)):
         t_batch = timed(lambda: comb.hpsi(xc, yc, prec, stream=stream), 3)

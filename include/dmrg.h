@@ -399,14 +399,21 @@ typedef struct {
 dmrg_status dmrg_davidson_batch(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts, dmrg_dav_batch_result* result,
                                 void* stream);
 
-/* Autotuner of the H.psi launch plan for `precision`: times candidate settings on the device, `reps`
- * timed calls each, and keeps the fastest. FP64 (one-wavefront kernel): widest output tile (2, 4, 8
- * MFMA tiles of 16 columns) x work items (8k, 32k, 64k) x launch order (heaviest first / cache-aware).
- * Split (LDS-staged and task-mode kernels): work items (4k, 8k, 16k, 32k) x launch order (heaviest
- * first / XCD-aware by left sector / for a merged handle, each problem's items together); its tile
- * width is reported as 0. chosen (3 ints: tile width,
- * items, order) and best_ms (milliseconds) may be NULL. Drops the handle's cached graphs.
- * Synchronizes `stream`. */
+/* Autotuner of the H.psi launch plan for `precision`: one pass of coordinate descent over the
+ * plan's settings, each taking in turn its fastest candidate value with the others held at their
+ * best so far; every candidate is timed on the device (the fastest of `reps` calls after one
+ * warm-up) and the plan is rebuilt with the winners. Settings, in the order of `chosen`:
+ * split: LDS work items (4k .. 64k; per merged problem on a merged handle), launch order (heaviest
+ * first / XCD-aware by left sector / each merged problem's items together), task-mode tile shape
+ * (0: 1 x 2, 1: 2 x 2, 2: 1 x 4 row x column MFMA tiles per wavefront), 64-wide stage classes (1 on),
+ * six-wavefront (S, 2) classes (bit mask 0x8 / 0 / 0xA), copy-wavefront classes (0 / 0xF), prefetch
+ * wavefront (0x4 / 0), 0. FP64: LDS-staged kernel work items (8k .. 64k), its copy wavefront (1/0),
+ * single-tile sources in it (1/0), its 7-wavefront register cap (1/0), two-pass routing of large
+ * targets (1 where cheaper, 2 all), one-wavefront tile width (2, 4, 8 tiles of 16 columns), its work
+ * items (8k, 32k, 64k) and launch order (0 heaviest first, 2 cache-aware). chosen
+ * (DMRG_AUTOTUNE_KNOBS ints) and best_ms (milliseconds of the chosen plan) may be NULL. Drops the
+ * handle's cached graphs. Synchronizes `stream`. */
+#define DMRG_AUTOTUNE_KNOBS 8
 dmrg_status dmrg_hop_autotune(dmrg_hop* hop, int32_t precision, int32_t reps, void* stream,
                               int32_t* chosen, double* best_ms);
 

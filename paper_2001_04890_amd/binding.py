@@ -23,6 +23,12 @@ DMRG_OK = 0
 DMRG_NOT_CONVERGED = 1
 PREC_FP64 = 0
 PREC_SPLIT2 = 1
+
+# dmrg_hop_autotune: settings reported in `chosen`, in order (DMRG_AUTOTUNE_KNOBS entries)
+AUTOTUNE_KNOBS = 8
+_AUTOTUNE_SPLIT = ("lds_items", "lds_order", "small_shape", "split64", "six_wave", "copy_wave", "prefetch")
+_AUTOTUNE_FP64 = ("lds64_items", "lds64_copy_wave", "lds64_small", "lds64_w7_cap", "big64", "max_tq", "items",
+                  "order")
 _KIND = {"H": 0, "C": 1, "A": 2, "B": 3, "S": 4, "U": 5, "P": 6, "Q": 7}
 
 i32p = C.POINTER(C.c_int32)
@@ -420,12 +426,16 @@ class Hop:
         _check(lib.dmrg_hop_trim(self._h))
 
     def autotune(self, precision=PREC_SPLIT2, reps=3, stream=None):
-        """Pick the fastest H.psi launch plan (dmrg_hop_autotune); returns (tile width, items, order, ms)."""
-        ch = np.zeros(3, dtype=np.int32)
+        """Pick the fastest H.psi launch plan (dmrg_hop_autotune); returns the chosen settings by name
+        and the chosen plan's time ("ms")."""
+        ch = np.zeros(AUTOTUNE_KNOBS, dtype=np.int32)
         ms = C.c_double()
         _check(lib.dmrg_hop_autotune(self._h, precision, reps, _stream_ptr(stream), _ptr(ch, C.c_int32),
                                      C.byref(ms)))
-        return int(ch[0]), int(ch[1]), int(ch[2]), ms.value
+        names = _AUTOTUNE_SPLIT if precision == PREC_SPLIT2 else _AUTOTUNE_FP64
+        out = {n: int(v) for n, v in zip(names, ch)}
+        out["ms"] = ms.value
+        return out
 
     def __del__(self):
         h = getattr(self, "_h", None)

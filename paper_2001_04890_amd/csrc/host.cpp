@@ -2241,6 +2241,9 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
         if (!H) throw Error(DMRG_ERR_ARG, "hop is NULL");
         if (H->device < 0) throw Error(DMRG_ERR_UNSUPPORTED, "host-only handle has no device state");
         if (H->trimmed) throw Error(DMRG_ERR_UNSUPPORTED, "handle was trimmed (dmrg_hop_trim)");
+        if (precision != DMRG_PREC_FP64 && precision != DMRG_PREC_SPLIT2) throw Error(DMRG_ERR_ARG, "unknown precision");
+        if (precision == DMRG_PREC_SPLIT2 && !H->has_split)
+            throw Error(DMRG_ERR_UNSUPPORTED, "handle built without split operators");
         if (reps < 1) reps = 3;
         HIPCHK(hipSetDevice(H->device));
         hipStream_t s = (hipStream_t)stream;
@@ -2250,41 +2253,81 @@ extern "C" dmrg_status dmrg_hop_autotune(dmrg_hop* H, int32_t precision, int32_t
         HIPCHK(hipMemsetAsync(x, 0, H->n_coeff * sizeof(double), s));
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
-        // FP64: widest output tile, work items and launch order of the one-wave kernel. Split: work
-        // items and launch order of the LDS-staged plan (first number reported as 0).
+        // The plan's settings, each with its candidate values (the current value is measured first).
+        // Split: LDS item count and launch order, the task-mode tile (row tiles x column tiles per
+        // wavefront: 1 x 2 / 2 x 2 / 1 x 4), the 64-wide stage classes, the six-wavefront (S, 2)
+        // classes, the copy and prefetch wavefronts. FP64: the LDS-staged kernel's item count, copy
+        // wavefront, single-tile sources and 7-wavefront register cap, the two-pass routing of large
+        // targets, and the one-wavefront kernel's tile width, item count and launch order.
+        struct Knob { int* field; std::vector<int> cand; };
+        std::vector<Knob> knobs;
+        int small_shape = H->tune_small_nq > 2 ? 2 : H->tune_small_nr > 1 ? 1 : 0;
         const bool split = precision == DMRG_PREC_SPLIT2;
-        std::vector<int> tq_c = split ? std::vector<int>{0} : std::vector<int>{2, 4, 8};
-        std::vector<int> items_c = split ? std::vector<int>{4096, 8192, 16384, 32768} : std::vector<int>{8192, 32768, 65536};
-        std::vector<int> order_c = split ? std::vector<int>{0, 1} : std::vector<int>{0, 2};
-        if (split && H->n_parts > 1) order_c.push_back(2);   // merged problems: keep each problem's items together
-        double best = INFINITY;
-        int bt = split ? 0 : H->tune_max_tq, bi = split ? H->tune_lds_items : H->tune_items;
-        int bo = split ? H->tune_lds_order : H->tune_order;
-        for (int tq : tq_c)
-            for (int it : items_c)
-                for (int od : order_c) {
-                    if (split) { H->tune_lds_items = it; H->tune_lds_order = od; }
-                    else { H->tune_max_tq = tq; H->tune_items = it; H->tune_order = od; }
-                    build_plan(*H, s);
-                    dmrg_status st = dmrg_hpsi(H, x, y, 1, precision, stream);
-                    if (st != DMRG_OK) throw Error(st, g_err);
-                    HIPCHK(hipEventRecord(e0, s));
-                    for (int r = 0; r < reps; ++r) {
-                        st = dmrg_hpsi(H, x, y, 1, precision, stream);
-                        if (st != DMRG_OK) throw Error(st, g_err);
-                    }
-                    HIPCHK(hipEventRecord(e1, s));
-                    HIPCHK(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-                    const double avg = ms / reps;
-                    if (avg < best) { best = avg; bt = tq; bi = it; bo = od; }
-                }
-        if (split) { H->tune_lds_items = bi; H->tune_lds_order = bo; }
-        else { H->tune_max_tq = bt; H->tune_items = bi; H->tune_order = bo; }
-        build_plan(*H, s);
-        if (chosen) { chosen[0] = bt; chosen[1] = bi; chosen[2] = bo; }
-        if (best_ms) *best_ms = best;
+        if (split) {
+            knobs.push_back({&H->tune_lds_items, {4096, 8192, 16384, 32768, 65536}});
+            knobs.push_back({&H->tune_lds_order, H->n_parts > 1 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 1}});
+            knobs.push_back({&small_shape, {0, 1, 2}});
+            knobs.push_back({&H->tune_lds_split64, {1, 0}});
+            knobs.push_back({&H->tune_lds_w6, {0x8, 0, 0xA}});
+            knobs.push_back({&H->tune_lds_cw, {0, 0xF}});
+            knobs.push_back({&H->tune_lds_pf, {0x4, 0}});
+        } else {
+            const bool lds64 = H->tune_lds64 != 0;
+            knobs.push_back({&H->tune_lds64_items, lds64 ? std::vector<int>{8192, 16384, 32768, 65536} : std::vector<int>{}});
+            knobs.push_back({&H->tune_lds64_cw, lds64 ? std::vector<int>{1, 0} : std::vector<int>{}});
+            knobs.push_back({&H->tune_lds64_small, lds64 ? std::vector<int>{1, 0} : std::vector<int>{}});
+            knobs.push_back({&H->tune_lds64_w7, lds64 ? std::vector<int>{1, 0} : std::vector<int>{}});
+            knobs.push_back({&H->tune_big64, {1, 2}});
+            knobs.push_back({&H->tune_max_tq, {2, 4, 8}});
+            knobs.push_back({&H->tune_items, {8192, 32768, 65536}});
+            knobs.push_back({&H->tune_order, {0, 2}});
+        }
+        const char* tr = std::getenv("DMRG_AUTOTUNE_TRACE");
+        const bool trace = tr && tr[0] == '1';
+        auto measure = [&]() {
+            H->tune_small_nr = small_shape == 1 ? 2 : 1;
+            H->tune_small_nq = small_shape == 2 ? 4 : 2;
+            const double tb = now();
+            build_plan(*H, s);
+            const double t_build = now() - tb;
+            dmrg_status st = dmrg_hpsi(H, x, y, 1, precision, stream);   // warm-up
+            if (st != DMRG_OK) throw Error(st, g_err);
+            double best = INFINITY;
+            for (int r = 0; r < reps; ++r) {
+                HIPCHK(hipEventRecord(e0, s));
+                st = dmrg_hpsi(H, x, y, 1, precision, stream);
+                if (st != DMRG_OK) throw Error(st, g_err);
+                HIPCHK(hipEventRecord(e1, s));
+                HIPCHK(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+                best = std::min(best, (double)ms);
+            }
+            if (trace) {
+                std::fprintf(stderr, "[dmrg autotune] precision %d:", precision);
+                for (const Knob& k : knobs) std::fprintf(stderr, " %d", *k.field);
+                std::fprintf(stderr, " -> %.3f ms (plan built in %.2f s)\n", best, t_build);
+            }
+            return best;
+        };
+        // one pass of coordinate descent: each setting in turn takes its fastest candidate, the
+        // others held at their best values so far
+        double best = measure();
+        for (Knob& k : knobs) {
+            const int keep = *k.field;
+            int arg = keep;
+            for (int v : k.cand) {
+                if (v == keep) continue;
+                *k.field = v;
+                const double t = measure();
+                if (t < best) { best = t; arg = v; }
+            }
+            *k.field = arg;
+        }
+        const double final_ms = measure();
+        if (chosen)
+            for (int i = 0; i < DMRG_AUTOTUNE_KNOBS; ++i) chosen[i] = i < (int)knobs.size() ? *knobs[i].field : 0;
+        if (best_ms) *best_ms = std::min(best, final_ms);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         (void)hipFree(xy);
