@@ -198,6 +198,9 @@ struct dmrg_hop {
                                                 // (0: those run in the one-wave kernel)
     int tune_lds64_w7 = 1;                      // 1: its 7-wavefront class held to 128 VGPRs (two per CU)
     int tune_lds64_cw = 1;                      // 1: a copy wavefront per workgroup issues every LDS copy
+    int tune_lds64_task_route = 0;              // 1: a target within its tiles keeps the tasks whose source fits
+                                                // them (larger sources: two-pass or one-wave path); 0: a
+                                                // target with any larger source leaves it entirely
     dmrg::LdsPlan64 lplan64{};
     std::vector<void*> plan_allocations;   // freed when the plan is rebuilt
     int64_t dev_bytes = 0, plan_bytes = 0; // device memory held (handle lifetime / current plan)

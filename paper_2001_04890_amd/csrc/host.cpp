@@ -1219,11 +1219,13 @@ void build_big_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& big, bo
             if (a_off < 0 || b_off < 0) throw Error(DMRG_ERR_ARG, "internal: no tiled identity block");
             const int64_t t_off = tsize;
             tsize += (int64_t)nrt * (pd / unit) * tile_el;
+            const int ka = (H.blk_ma[ht.i] + unit - 1) / unit, kd = (H.blk_md[ht.i] + unit - 1) / unit;
             for (int rb = 0; rb < nrt; rb += 8)
-                for (int jb = 0; jb < pd / unit; jb += 128 / unit)
+                for (int jb = 0; jb < kd; jb += 128 / unit)
                     t1.push_back({esc * pk_off[ht.i], a_off, t_off, ht.f, (int16_t)(pa / unit),
-                                  (int16_t)(pd / unit), (int16_t)nrt, (int16_t)rb, (int16_t)jb, 0});
-            t2.push_back({t_off, b_off, pd / unit, 0});
+                                  (int16_t)(pd / unit), (int16_t)nrt, (int16_t)rb, (int16_t)jb, 0, (int16_t)ka,
+                                  (int16_t)kd});
+            t2.push_back({t_off, b_off, pd / unit, kd});
         }
         H.big_t2_range[j] = {b0, (int32_t)t2.size()};
         for (size_t g = g_t1; g < t1.size(); ++g) t1[g].part = (int16_t)part_j;
@@ -1289,19 +1291,22 @@ std::vector<char> large_targets(const dmrg_hop& H, int limit = 96) {
 // one-wavefront kernel recomputes A.X for every 128-column output tile) divided by the fraction of
 // the FP64 MFMA rate it sustains (measured: two-pass ~0.65 of peak on its padded work, one-wavefront
 // ~0.3). mode 2: every target above the 96-wide LDS stages (as the split path).
-std::vector<char> fp64_big_targets(const dmrg_hop& H, int mode) {
+// Tasks already taken by the FP64 LDS-staged kernel (lds_task) are left out of the comparison.
+std::vector<char> fp64_big_targets(const dmrg_hop& H, int mode, const std::vector<char>* lds_task) {
     // with the LDS-staged kernel on, targets within its 112 x 112 tiles are its own
     std::vector<char> big = large_targets(H, H.tune_lds64 ? 16 * dmrg::kLds64MaxTiles : 96);
     if (mode == 2) return big;
     auto up = [](double m, double q) { return std::ceil(m / q) * q; };
     std::vector<double> c_big(H.blk.size(), 0.0), c_one(H.blk.size(), 0.0);
-    for (const auto& t : H.tasks) {
-        if (!big[t.j]) continue;
+    for (size_t k = 0; k < H.tasks.size(); ++k) {
+        const auto& t = H.tasks[k];
+        if (!big[t.j] || (lds_task && !lds_task->empty() && (*lds_task)[k])) continue;
         const double ma = H.blk_ma[t.i], md = H.blk_md[t.i], mj = H.blk_ma[t.j], nj = H.blk_md[t.j];
         const double r16 = up(mj, 16), nrt = r16 / 16, nq = up(nj, 16) / 16;
-        const double pa = up(ma, 32), pd = up(md, 32);
-        // two-pass: pass 1 (8 x 8 tiles of 16 per group, pa k), pass 2 (8 x 8 tiles, pd k)
-        c_big[t.j] += (2.0 * up(nrt, 8) * 16 * up(pd / 16, 8) * 16 * pa + 2.0 * up(nrt, 8) * 16 * up(nq, 8) * 16 * pd) / 0.65;
+        const double ka = up(ma, 16), kd = up(md, 16);
+        // two-pass: pass 1 (8 x 8 tiles of 16 per group, k over the source rows holding data), pass 2
+        // (the output tiles inside the target, k over the T tiles holding data)
+        c_big[t.j] += (2.0 * up(nrt, 8) * 16 * up(kd / 16, 8) * 16 * ka + 2.0 * r16 * up(nj, 16) * kd) / 0.65;
         // one wavefront per 32 x 128 tile: A.X per column tile, then (A.X).B^T
         const double ncol = std::ceil(nj / 128.0);
         c_one[t.j] += (2.0 * up(mj, 32) * up(ma, 16) * up(md, 16) * ncol + 2.0 * up(mj, 32) * up(md, 16) * up(nj, 16)) / 0.3;
@@ -1401,6 +1406,7 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
             const int a = H.blk[ht.i][0], d = H.blk[ht.i][3];
             const int pa = dmrg::ld_of(H.blk_ma[ht.i]), pd = dmrg::ld_of(H.blk_md[ht.i]);
             if (!H.tune_lds64_small && pa <= 32 && pd <= 32) continue;   // single-tile source: one-wave kernel
+            if (std::max(H.blk_ma[ht.i], H.blk_md[ht.i]) > 16 * kMax) continue;   // source above the tiles: other paths
             lds[t] = 1;
             dmrg::LTask64 L;
             L.x_off = pk_off[ht.i];
@@ -1520,21 +1526,27 @@ void build_plan(dmrg_hop& H, hipStream_t s) {
     const size_t nb = H.blk.size();
     std::vector<char> big64(nb, 0), lds64;   // targets of the two-pass path; tasks of the LDS kernel
     bool any_big = false, any_lds = false;
-    if (H.tune_big64) {
-        big64 = fp64_big_targets(H, H.tune_big64);
-        for (char b : big64) any_big |= b != 0;
-    }
-    if (H.tune_lds64 || any_big) make_tiled_f64(H, s);
     if (H.tune_lds64) {
-        build_lds64_plan(H, s, large_targets(H, 16 * dmrg::kLds64MaxTiles), lds64);
+        // the LDS-staged kernel takes the targets within its 112 x 112 tiles: with task routing every
+        // task of such a target whose source fits too, otherwise only targets whose sources all fit
+        make_tiled_f64(H, s);
+        std::vector<char> lds_large = large_targets(H, 16 * dmrg::kLds64MaxTiles);
+        if (H.tune_lds64_task_route)
+            for (size_t j = 0; j < nb; ++j) lds_large[j] = std::max(H.blk_ma[j], H.blk_md[j]) > 16 * dmrg::kLds64MaxTiles;
+        build_lds64_plan(H, s, lds_large, lds64);
         for (char b : lds64) any_lds |= b != 0;
     }
+    if (H.tune_big64) {
+        big64 = fp64_big_targets(H, H.tune_big64, &lds64);
+        for (char b : big64) any_big |= b != 0;
+    }
+    if (any_big) make_tiled_f64(H, s);
     if (any_big || any_lds) {
         std::vector<char> rest(nb), rest_tasks(H.tasks.size(), 1);
         for (size_t j = 0; j < nb; ++j) rest[j] = !big64[j];
         for (size_t t = 0; t < lds64.size(); ++t) rest_tasks[t] = !lds64[t];
         build_plan_core(H, s, &rest, false, H.plan, H.launches, H.phases, &rest_tasks);
-        if (any_big) build_big_plan(H, s, big64, true);
+        if (any_big) build_big_plan(H, s, big64, true, &rest_tasks);
         H.xt64 = plan_alloc<double>(H, (size_t)std::max<int64_t>(H.plan.packed_size, 1));
     } else {
         build_plan_core(H, s, nullptr, false, H.plan, H.launches, H.phases);
@@ -1866,6 +1878,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_W7")) H->tune_lds64_w7 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_CW")) H->tune_lds64_cw = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS64_TASK_ROUTE")) H->tune_lds64_task_route = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS_CW")) H->tune_lds_cw = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_SPLIT_TASK_ROUTE")) H->tune_split_task_route = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_PART_ITEMS")) H->tune_part_items = std::atoi(e) != 0;
@@ -2159,6 +2172,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64_small = hops[0]->tune_lds64_small;
         C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
         C->tune_lds64_cw = hops[0]->tune_lds64_cw;
+        C->tune_lds64_task_route = hops[0]->tune_lds64_task_route;
         C->tune_split_task_route = hops[0]->tune_split_task_route;
         C->tune_part_items = hops[0]->tune_part_items;
         C->vec_step = hops[0]->vec_step;

@@ -94,8 +94,9 @@ __global__ void k_pack_xt64(const PackBlock* __restrict__ packs, const double* _
 
 // ------------------------------------------------------------------ pass 1: T = f A X per task
 // Group: one task, T rows [16 rb, 16 rb + 128) (8 row tiles), T columns [16 jb, 16 jb + 128) (8 j
-// tiles); BigT1.pa32 / pd32 hold the source's 16-wide k tiles here. Wave (wj, wr): j tiles jb + 4 wj
-// + {0..3}, row tiles rb + 4 wr + {0..3}: 16 accumulator tiles.
+// tiles); BigT1.pa32 / pd32 hold the source's 16-wide k tiles here (the tile strides) and ka / kd the
+// ones that hold data: the k loop stops at ka, and T tiles past kd are neither copied nor stored.
+// Wave (wj, wr): j tiles jb + 4 wj + {0..3}, row tiles rb + 4 wr + {0..3}: 16 accumulator tiles.
 __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work, const int32_t* __restrict__ ranges,
                                                  const double* __restrict__ pool_t, const double* __restrict__ xt,
                                                  double* __restrict__ tbuf, const int32_t* __restrict__ mask) {
@@ -104,20 +105,21 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
     if (mask && mask[work[g_begin].part] != kPartActive) return;   // a workgroup's groups share one part
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int wj = wave & 1, wr = wave >> 1;
-    struct G { int64_t x, a, t; double f; int pa, pd, nrt, rb, jb; };
+    struct G { int64_t x, a, t; double f; int pa, pd, nrt, rb, jb, ka, kd; };
     auto load_g = [&](int i) {
         const BigT1* wp = work + i;
         G d;
         d.x = uni64(wp->xt); d.a = uni64(wp->a); d.t = uni64(wp->t);
         d.f = __builtin_bit_cast(double, uni64(__builtin_bit_cast(int64_t, wp->f)));
         d.pa = uni(wp->pa32); d.pd = uni(wp->pd32); d.nrt = uni(wp->nrt); d.rb = uni(wp->rb); d.jb = uni(wp->jb);
+        d.ka = uni(wp->ka); d.kd = uni(wp->kd);
         return d;
     };
     auto sources = [&](const G d, int kt, int64_t (&src)[kStageTiles]) {
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int jt = d.jb + i;
-            src[i] = jt < d.pd ? d.x + (int64_t)(jt * d.pa + kt) * kTileD : -1;
+            src[i] = jt < d.kd ? d.x + (int64_t)(jt * d.pa + kt) * kTileD : -1;
             const int rt = d.rb + i;
             src[8 + i] = rt < d.nrt ? d.a + (int64_t)(rt * d.pa + kt) * kTileD : -1;
         }
@@ -126,7 +128,9 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+        }
     auto store = [&](const G d) {
         int ln = lane;   // opaque copy: keep the store addresses out of the main loop
         asm volatile("" : "+v"(ln));
@@ -135,7 +139,7 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int jt = d.jb + 4 * wj + jj, rt = d.rb + 4 * wr + rr;
-                if (jt < d.pd && rt < d.nrt) {
+                if (jt < d.kd && rt < d.nrt) {
                     // acc[jj][rr][v] = T'^T[j 16 jt + g + 4 v][r 16 rt + li] = T tile (rt, jt), lane value v
                     f64x4 v = acc[jj][rr] * d.f;
                     *reinterpret_cast<f64x4*>(tbuf + d.t + (int64_t)(rt * d.pd + jt) * kTileD + ln * 4) = v;
@@ -156,7 +160,7 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
     int st = 0;
     for (;;) {
         int ngi = gi, nkt = kt + 1;
-        if (nkt == cur.pa) { ngi = gi + 1; nkt = 0; }
+        if (nkt == cur.ka) { ngi = gi + 1; nkt = 0; }
         const bool has_next = ngi < g_end;
         G nxt = cur;
         if (has_next) {
@@ -171,7 +175,8 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
         for (int jj = 0; jj < 4; ++jj) p[jj] = lds4(sp + (4 * wj + jj) * kTileD);
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) q[rr] = lds4(sp + (8 + 4 * wr + rr) * kTileD);
-        // consecutive MFMAs accumulate into the same registers (the fast path of the matrix core)
+        // consecutive MFMAs accumulate into the same registers (the fast path of the matrix core); every
+        // tile runs (skipping those outside the block costs this kernel its second workgroup per CU)
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj)
 #pragma unroll
@@ -189,6 +194,8 @@ __global__ __launch_bounds__(256) void k_big64_t(const BigT1* __restrict__ work,
 }
 
 // ------------------------------------------------------------------ pass 2: Y += sum T B^T per tile
+// The k loop runs over the T tiles that hold data (BigT2.kd); a wave runs the MFMAs of its output
+// tiles inside the target only.
 __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items, const BigT2* __restrict__ tasks,
                                                  const double* __restrict__ pool_t, const double* __restrict__ tbuf,
                                                  double* __restrict__ y, double* __restrict__ part,
@@ -223,9 +230,11 @@ __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items,
             asm volatile("" : "+a"(acc[a][b]));   // accumulators live in AGPRs across the loop
         }
 
+    // this wave's output tiles inside the target (wave-uniform counts)
+    const int nr = min(4, max(0, nrt - rb - 4 * wr)), nqw = min(4, max(0, nq - qb - 4 * wq));
     int t = t_begin, jt = 0;
     int64_t T_t = uni64(tasks[t].t), T_b = uni64(tasks[t].b);
-    int T_pd = uni(tasks[t].pd32);
+    int T_pd = uni(tasks[t].pd32), T_kd = uni(tasks[t].kd);
     {
         int64_t src[kStageTiles];
         sources(T_t, T_b, T_pd, 0, src);
@@ -236,12 +245,15 @@ __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items,
     int st = 0;
     for (;;) {
         int nt = t, njt = jt + 1;
-        if (njt == T_pd) { nt = t + 1; njt = 0; }
+        if (njt == T_kd) { nt = t + 1; njt = 0; }
         const bool has_next = nt < t_end;
         int64_t N_t = T_t, N_b = T_b;
-        int N_pd = T_pd;
+        int N_pd = T_pd, N_kd = T_kd;
         if (has_next) {
-            if (nt != t) { N_t = uni64(tasks[nt].t); N_b = uni64(tasks[nt].b); N_pd = uni(tasks[nt].pd32); }
+            if (nt != t) {
+                N_t = uni64(tasks[nt].t); N_b = uni64(tasks[nt].b);
+                N_pd = uni(tasks[nt].pd32); N_kd = uni(tasks[nt].kd);
+            }
             int64_t src[kStageTiles];
             sources(N_t, N_b, N_pd, njt, src);
             copy_stage(tbuf, pool_t, src, lds + (st ^ 1) * kStageD, wave, lane);
@@ -256,13 +268,15 @@ __global__ __launch_bounds__(256) void k_big64_y(const Item* __restrict__ items,
         for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
             for (int qq = 0; qq < 4; ++qq)
+                if (rr < nr && qq < nqw) {
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[rr][qq] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[rr][v], q[qq][v], acc[rr][qq], 0, 0, 0);
+                    for (int v = 0; v < 4; ++v)
+                        acc[rr][qq] = __builtin_amdgcn_mfma_f64_16x16x4f64(p[rr][v], q[qq][v], acc[rr][qq], 0, 0, 0);
+                }
         wait_vm();
         __syncthreads();
         if (!has_next) break;
-        t = nt; jt = njt; T_t = N_t; T_b = N_b; T_pd = N_pd;
+        t = nt; jt = njt; T_t = N_t; T_b = N_b; T_pd = N_pd; T_kd = N_kd;
         st ^= 1;
     }
     // pin the accumulators to AGPRs at the loop exit (else the allocator copies them to VGPRs on every

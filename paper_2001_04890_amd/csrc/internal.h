@@ -239,11 +239,13 @@ struct BigT1 {             // pass-1 group: one task, rows [16 rb, 16 rb + 128),
     int16_t nrt;           // row tiles of the target block
     int16_t rb, jb;        // first row tile, first 32-column chunk
     int16_t part;          // merged problem of the target (masks use part < 32768)
+    int16_t ka, kd;        // source rows / cols holding data, in k tiles (FP64 form: the k loop of
+                           // pass 1 and the T tiles it writes stop there)
 };
 struct BigT2 {             // pass-2 task: T of the task and its B block
     int64_t t, b;
     int32_t pd32;
-    int32_t pad;
+    int32_t kd;            // T tiles holding data along k (FP64 form: the k loop of pass 2 stops there)
 };
 // Chunk c: pass-1 workgroups [t1_begin, t1_end) (workgroup w runs groups t1_ranges[w] ..
 // t1_ranges[w + 1] - 1), pass-2 items [item_begin, item_end), reductions [red_begin, red_end).

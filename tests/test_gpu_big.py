@@ -12,7 +12,9 @@ pass-2 items: task lists cut into partial tiles that ordered reductions add); th
 with any source above the stages sends all its tasks to the large-block path (by default only those
 tasks do, the rest of the target stays in the LDS-staged kernel), with the FP64 LDS kernel off; and
 "copy_wave": the split row-mode classes with a copy wavefront (four and two row tiles per compute
-wavefront). Bars as for
+wavefront); "lds64_route": FP64 targets within the 112-wide LDS-staged tiles keep the tasks whose
+source fits them there and send only the larger-source tasks to the two-pass (or one-wavefront)
+path, with the two-pass path chosen by cost or forced. Bars as for
 every H.psi: FP64 within 1e-12 of max|y|, split element by element within its error bound
 (helpers.assert_split_bound); split plans that move FP32 run boundaries agree within 2e-6; every
 plan is deterministic bit for bit.
@@ -44,6 +46,8 @@ VARIANTS = {
     "off": {"DMRG_BIG": "0", "DMRG_BIG64": "0"},
     "target_route": {"DMRG_SPLIT_TASK_ROUTE": "0", "DMRG_LDS64": "0"},
     "copy_wave": {"DMRG_LDS_CW": "15", "DMRG_LDS_W6": "0"},
+    "lds64_route": {"DMRG_LDS64_TASK_ROUTE": "1"},
+    "lds64_route_forced": {"DMRG_LDS64_TASK_ROUTE": "1", "DMRG_BIG64": "2"},
 }
 
 
