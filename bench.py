@@ -166,6 +166,24 @@ def main():
     log(f"[bench] Davidson s/iter: split {s_iter_sp * 1e3:.2f} ms ({value:.2f} TF/s), "
         f"fp64 {s_iter_64 * 1e3:.2f} ms ({value_64:.2f} TF/s)")
 
+    # --- the same iterations with the whole iteration on the device (dmrg_davidson_batch, one part)
+    def dav_steps_dev(prec, iters, graph):
+        psi = torch.as_tensor(random_vector(n, 3), device=dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = hop.davidson_batch(psi, tol=1e-30, max_iter=iters, max_sub=24, precision=prec, use_graph=graph,
+                               stream=stream)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, r
+
+    dev_iter = {}
+    for name, prec in (("fp64", dm.PREC_FP64), ("split", dm.PREC_SPLIT2)):
+        for graph in (False, True):
+            dav_steps_dev(prec, args.warmup, graph)
+            w, r = dav_steps_dev(prec, args.steps, graph)
+            dev_iter[f"{name}{'_graph' if graph else ''}_ms"] = round(w / args.steps * 1e3, 3)
+    log(f"[bench] device-resident Davidson s/iter: {dev_iter}")
+
     # --- convergence at equal tolerance: FP64 vs split + FP64 polish
     conv = {}
     if not args.no_converge:
@@ -233,6 +251,7 @@ def main():
                   "ms_per_iter": round(s_iter_sp * 1e3, 3), "kernel_ms": round(tsp * 1e3, 4),
                   "rel_matvec_err": rel_mv},
         "converge": conv,
+        "device_davidson_ms_per_iter": dev_iter,
         "mlp_precond_ms": round(mlp_ms, 4),
         "build_seconds": round(t_build, 2),
         "roofline": roofline,

@@ -48,6 +48,8 @@ struct BatchDev {
     double* rnorm;             // n_parts
     int32_t* status;           // n_parts
     int32_t* iters;            // n_parts: iterations while active
+    double* Qp;                // n_parts x K x K: eigenvectors of the last Rayleigh-Ritz step (ld K)
+    int32_t* qk;               // n_parts: their size (0: none, the next step starts cold)
 };
 
 // dots[p][slot + j] = <V[j], x> over part p, j < nv (nv <= K + kDotTail - slot), active parts
@@ -63,7 +65,8 @@ hipError_t bscale(const BatchDev& B, double* x, int slot, hipStream_t s);
 hipError_t bprecond(const BatchDev& B, const double* r, const double* d, double* t, hipStream_t s);
 // dst = src on the parts whose status is active (all parts: all_parts)
 hipError_t bcopy(const BatchDev& B, const double* src, double* dst, bool all_parts, hipStream_t s);
-// Rayleigh-Ritz of the k x k leading block of G_p (active parts): theta, s, ms
+// Rayleigh-Ritz of the k x k leading block of G_p (active parts): theta, s, ms; warm-started from
+// the previous step's eigenvectors when G grew by one row and column since
 hipError_t brr(const BatchDev& B, int k, hipStream_t s);
 // residual check: rnorm = sqrt(dots[K + kSlotResid]); converged below tol; counts the iteration
 hipError_t bcheck(const BatchDev& B, double tol, hipStream_t s);

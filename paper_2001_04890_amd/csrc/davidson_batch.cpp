@@ -19,7 +19,7 @@ namespace {
 
 using dmrg::Error;
 
-constexpr int64_t kChunk = 4096;     // reduction chunk (coefficients)
+constexpr int64_t kChunk = 1024;     // reduction chunk (coefficients): four per thread of a 256-wide workgroup
 constexpr int kCheckEvery = 4;       // iterations between status reads
 
 struct Dev {
@@ -110,6 +110,8 @@ extern "C" dmrg_status dmrg_davidson_batch(dmrg_hop* H, double* psi, const dmrg_
         B.rnorm = d.get<double>(P, s);
         B.status = d.get<int32_t>(P, s);
         B.iters = d.get<int32_t>(P, s);
+        B.Qp = d.get<double>((size_t)P * K * K, s);
+        B.qk = d.get<int32_t>(P, s);
         double* V = d.get<double>((size_t)K * n, s);
         double* W = d.get<double>((size_t)K * n, s);
         double* u = d.get<double>(n, s);

@@ -38,30 +38,38 @@ __global__ __launch_bounds__(256) void k_bdots(BatchDev B, const double* __restr
         for (int j = 0; j < kDotGroup; ++j)
             if (j < nj) acc[j] = fma(V[(int64_t)(j0 + j) * B.n + i], xi, acc[j]);
     }
-    __shared__ double red[kDotGroup][256];
+    // butterfly sums inside each wavefront, then the four wavefronts' sums in a fixed order
+    __shared__ double red[4][kDotGroup];
 #pragma unroll
-    for (int j = 0; j < kDotGroup; ++j) red[j][threadIdx.x] = acc[j];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-#pragma unroll
-            for (int j = 0; j < kDotGroup; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + w];
-        __syncthreads();
+    for (int j = 0; j < kDotGroup; ++j) {
+        double v = acc[j];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6][j] = v;
     }
+    __syncthreads();
     const int ld = B.K + kDotTail;
-    if ((int)threadIdx.x < nj) B.partial[(int64_t)blockIdx.x * ld + slot + j0 + threadIdx.x] = red[threadIdx.x][0];
+    if ((int)threadIdx.x < nj)
+        B.partial[(int64_t)blockIdx.x * ld + slot + j0 + threadIdx.x] =
+            ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
-__global__ void k_bdots_finish(BatchDev B, int nv, int slot) {
-    const int p = blockIdx.x;
+// one workgroup per (part, dot product): thread t adds the partials of chunks c0 + t, c0 + t + 256, ...
+// in order, then a fixed tree adds the 256 sums (deterministic for a given chunk table)
+__global__ __launch_bounds__(256) void k_bdots_finish(BatchDev B, int slot) {
+    const int p = blockIdx.x, j = blockIdx.y;
     if (status_of(B, p) != kActive) return;
     const int ld = B.K + kDotTail;
     const int c0 = B.part_chunk[p], c1 = B.part_chunk[p + 1];
-    for (int j = threadIdx.x; j < nv; j += blockDim.x) {
-        double sum = 0.0;
-        for (int c = c0; c < c1; ++c) sum += B.partial[(int64_t)c * ld + slot + j];
-        B.dots[(int64_t)p * ld + slot + j] = sum;
+    double sum = 0.0;
+    for (int c = c0 + (int)threadIdx.x; c < c1; c += blockDim.x) sum += B.partial[(int64_t)c * ld + slot + j];
+    __shared__ double red[256];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) B.dots[(int64_t)p * ld + slot + j] = red[0];
 }
 
 __global__ __launch_bounds__(256) void k_bcombine(BatchDev B, const double* __restrict__ V, int nv,
@@ -69,9 +77,8 @@ __global__ __launch_bounds__(256) void k_bcombine(BatchDev B, const double* __re
                                                   double beta) {
     const BChunk c = B.chunks[blockIdx.x];
     if (status_of(B, c.part) != kActive) return;
-    __shared__ double cf[kRR];
-    for (int j = threadIdx.x; j < nv; j += blockDim.x) cf[j] = coef[(int64_t)c.part * B.K + j];
-    __syncthreads();
+    // the coefficients are uniform over the workgroup: scalar loads, no LDS in the dependency chain
+    const double* __restrict__ cf = coef + (int64_t)__builtin_amdgcn_readfirstlane(c.part) * B.K;
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) {
         double v = beta != 0.0 ? beta * out[i] : 0.0;
         for (int j = 0; j < nv; ++j) v = fma(cf[j], V[(int64_t)j * B.n + i], v);
@@ -83,10 +90,8 @@ __global__ __launch_bounds__(256) void k_bproject(BatchDev B, const double* __re
                                                   double* __restrict__ x) {
     const BChunk c = B.chunks[blockIdx.x];
     if (status_of(B, c.part) != kActive) return;
-    __shared__ double cf[kRR];
     const int ld = B.K + kDotTail;
-    for (int j = threadIdx.x; j < nv; j += blockDim.x) cf[j] = B.dots[(int64_t)c.part * ld + j];
-    __syncthreads();
+    const double* __restrict__ cf = B.dots + (int64_t)__builtin_amdgcn_readfirstlane(c.part) * ld;
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) {
         double v = x[i];
         for (int j = 0; j < nv; ++j) v = fma(-cf[j], V[(int64_t)j * B.n + i], v);
@@ -122,23 +127,54 @@ __global__ __launch_bounds__(256) void k_bcopy(BatchDev B, const double* __restr
     for (int64_t i = c.begin + threadIdx.x; i < c.end; i += blockDim.x) dst[i] = src[i];
 }
 
-// one workgroup of 64 threads per part
+// one workgroup of 64 threads per part. Warm start: when the part's previous Rayleigh-Ritz step
+// diagonalized the leading (k-1) x (k-1) block of this G (Qp, qk = k - 1), the Jacobi sweeps start
+// from A = Q^T G Q with Q = diag(Qp, 1), which is diagonal but for the new row and column, and
+// accumulate onto that Q; any orthogonal start gives the same eigenpairs, only in fewer sweeps.
 __global__ __launch_bounds__(64) void k_brr(BatchDev B, int k) {
     const int p = blockIdx.x;
     if (status_of(B, p) != kActive) return;
     __shared__ double A[kRR][kRR + 1];
     __shared__ double Q[kRR][kRR + 1];
+    __shared__ double T[kRR][kRR + 1];
     __shared__ double cs[kRR / 2], sn[kRR / 2];
     __shared__ int pa[kRR / 2], pb[kRR / 2];
     __shared__ double red[64];
     const int tid = threadIdx.x;
     const double* G = B.G + (int64_t)p * B.K * B.K;
+    double* Qp = B.Qp + (int64_t)p * B.K * B.K;
+    const bool warm = k >= 2 && B.qk[p] == k - 1;
     for (int e = tid; e < k * k; e += 64) {
         const int i = e / k, j = e - (e / k) * k;
         A[i][j] = 0.5 * (G[(int64_t)i * B.K + j] + G[(int64_t)j * B.K + i]);
-        Q[i][j] = i == j ? 1.0 : 0.0;
+        Q[i][j] = warm && i < k - 1 && j < k - 1 ? Qp[(int64_t)i * B.K + j] : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
+    if (warm) {
+        for (int e = tid; e < k * k; e += 64) {   // T = A Q
+            const int i = e / k, j = e - (e / k) * k;
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v = fma(A[i][l], Q[l][j], v);
+            T[i][j] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < k * k; e += 64) {   // A = Q^T T
+            const int i = e / k, j = e - (e / k) * k;
+            double v = 0.0;
+            for (int l = 0; l < k; ++l) v = fma(Q[l][i], T[l][j], v);
+            A[i][j] = v;
+        }
+        __syncthreads();
+        for (int e = tid; e < k * k; e += 64) {   // symmetric to the last bit
+            const int i = e / k, j = e - (e / k) * k;
+            if (i < j) {
+                const double m = 0.5 * (A[i][j] + A[j][i]);
+                A[i][j] = m;
+                A[j][i] = m;
+            }
+        }
+        __syncthreads();
+    }
     const int kk = k + (k & 1);              // even count; index k is a dummy when k is odd
     const int np = kk / 2;
     for (int sweep = 0; sweep < 60 && k > 1; ++sweep) {
@@ -220,6 +256,11 @@ __global__ __launch_bounds__(64) void k_brr(BatchDev B, int k) {
         B.s[(int64_t)p * B.K + j] = v;
         B.ms[(int64_t)p * B.K + j] = -th * v;
     }
+    for (int e = tid; e < k * k; e += 64) {
+        const int i = e / k, j = e - (e / k) * k;
+        Qp[(int64_t)i * B.K + j] = Q[i][j];
+    }
+    if (tid == 0) B.qk[p] = k;
 }
 
 __global__ void k_bcheck(BatchDev B, double tol) {
@@ -316,6 +357,7 @@ __global__ __launch_bounds__(64) void k_brestart(BatchDev B) {
     const double g00 = dot(sv, gs), g01 = dot(sv, gy), g11 = dot(y, gy);
     for (int j = tid; j < K; j += 64) B.y1[(int64_t)p * K + j] = y[j];
     if (tid == 0) {
+        B.qk[p] = 0;   // G is replaced: the next Rayleigh-Ritz step starts cold
         G[0] = g00;
         G[1] = g01;
         G[K] = g01;
@@ -326,6 +368,7 @@ __global__ __launch_bounds__(64) void k_brestart(BatchDev B) {
 __global__ void k_bactivate(BatchDev B, int reset_iters) {
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < B.n_parts; p += gridDim.x * blockDim.x) {
         B.status[p] = kActive;
+        B.qk[p] = 0;
         if (reset_iters) B.iters[p] = 0;
     }
 }
@@ -336,7 +379,7 @@ hipError_t bdots(const BatchDev& B, const double* V, int nv, const double* x, in
     if (nv <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bdots, dim3(B.n_chunks, (nv + kDotGroup - 1) / kDotGroup), dim3(256), 0, s, B, V, nv, x,
                        slot);
-    hipLaunchKernelGGL(k_bdots_finish, dim3(B.n_parts), dim3(64), 0, s, B, nv, slot);
+    hipLaunchKernelGGL(k_bdots_finish, dim3(B.n_parts, nv), dim3(256), 0, s, B, slot);
     return hipGetLastError();
 }
 hipError_t bcombine(const BatchDev& B, const double* V, int nv, const double* coef, double* out, double beta,
