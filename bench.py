@@ -59,7 +59,14 @@ def main():
                          "large: L=76 (57,56) M=6000, one GPU's share of the operator pairs; "
                          "precond: learned vs diagonal Davidson preconditioner at L=32 M=1500")
     ap.add_argument("--bonds", type=str, default="4,8,12,15,19,23,27",
-                    help="precond: left-site indices of the evaluated bonds")
+                    help="precond --precond-eval bonds: left-site indices of the evaluated bonds")
+    ap.add_argument("--precond-eval", choices=["sweep", "bonds"], default="sweep",
+                    help="precond: A/B along the last of two sweeps at L=32 (default), or at single bonds of "
+                         "synthetic blocks")
+    ap.add_argument("--precond-m", type=str, default="512,1500",
+                    help="precond sweep evaluation: bond dimension of each sweep (the A/B runs the last)")
+    ap.add_argument("--precond-train-m", type=str, default="256,512",
+                    help="precond sweep evaluation: sweeps at L=20..28 whose middle-bond blocks give training pairs")
     ap.add_argument("--pairs", type=int, default=1000,
                     help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
@@ -382,6 +389,61 @@ def _batch_problem(j):
     return L, M, synthetic_problem(L, (L + 1) // 2, L // 2, M, 1.5, 2000 + j)
 
 
+def bench_precond_sweep(args, net, stream, t0):
+    import torch
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_integrals, random_vector
+    train_m = [int(m) for m in args.precond_train_m.split(",")]
+    eval_m = [int(m) for m in args.precond_m.split(",")]
+    # training pairs: converged solves at the middle bond of swept states, L = 20 .. 28
+    for k, L in enumerate((20, 22, 24, 26, 28)):
+        h, eri = random_integrals(L, 3000 + k)
+        site = L // 2 - 1
+        ts = time.time()
+        sw = dm.sweep(h, eri, L // 2, L // 2, train_m, m_warmup=train_m[0], tol=1e-6, max_iter=400, seed=k,
+                      stream=stream, keep_site=site)
+        hop = dm.Hop(h, eri, sw["left"], sw["right"], L // 2, L // 2, site, device=0, stream=stream)
+        psi = torch.as_tensor(random_vector(hop.n_coeff, 40 + k), device="cuda:0")
+        res = net.collect(hop, psi, slot=0, rows_per_iter=4096, seed=k, tol=1e-9, max_iter=600, stream=stream)
+        log(f"[bench] precond: L={L} swept ({time.time() - ts:.1f}s, M {train_m}), |psi|={hop.n_coeff}: "
+            f"collected {res['rows']} rows in {res['iters']} iterations")
+        del hop, sw
+    losses = net.train(3000, batch=4096, lr=1e-3, seed=1, stream=stream)
+    t_train = time.time() - t0
+    log(f"[bench] precond: training loss {float(losses[:50].mean()):.4f} -> {float(losses[-50:].mean()):.4f} "
+        f"({t_train:.1f}s incl. sweeps and collection)")
+    # A/B along the last sweep at L = 32
+    L = 32
+    h, eri = random_integrals(L, 3200)
+    runs = {}
+    for name, use in (("diag", None), ("mlp", net)):
+        ts = time.time()
+        r = dm.sweep(h, eri, L // 2, L // 2, eval_m, m_warmup=eval_m[0], tol=1e-8, max_iter=1000, seed=7,
+                     stream=stream, mlp=use, mlp_from_sweep=len(eval_m) - 1)
+        runs[name] = r
+        log(f"[bench] precond sweep {name}: {time.time() - ts:.1f}s, E {r['energy']:.10f}, "
+            f"iterations {int(r['iters'].sum())}, not converged {r['n_not_converged']}")
+    per = 2 * L - 3                          # solves of the last sweep (n sweeps: n (2L - 3) + 1 solves)
+    last = slice(len(runs["diag"]["iters"]) - per, None)
+    it_d = int(runs["diag"]["iters"][last].sum())
+    it_m = int(runs["mlp"]["iters"][last].sum())
+    first_equal = bool(np.array_equal(runs["diag"]["energies"][:last.start], runs["mlp"]["energies"][:last.start]))
+    de = np.abs(runs["diag"]["energies"][last] - runs["mlp"]["energies"][last])
+    line = {"metric": "Davidson iterations to ||r||<=1e-8 over the last sweep, learned vs diagonal preconditioner",
+            "value": it_m, "unit": "iterations (sum over the sweep's solves)", "n_gpus": 1, "steps": per, "warmup": 0,
+            "ms_per_step": None, "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"two-site sweeps at L={L} N={L}, random integrals (seed 3200), bond dimensions "
+                                   f"{eval_m}; the A/B runs the last sweep; network trained on middle-bond solves of "
+                                   f"swept states at L=20..28 (bond dimensions {train_m})"},
+            "diag_iters": it_d, "mlp_iters": it_m, "earlier_sweeps_identical": first_equal,
+            "max_dE_per_solve": float(de.max()), "final_dE": abs(runs["diag"]["energy"] - runs["mlp"]["energy"]),
+            "diag_energy": runs["diag"]["energy"], "mlp_energy": runs["mlp"]["energy"],
+            "diag_sweep_iters": runs["diag"]["iters"][last].tolist(), "mlp_sweep_iters": runs["mlp"]["iters"][last].tolist(),
+            "train_seconds": round(t_train, 1)}
+    print(json.dumps(line), flush=True)
+
+
 def bench_large(args):
     """Large shape: L = 76, N = 113 (57, 56), M = 6000 per block at the middle bond, synthetic block
     operators (sigma 1.5, sectors up to 420 states) restricted to one GPU's share of the operator
@@ -441,18 +503,24 @@ def bench_large(args):
 
 
 def bench_precond(args):
-    """Learned Davidson preconditioner vs the diagonal one. Training pairs come from converged FP64
-    solves of synthetic middle-bond problems at L = 20, 22, 24, 26, 28 (N = L, M = 512, seeds 3000+);
-    the network is trained on the GPU (Adam, 3000 steps of 4096 rows). Evaluation: L = 32, N = 32,
-    M = 1500 at the bonds --bonds (synthetic blocks of each bond, seed 3100 + bond), Davidson to
-    ||r|| <= 1e-8 from the same start vector with each preconditioner; iterations, time and |dE|."""
+    """Learned Davidson preconditioner vs the diagonal one at L = 32, N = 32, tolerance 1e-8.
+    Default (--precond-eval sweep): training pairs come from converged FP64 solves at the middle bond
+    of swept states (dmrg_sweep over random integrals at L = 20, 22, 24, 26, 28, N = L, bond
+    dimensions --precond-train-m, the bond's blocks handed back by keep_site); the network is trained
+    on the GPU (Adam, 3000 steps of 4096 rows). Evaluation: dmrg_sweep at L = 32 with bond dimensions
+    --precond-m, once with the diagonal preconditioner everywhere and once with the learned one in the
+    last sweep (same seed: the earlier sweeps are identical), Davidson to ||r|| <= 1e-8 at every bond;
+    iterations and time of the last sweep and |dE| per solve. --precond-eval bonds: the earlier form
+    (synthetic blocks at single bonds, network trained on synthetic middle-bond problems)."""
     import torch
     import paper_2001_04890_amd as dm
-    from dmrg_inputs import random_vector
+    from dmrg_inputs import random_integrals, random_vector
     from dmrg_inputs.synthetic import synthetic_problem
     stream = torch.cuda.current_stream()
     net = dm.Mlp(device=0, seed=5)
     t0 = time.time()
+    if args.precond_eval == "sweep":
+        return bench_precond_sweep(args, net, stream, t0)
     for k, L in enumerate((20, 22, 24, 26, 28)):
         h, eri, left, right, site = synthetic_problem(L, L // 2, L // 2, 512, 1.5, 3000 + k)
         hop = dm.Hop(h, eri, left, right, L // 2, L // 2, site, device=0, stream=stream)

@@ -453,6 +453,10 @@ typedef struct {
     int32_t        verbose;        /* 1: one line per solve on stderr */
     int32_t        keep_site;      /* 1 .. n_orb - 3: hand the blocks of the bond (keep_site, keep_site+1)
                                       after the last sweep back in the result; 0: none */
+    const struct dmrg_mlp* mlp;    /* learned preconditioner (DMRG_PRECOND_MLP, with its diagonal judge)
+                                      for the solves of sweeps mlp_from_sweep .. n_sweeps - 1; NULL: the
+                                      diagonal preconditioner everywhere (warm-up has no solves) */
+    int32_t        mlp_from_sweep; /* 0 .. n_sweeps - 1 */
 } dmrg_sweep_opts;
 
 typedef struct {
@@ -475,7 +479,8 @@ typedef struct {
 
 /* Run the warm-up and n_sweeps sweeps for `problem` (its site field is ignored). Returns
  * DMRG_NOT_CONVERGED when some Davidson solve reached max_iter (the sweep goes on with its best
- * pair), errors as the calls it makes; keep_site outside 0 .. n_orb - 3 is DMRG_ERR_ARG. */
+ * pair), errors as the calls it makes; keep_site outside 0 .. n_orb - 3, or mlp_from_sweep outside
+ * 0 .. n_sweeps - 1 with an mlp, is DMRG_ERR_ARG. */
 dmrg_status dmrg_sweep(const dmrg_problem* problem, const dmrg_sweep_opts* opts, dmrg_sweep_result* result);
 
 /* ---------------------------------------------------------------------------------------------

@@ -78,7 +78,7 @@ class SweepOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int32), ("m_per_sweep", i32p), ("m_warmup", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32), ("fp64_polish", C.c_int32),
                 ("split_tol", C.c_double), ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("verbose", C.c_int32), ("keep_site", C.c_int32)]
+                ("verbose", C.c_int32), ("keep_site", C.c_int32), ("mlp", C.c_void_p), ("mlp_from_sweep", C.c_int32)]
 
 
 class SweepResult(C.Structure):
@@ -309,11 +309,12 @@ def block_grow(h, eri, n_alpha, n_beta, site, block, side, kept=None, O=None, de
 
 def sweep(h, eri, n_alpha, n_beta, m_per_sweep, m_warmup=None, tol=1e-8, max_iter=300, max_sub=24,
           precision=PREC_FP64, fp64_polish=False, split_tol=1e-5, seed=0, device=0, stream=None, verbose=False,
-          keep_site=0):
+          keep_site=0, mlp=None, mlp_from_sweep=0):
     """dmrg_sweep: warm-up plus len(m_per_sweep) two-site sweeps. Returns a dict with the per-solve
     energies, discarded weights, iterations and bond sites, and the run's summary fields; with
     keep_site > 0 also "left" and "right", the blocks of the bond (keep_site, keep_site + 1) after the
-    last sweep (dmrg_inputs Blocks)."""
+    last sweep (dmrg_inputs Blocks). mlp: a learned preconditioner (Mlp) for the solves of sweeps
+    mlp_from_sweep and later."""
     h = np.ascontiguousarray(h, dtype=np.float64)
     eri = np.ascontiguousarray(eri, dtype=np.float64)
     L = h.shape[0]
@@ -321,7 +322,8 @@ def sweep(h, eri, n_alpha, n_beta, m_per_sweep, m_warmup=None, tol=1e-8, max_ite
     prob = Problem(L, n_alpha, n_beta, 0, _ptr(h, C.c_double), _ptr(eri, C.c_double))
     opts = SweepOpts(int(ms.size), _ptr(ms, C.c_int32), int(m_warmup if m_warmup else ms[0]), tol, max_iter, max_sub,
                      precision, 1 if fp64_polish else 0, split_tol, seed, device, _stream_ptr(stream),
-                     1 if verbose else 0, int(keep_site))
+                     1 if verbose else 0, int(keep_site), mlp._h.value if mlp is not None else None,
+                     int(mlp_from_sweep))
     cap = int(ms.size) * (2 * L) + 2
     e = np.zeros(cap)
     d = np.zeros(cap)

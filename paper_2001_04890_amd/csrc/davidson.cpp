@@ -164,6 +164,13 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         bool mlp_on = o->precond == DMRG_PRECOND_MLP;
         double best_mlp_r = INFINITY;
         int mlp_stall = 0;
+        // rate rule of the judge: the network must cut the residual by judge_factor within judge_window
+        // iterations (0: rule off)
+        int judge_window = 0;
+        double judge_factor = 0.0;
+        if (const char* e = std::getenv("DMRG_MLP_JUDGE_WINDOW")) judge_window = std::max(0, std::atoi(e));
+        if (const char* e = std::getenv("DMRG_MLP_JUDGE_FACTOR")) judge_factor = std::atof(e);
+        std::vector<double> rhist;
         res->precond_fallback_iter = -1;
         for (it = 1; it <= o->max_iter; ++it) {
             std::vector<double> A((size_t)k * k);
@@ -248,6 +255,13 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
                 // minimum (by 1%) for 20 iterations, the rest of the solve uses the diagonal correction
                 if (rnorm < 0.99 * best_mlp_r) { best_mlp_r = rnorm; mlp_stall = 0; }
                 else if (++mlp_stall >= 20) { mlp_on = false; res->precond_fallback_iter = it; }
+                rhist.push_back(rnorm);
+                const size_t nh = rhist.size();
+                if (mlp_on && judge_window > 0 && nh > (size_t)judge_window &&
+                    rnorm > judge_factor * rhist[nh - 1 - judge_window]) {
+                    mlp_on = false;
+                    res->precond_fallback_iter = it;
+                }
             }
             if (sess) sess->correction(r, u, t, theta, w.V, k, mlp_on);
             // next basis vector, built in place on the device: orthogonalize, normalize, and once more

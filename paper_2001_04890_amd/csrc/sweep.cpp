@@ -160,6 +160,8 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
         res->left_block = res->right_block = nullptr;
         if (o->keep_site < 0 || (o->keep_site > 0 && o->keep_site > L - 3))
             throw Error(DMRG_ERR_ARG, "keep_site must be 0 (none) or 1 .. n_orb - 3");
+        if (o->mlp && (o->mlp_from_sweep < 0 || o->mlp_from_sweep >= o->n_sweeps))
+            throw Error(DMRG_ERR_ARG, "mlp_from_sweep must be 0 .. n_sweeps - 1");
         const double t0 = dmrg::now_seconds();
         hipStream_t s = (hipStream_t)o->stream;
         HIPCHK(hipSetDevice(o->device));
@@ -225,6 +227,9 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
             for (double& v : x) v = g.normal();
             HIPCHK(hipMemcpyAsync(psi.p, x.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
             dmrg_dav_result r{};
+            const bool learned = o->mlp && sweep >= o->mlp_from_sweep;
+            dav.precond = learned ? DMRG_PRECOND_MLP : DMRG_PRECOND_DIAG;
+            dav.mlp = learned ? o->mlp : nullptr;
             const dmrg_status st = dmrg_davidson(hop.p, psi.p, &dav, &r, s);
             check(st);
             if (n_solves < res->capacity) {

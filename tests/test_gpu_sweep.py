@@ -9,6 +9,10 @@ brute-force FCI (the oracle's determinant CI from the same integrals).
   the energy the last backward sweep found there (same blocks, so the same two-site problem), equal
   to E_FCI at full M and above it (by at most the sweep's own error) when truncated; the blocks have
   the orbitals, sectors and kept dimension of that bond. keep_site out of range is an argument error.
+* Learned preconditioner in sweeps: a new network (output layer zero, so its correction is the
+  diagonal one) in the solves of the second sweep gives the diagonal run's energies and iteration
+  counts; a trained network changes no energy beyond the tolerance's reach (|dE| <= 1e-8 per solve,
+  the final energy within 1e-9); mlp_from_sweep out of range is an argument error.
 """
 import numpy as np
 import pytest
@@ -87,3 +91,31 @@ def test_keep_site_out_of_range_is_an_argument_error(l8):
     h, eri, _ = l8
     with pytest.raises(lib_mod.DmrgError):
         lib_mod.sweep(h, eri, 4, 4, [4], m_warmup=4, keep_site=6)
+
+
+def test_learned_preconditioner_in_sweeps(l8):
+    h, eri, e_fci = l8
+    kw = dict(m_warmup=24, tol=1e-9, max_iter=500, seed=4)
+    ref = lib_mod.sweep(h, eri, 4, 4, [24, 24], **kw)
+    fresh = lib_mod.Mlp(device=0, seed=9)
+    r = lib_mod.sweep(h, eri, 4, 4, [24, 24], mlp=fresh, mlp_from_sweep=1, **kw)
+    print(f"[sweep mlp] fresh network: iters {r['iters'].sum()} vs {ref['iters'].sum()}", flush=True)
+    assert np.array_equal(r["iters"], ref["iters"])
+    assert np.abs(r["energies"] - ref["energies"]).max() < 1e-12
+    # a network trained on this problem's own solves: same energies within the solver's tolerance
+    net = lib_mod.Mlp(device=0, seed=10)
+    from dmrg_inputs import random_vector
+    for k, site in enumerate((2, 3, 4)):
+        kept = lib_mod.sweep(h, eri, 4, 4, [24], keep_site=site, **kw)
+        hop = lib_mod.Hop(h, eri, kept["left"], kept["right"], 4, 4, site, device=0)
+        psi = torch.as_tensor(random_vector(hop.n_coeff, 60 + k), device="cuda:0")
+        net.collect(hop, psi, slot=0, rows_per_iter=512, seed=k, tol=1e-10, max_iter=300)
+    net.train(200, batch=1024, lr=1e-3, seed=2)
+    r2 = lib_mod.sweep(h, eri, 4, 4, [24, 24], mlp=net, mlp_from_sweep=1, **kw)
+    print(f"[sweep mlp] trained network: iters {r2['iters'].sum()} vs {ref['iters'].sum()}, "
+          f"E {r2['energy']:.12f} vs {ref['energy']:.12f} (FCI {e_fci:.12f})", flush=True)
+    assert r2["converged"]
+    assert np.abs(r2["energies"] - ref["energies"]).max() < 1e-8
+    assert abs(r2["energy"] - ref["energy"]) < 1e-9
+    with pytest.raises(lib_mod.DmrgError):
+        lib_mod.sweep(h, eri, 4, 4, [24], mlp=fresh, mlp_from_sweep=1, **kw)
