@@ -67,6 +67,14 @@ def main():
                     help="precond sweep evaluation: bond dimension of each sweep (the A/B runs the last)")
     ap.add_argument("--precond-train-m", type=str, default="256,512",
                     help="precond sweep evaluation: sweeps at L=20..28 whose middle-bond blocks give training pairs")
+    ap.add_argument("--precond-stage", choices=["all", "train", "eval"], default="all",
+                    help="precond sweep evaluation: train only (write --mlp-params), evaluate only (read it), or both")
+    ap.add_argument("--precond-arm", choices=["shadow", "both", "diag", "mlp"], default="shadow",
+                    help="precond sweep evaluation: shadow (default): one sweep that solves every bond of the last "
+                         "sweep with both preconditioners on the same problem and goes on with the diagonal solve; "
+                         "both: two sweeps, each with its own preconditioner; diag / mlp: one of those sweeps")
+    ap.add_argument("--mlp-params", type=str, default=None,
+                    help="precond sweep evaluation: .npy file of the trained network's parameters")
     ap.add_argument("--pairs", type=int, default=1000,
                     help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
@@ -389,13 +397,12 @@ def _batch_problem(j):
     return L, M, synthetic_problem(L, (L + 1) // 2, L // 2, M, 1.5, 2000 + j)
 
 
-def bench_precond_sweep(args, net, stream, t0):
+def train_swept(net, train_m, stream, t0):
+    """Training pairs from converged FP64 solves at the middle bond of swept states (L = 20 .. 28,
+    random integrals, seeds 3000+), then 3000 Adam steps of 4096 rows; returns the seconds taken."""
     import torch
     import paper_2001_04890_amd as dm
     from dmrg_inputs import random_integrals, random_vector
-    train_m = [int(m) for m in args.precond_train_m.split(",")]
-    eval_m = [int(m) for m in args.precond_m.split(",")]
-    # training pairs: converged solves at the middle bond of swept states, L = 20 .. 28
     for k, L in enumerate((20, 22, 24, 26, 28)):
         h, eri = random_integrals(L, 3000 + k)
         site = L // 2 - 1
@@ -412,18 +419,80 @@ def bench_precond_sweep(args, net, stream, t0):
     t_train = time.time() - t0
     log(f"[bench] precond: training loss {float(losses[:50].mean()):.4f} -> {float(losses[-50:].mean()):.4f} "
         f"({t_train:.1f}s incl. sweeps and collection)")
+    return t_train
+
+
+def bench_precond_sweep(args, net, stream, t0):
+    import paper_2001_04890_amd as dm
+    from dmrg_inputs import random_integrals
+    train_m = [int(m) for m in args.precond_train_m.split(",")]
+    eval_m = [int(m) for m in args.precond_m.split(",")]
+    if args.precond_stage == "eval":
+        net.set_params(np.load(args.mlp_params))
+        t_train = None
+        log(f"[bench] precond: network parameters from {args.mlp_params}")
+    else:
+        t_train = train_swept(net, train_m, stream, t0)
+        if args.mlp_params:
+            np.save(args.mlp_params, net.get_params())
+        if args.precond_stage == "train":
+            return
     # A/B along the last sweep at L = 32
     L = 32
     h, eri = random_integrals(L, 3200)
-    runs = {}
-    for name, use in (("diag", None), ("mlp", net)):
+    if args.precond_arm == "shadow":
         ts = time.time()
         r = dm.sweep(h, eri, L // 2, L // 2, eval_m, m_warmup=eval_m[0], tol=1e-8, max_iter=1000, seed=7,
-                     stream=stream, mlp=use, mlp_from_sweep=len(eval_m) - 1)
+                     stream=stream, mlp=net, mlp_from_sweep=len(eval_m) - 1, mlp_shadow=True, verbose=True)
+        per = 2 * L - 4                      # solves of the last sweep (the first has 2L - 3, later ones 2L - 4)
+        last = slice(len(r["iters"]) - per, None)
+        it_d, it_m = r["iters"][last], r["iters_alt"][last]
+        de = np.abs(r["energies"][last] - r["energies_alt"][last])
+        log(f"[bench] precond shadow sweep: {time.time() - ts:.1f}s, diagonal {int(it_d.sum())} vs learned "
+            f"{int(it_m.sum())} iterations, max |dE| {de.max():.1e}")
+        line = {"metric": "Davidson iterations to ||r||<=1e-8 over the last sweep, learned vs diagonal preconditioner "
+                          "on the same two-site problems",
+                "value": int(it_m.sum()), "unit": "iterations (sum over the sweep's solves)", "n_gpus": 1,
+                "steps": per, "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"two-site sweeps at L={L} N={L}, random integrals (seed 3200), bond dimensions "
+                                       f"{eval_m}; every bond of the last sweep solved with both preconditioners from "
+                                       f"the same start vector (the sweep goes on with the diagonal solve); network "
+                                       f"trained on middle-bond solves of swept states at L=20..28 (bond dimensions "
+                                       f"{train_m})"},
+                "diag_iters": int(it_d.sum()), "mlp_iters": int(it_m.sum()),
+                "bonds_mlp_fewer": int((it_m < it_d).sum()), "bonds_mlp_more": int((it_m > it_d).sum()),
+                "max_dE_per_solve": float(de.max()), "energy": r["energy"], "sweep_seconds": r["seconds"],
+                "diag_sweep_iters": it_d.tolist(), "mlp_sweep_iters": it_m.tolist(),
+                "train_seconds": round(t_train, 1) if t_train is not None else None,
+                "judge": "no new residual minimum (by 1%) in 20 iterations, or no halving in 10"}
+        print(json.dumps(line), flush=True)
+        return
+    runs = {}
+    arms = (("diag", None), ("mlp", net)) if args.precond_arm == "both" else \
+        ((args.precond_arm, None if args.precond_arm == "diag" else net),)
+    for name, use in arms:
+        ts = time.time()
+        r = dm.sweep(h, eri, L // 2, L // 2, eval_m, m_warmup=eval_m[0], tol=1e-8, max_iter=1000, seed=7,
+                     stream=stream, mlp=use, mlp_from_sweep=len(eval_m) - 1, verbose=True)
         runs[name] = r
         log(f"[bench] precond sweep {name}: {time.time() - ts:.1f}s, E {r['energy']:.10f}, "
             f"iterations {int(r['iters'].sum())}, not converged {r['n_not_converged']}")
-    per = 2 * L - 3                          # solves of the last sweep (n sweeps: n (2L - 3) + 1 solves)
+    per = 2 * L - 4                          # solves of the last sweep (the first has 2L - 3, later ones 2L - 4)
+    if args.precond_arm != "both":
+        name = args.precond_arm
+        r = runs[name]
+        last = slice(len(r["iters"]) - per, None)
+        line = {"metric": "Davidson iterations to ||r||<=1e-8 over the last sweep, one preconditioner",
+                "value": int(r["iters"][last].sum()), "unit": "iterations (sum over the sweep's solves)",
+                "n_gpus": 1, "steps": per, "warmup": 0, "ms_per_step": None, "higher_is_better": False,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+                "config": {"workload": f"two-site sweeps at L={L} N={L}, random integrals (seed 3200), bond "
+                                       f"dimensions {eval_m}; preconditioner of the last sweep: {name}"},
+                "arm": name, "energy": r["energy"], "seconds": r["seconds"],
+                "energies": r["energies"].tolist(), "iters": r["iters"].tolist(), "n_not_converged": r["n_not_converged"]}
+        print(json.dumps(line), flush=True)
+        return
     last = slice(len(runs["diag"]["iters"]) - per, None)
     it_d = int(runs["diag"]["iters"][last].sum())
     it_m = int(runs["mlp"]["iters"][last].sum())
@@ -440,7 +509,8 @@ def bench_precond_sweep(args, net, stream, t0):
             "max_dE_per_solve": float(de.max()), "final_dE": abs(runs["diag"]["energy"] - runs["mlp"]["energy"]),
             "diag_energy": runs["diag"]["energy"], "mlp_energy": runs["mlp"]["energy"],
             "diag_sweep_iters": runs["diag"]["iters"][last].tolist(), "mlp_sweep_iters": runs["mlp"]["iters"][last].tolist(),
-            "train_seconds": round(t_train, 1)}
+            "train_seconds": round(t_train, 1) if t_train is not None else None,
+            "judge": "no new residual minimum (by 1%) in 20 iterations, or no halving in 10"}
     print(json.dumps(line), flush=True)
 
 

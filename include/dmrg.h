@@ -335,7 +335,8 @@ typedef struct {
     double  t_hpsi;          /* seconds spent in H.psi (device time, HIP events) */
     int32_t precond_fallback_iter; /* DMRG_PRECOND_MLP: iteration from which the diagonal correction
                                       replaced the network (the residual made no new minimum, by 1%,
-                                      for 20 iterations); -1 if the network ran to the end */
+                                      for 20 iterations, or did not halve within 10 iterations under
+                                      the network); -1 if the network ran to the end */
 } dmrg_dav_result;
 
 /* psi: device pointer, n_coeff doubles: in = start vector (need not be normalized, must be
@@ -457,6 +458,10 @@ typedef struct {
                                       for the solves of sweeps mlp_from_sweep .. n_sweeps - 1; NULL: the
                                       diagonal preconditioner everywhere (warm-up has no solves) */
     int32_t        mlp_from_sweep; /* 0 .. n_sweeps - 1 */
+    int32_t        mlp_shadow;     /* 1: in those sweeps every bond is solved twice from the same start
+                                      vector, with the diagonal preconditioner (the sweep goes on with
+                                      this solve) and with the network (results in energies_alt /
+                                      iters_alt): a comparison on identical two-site problems */
 } dmrg_sweep_opts;
 
 typedef struct {
@@ -465,7 +470,7 @@ typedef struct {
     double*  discarded;            /* discarded weight of the renormalization after that solve (0 if none) */
     int32_t* iters;                /* Davidson iterations */
     int32_t* sites;                /* left site of the solve's bond */
-    int32_t  n_solves;             /* solves performed (n_sweeps (2L - 3) + 1) */
+    int32_t  n_solves;             /* solves performed (2L - 3 in the first sweep, 2L - 4 in each later one) */
     int32_t  n_not_converged;      /* solves that reached max_iter */
     double   energy;               /* energy of the last solve */
     double   best_energy;          /* lowest energy of any solve */
@@ -475,6 +480,8 @@ typedef struct {
                                       last sweep left them (left from its forward pass, right from its
                                       backward pass: the pair the last solve at that bond used); owned
                                       by the caller (dmrg_block_free); NULL otherwise or on error */
+    double*  energies_alt;         /* mlp_shadow: per solve, the learned solve's Ritz value (NaN where */
+    int32_t* iters_alt;            /* none ran) and iterations (-1); may be NULL */
 } dmrg_sweep_result;
 
 /* Run the warm-up and n_sweeps sweeps for `problem` (its site field is ignored). Returns

@@ -78,14 +78,15 @@ class SweepOpts(C.Structure):
     _fields_ = [("n_sweeps", C.c_int32), ("m_per_sweep", i32p), ("m_warmup", C.c_int32), ("tol", C.c_double),
                 ("max_iter", C.c_int32), ("max_sub", C.c_int32), ("precision", C.c_int32), ("fp64_polish", C.c_int32),
                 ("split_tol", C.c_double), ("seed", C.c_uint64), ("device", C.c_int32), ("stream", C.c_void_p),
-                ("verbose", C.c_int32), ("keep_site", C.c_int32), ("mlp", C.c_void_p), ("mlp_from_sweep", C.c_int32)]
+                ("verbose", C.c_int32), ("keep_site", C.c_int32), ("mlp", C.c_void_p), ("mlp_from_sweep", C.c_int32),
+                ("mlp_shadow", C.c_int32)]
 
 
 class SweepResult(C.Structure):
     _fields_ = [("capacity", C.c_int32), ("energies", f64p), ("discarded", f64p), ("iters", i32p), ("sites", i32p),
                 ("n_solves", C.c_int32), ("n_not_converged", C.c_int32), ("energy", C.c_double),
                 ("best_energy", C.c_double), ("seconds", C.c_double), ("left_block", C.POINTER(BlockDesc)),
-                ("right_block", C.POINTER(BlockDesc))]
+                ("right_block", C.POINTER(BlockDesc)), ("energies_alt", f64p), ("iters_alt", i32p)]
 
 
 lib.dmrg_last_error.restype = C.c_char_p
@@ -309,12 +310,13 @@ def block_grow(h, eri, n_alpha, n_beta, site, block, side, kept=None, O=None, de
 
 def sweep(h, eri, n_alpha, n_beta, m_per_sweep, m_warmup=None, tol=1e-8, max_iter=300, max_sub=24,
           precision=PREC_FP64, fp64_polish=False, split_tol=1e-5, seed=0, device=0, stream=None, verbose=False,
-          keep_site=0, mlp=None, mlp_from_sweep=0):
+          keep_site=0, mlp=None, mlp_from_sweep=0, mlp_shadow=False):
     """dmrg_sweep: warm-up plus len(m_per_sweep) two-site sweeps. Returns a dict with the per-solve
     energies, discarded weights, iterations and bond sites, and the run's summary fields; with
     keep_site > 0 also "left" and "right", the blocks of the bond (keep_site, keep_site + 1) after the
     last sweep (dmrg_inputs Blocks). mlp: a learned preconditioner (Mlp) for the solves of sweeps
-    mlp_from_sweep and later."""
+    mlp_from_sweep and later; mlp_shadow: those bonds are solved with both preconditioners on the same
+    problem, the sweep continuing with the diagonal solve ("energies_alt", "iters_alt": the learned ones)."""
     h = np.ascontiguousarray(h, dtype=np.float64)
     eri = np.ascontiguousarray(eri, dtype=np.float64)
     L = h.shape[0]
@@ -323,18 +325,22 @@ def sweep(h, eri, n_alpha, n_beta, m_per_sweep, m_warmup=None, tol=1e-8, max_ite
     opts = SweepOpts(int(ms.size), _ptr(ms, C.c_int32), int(m_warmup if m_warmup else ms[0]), tol, max_iter, max_sub,
                      precision, 1 if fp64_polish else 0, split_tol, seed, device, _stream_ptr(stream),
                      1 if verbose else 0, int(keep_site), mlp._h.value if mlp is not None else None,
-                     int(mlp_from_sweep))
+                     int(mlp_from_sweep), 1 if mlp_shadow else 0)
     cap = int(ms.size) * (2 * L) + 2
     e = np.zeros(cap)
     d = np.zeros(cap)
     it = np.zeros(cap, dtype=np.int32)
     si = np.zeros(cap, dtype=np.int32)
+    ea = np.zeros(cap)
+    ia = np.zeros(cap, dtype=np.int32)
     res = SweepResult(cap, _ptr(e, C.c_double), _ptr(d, C.c_double), _ptr(it, C.c_int32), _ptr(si, C.c_int32))
+    res.energies_alt = _ptr(ea, C.c_double)
+    res.iters_alt = _ptr(ia, C.c_int32)
     st = _check(lib.dmrg_sweep(C.byref(prob), C.byref(opts), C.byref(res)), allow=(DMRG_OK, DMRG_NOT_CONVERGED))
     n = res.n_solves
     out = dict(energies=e[:n], discarded=d[:n], iters=it[:n], sites=si[:n], energy=res.energy,
                best_energy=res.best_energy, seconds=res.seconds, n_not_converged=res.n_not_converged,
-               converged=st == DMRG_OK)
+               converged=st == DMRG_OK, energies_alt=ea[:n], iters_alt=ia[:n])
     if keep_site > 0:
         out["left"] = _take_block(res.left_block, "left", range(0, keep_site))
         out["right"] = _take_block(res.right_block, "right", range(keep_site + 2, L))

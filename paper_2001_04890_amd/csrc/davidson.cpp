@@ -165,9 +165,10 @@ dmrg_status dmrg::davidson_run(dmrg_hop* H, double* psi, const dmrg_dav_opts* o,
         double best_mlp_r = INFINITY;
         int mlp_stall = 0;
         // rate rule of the judge: the network must cut the residual by judge_factor within judge_window
-        // iterations (0: rule off)
-        int judge_window = 0;
-        double judge_factor = 0.0;
+        // iterations (window 0: rule off); at L = 32 along a sweep the no-new-minimum rule alone let a
+        // few solves run 2-4x longer than with the diagonal correction, this rule stops them early
+        int judge_window = 10;
+        double judge_factor = 0.5;
         if (const char* e = std::getenv("DMRG_MLP_JUDGE_WINDOW")) judge_window = std::max(0, std::atoi(e));
         if (const char* e = std::getenv("DMRG_MLP_JUDGE_FACTOR")) judge_factor = std::atof(e);
         std::vector<double> rhist;

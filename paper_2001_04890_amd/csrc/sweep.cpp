@@ -205,8 +205,12 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
         int n_solves = 0;
         double best = INFINITY;
         HopPtr hop;
-        DevVec psi;
+        DevVec psi, psi2;
         int64_t psi_n = 0;
+        for (int i = 0; i < res->capacity; ++i) {
+            if (res->energies_alt) res->energies_alt[i] = std::nan("");
+            if (res->iters_alt) res->iters_alt[i] = -1;
+        }
         auto solve = [&](int site, int sweep, int m) {
             dmrg_problem q = *p;
             q.site = site;
@@ -217,10 +221,12 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
             int64_t n = 0;
             check(dmrg_hop_layout(hop.p, &n, nullptr, nullptr, nullptr, nullptr));
             if (n > psi_n) {
-                if (psi.p) (void)hipFree(psi.p);
-                psi.p = nullptr;
-                if (hipMalloc(&psi.p, (size_t)n * sizeof(double)) != hipSuccess)
-                    throw Error(DMRG_ERR_NOMEM, "device allocation failed (sweep vector)");
+                for (DevVec* v : {&psi, &psi2}) {
+                    if (v->p) (void)hipFree(v->p);
+                    v->p = nullptr;
+                    if (hipMalloc(&v->p, (size_t)n * sizeof(double)) != hipSuccess)
+                        throw Error(DMRG_ERR_NOMEM, "device allocation failed (sweep vector)");
+                }
                 psi_n = n;
             }
             std::vector<double> x((size_t)n);
@@ -228,8 +234,23 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
             HIPCHK(hipMemcpyAsync(psi.p, x.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
             dmrg_dav_result r{};
             const bool learned = o->mlp && sweep >= o->mlp_from_sweep;
-            dav.precond = learned ? DMRG_PRECOND_MLP : DMRG_PRECOND_DIAG;
-            dav.mlp = learned ? o->mlp : nullptr;
+            const bool shadow = learned && o->mlp_shadow;
+            if (shadow) {
+                // the learned solve on the same problem from the same start vector; the sweep goes on
+                // with the diagonal one below
+                HIPCHK(hipMemcpyAsync(psi2.p, x.data(), (size_t)n * sizeof(double), hipMemcpyHostToDevice, s));
+                dmrg_dav_opts d2 = dav;
+                d2.precond = DMRG_PRECOND_MLP;
+                d2.mlp = o->mlp;
+                dmrg_dav_result r2{};
+                check(dmrg_davidson(hop.p, psi2.p, &d2, &r2, s));
+                if (n_solves < res->capacity) {
+                    if (res->energies_alt) res->energies_alt[n_solves] = r2.energy;
+                    if (res->iters_alt) res->iters_alt[n_solves] = r2.iters;
+                }
+            }
+            dav.precond = learned && !shadow ? DMRG_PRECOND_MLP : DMRG_PRECOND_DIAG;
+            dav.mlp = learned && !shadow ? o->mlp : nullptr;
             const dmrg_status st = dmrg_davidson(hop.p, psi.p, &dav, &r, s);
             check(st);
             if (n_solves < res->capacity) {

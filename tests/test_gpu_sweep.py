@@ -12,7 +12,9 @@ brute-force FCI (the oracle's determinant CI from the same integrals).
 * Learned preconditioner in sweeps: a new network (output layer zero, so its correction is the
   diagonal one) in the solves of the second sweep gives the diagonal run's energies and iteration
   counts; a trained network changes no energy beyond the tolerance's reach (|dE| <= 1e-8 per solve,
-  the final energy within 1e-9); mlp_from_sweep out of range is an argument error.
+  the final energy within 1e-9); in shadow mode the sweep is the diagonal one and the learned solves
+  of the same problems agree with it within 1e-8 and take fewer iterations in total (the network is
+  trained on this problem's own middle-bond solves); mlp_from_sweep out of range is an argument error.
 """
 import numpy as np
 import pytest
@@ -117,5 +119,15 @@ def test_learned_preconditioner_in_sweeps(l8):
     assert r2["converged"]
     assert np.abs(r2["energies"] - ref["energies"]).max() < 1e-8
     assert abs(r2["energy"] - ref["energy"]) < 1e-9
+    # shadow mode: both preconditioners on the same problems, the sweep going on with the diagonal one
+    sh = lib_mod.sweep(h, eri, 4, 4, [24, 24], mlp=net, mlp_from_sweep=1, mlp_shadow=True, **kw)
+    per = 2 * 8 - 4                                    # solves of the second sweep
+    assert np.array_equal(sh["energies"], ref["energies"]) and np.array_equal(sh["iters"], ref["iters"])
+    assert np.all(np.isnan(sh["energies_alt"][:-per])) and np.all(sh["iters_alt"][:-per] == -1)
+    assert np.all(sh["iters_alt"][-per:] > 0)
+    assert np.abs(sh["energies_alt"][-per:] - sh["energies"][-per:]).max() < 1e-8
+    n_d, n_m = int(sh["iters"][-per:].sum()), int(sh["iters_alt"][-per:].sum())
+    print(f"[sweep mlp] shadow: diagonal {n_d} vs learned {n_m} iterations on the same problems", flush=True)
+    assert n_m < n_d                                   # the trained network saves iterations
     with pytest.raises(lib_mod.DmrgError):
         lib_mod.sweep(h, eri, 4, 4, [24], mlp=fresh, mlp_from_sweep=1, **kw)
