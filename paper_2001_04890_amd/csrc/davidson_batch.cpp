@@ -283,5 +283,9 @@ extern "C" dmrg_status dmrg_davidson_batch(dmrg_hop* H, double* psi, const dmrg_
         if (cap) (void)hipStreamDestroy(cap);
         dmrg::last_error() = "host allocation failed";
         return DMRG_ERR_NOMEM;
+    } catch (const std::exception& e) {   // nothing else may cross the C boundary
+        if (cap) (void)hipStreamDestroy(cap);
+        dmrg::last_error() = e.what();
+        return DMRG_ERR_ARG;
     }
 }

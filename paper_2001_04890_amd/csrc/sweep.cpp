@@ -200,8 +200,6 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
             right[k + 1].reset(nb);
             if (o->verbose) std::fprintf(stderr, "[dmrg_sweep] warm-up right block of %d orbitals\n", k + 1);
         }
-        const int n_bonds = L - 1;
-        const int per_sweep = 2 * n_bonds;
         int n_solves = 0;
         double best = INFINITY;
         HopPtr hop;
@@ -321,12 +319,14 @@ extern "C" dmrg_status dmrg_sweep(const dmrg_problem* p, const dmrg_sweep_opts* 
         res->n_solves = n_solves;
         res->best_energy = best;
         res->seconds = dmrg::now_seconds() - t0;
-        (void)per_sweep;
         return res->n_not_converged ? DMRG_NOT_CONVERGED : DMRG_OK;
     } catch (const Error& e) {
         return dmrg::record_error(e);
     } catch (const std::bad_alloc&) {
         dmrg::last_error() = "host allocation failed";
         return DMRG_ERR_NOMEM;
+    } catch (const std::exception& e) {   // nothing else may cross the C boundary
+        dmrg::last_error() = e.what();
+        return DMRG_ERR_ARG;
     }
 }
