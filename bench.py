@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--pairs", type=int, default=1000,
                     help="large: normal/complementary pairs per family (B/Q and A/P) in the share")
     ap.add_argument("--n-problems", type=int, default=128)
+    ap.add_argument("--batch-davidson", choices=["serial", "graph", "eager"], default=None,
+                    help="batch: only the Davidson solves, serially or batched (graph / eager launches), for profiling")
     ap.add_argument("--operators", choices=["synthetic", "swept"], default="swept",
                     help="precision workload: synthetic block operators (sector sizes from the sigma model) or "
                          "the blocks that two-site sweeps (dmrg_sweep) over random integrals leave at the middle bond")
@@ -309,6 +311,24 @@ def bench_batch(args):
             if j % 16 == 15:
                 log(f"[bench] built {j + 1}/{args.n_problems} problems ({time.time() - t0:.0f}s)")
     flops = sum(hp.stats()["flops"] for hp in hops)
+    if args.batch_davidson:
+        dav = dict(tol=1e-6, max_iter=400, max_sub=24, precision=dm.PREC_SPLIT2, fp64_polish=True, split_tol=3e-4)
+        starts = [torch.as_tensor(random_vector(hp.n_coeff, 100 + k), device="cuda:0") for k, hp in enumerate(hops)]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        if args.batch_davidson == "serial":
+            its = [hp.davidson(x0.clone(), stream=stream, **dav)["iters"] for hp, x0 in zip(hops, starts)]
+            n_mv = None
+        else:
+            comb = dm.Hop.combine(hops, stream=stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            rb = comb.davidson_batch(torch.cat(starts), use_graph=args.batch_davidson == "graph", stream=stream, **dav)
+            its, n_mv = rb["iters"].tolist(), rb["matvecs"]
+        torch.cuda.synchronize()
+        log(f"[bench] {args.batch_davidson} Davidson of {len(hops)} problems: {time.perf_counter() - t:.3f} s, "
+            f"iterations {int(np.sum(its))} in total, merged H.psi launches {n_mv}")
+        return
     xs = [torch.as_tensor(random_vector(hp.n_coeff, 7 + k), device="cuda:0") for k, hp in enumerate(hops)]
     ys = {p: [torch.empty_like(x) for x in xs] for p in (dm.PREC_SPLIT2, dm.PREC_FP64)}
     xc = torch.cat(xs)
