@@ -17,7 +17,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed-FP32 instructions are disabled for every HIP translation unit.
 COMMON = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "hpsi_lds64.hip", "mlp.hip", "host.cpp", "mlp_host.cpp",
+SOURCES = ["kernels.hip", "hpsi_lds.hip", "hpsi_big.hip", "hpsi_big64.hip", "hpsi_lds64.hip", "mlp.hip", "host.cpp", "plan.cpp", "mlp_host.cpp",
            "renorm_host.cpp", "davidson.cpp", "eigen.cpp", "noalloc.cpp", "grow.hip", "grow.cpp",
            "sweep.cpp", "davidson_batch.hip", "davidson_batch.cpp"]
 
