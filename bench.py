@@ -63,7 +63,7 @@ def main():
     ap.add_argument("--precond-eval", choices=["sweep", "bonds"], default="sweep",
                     help="precond: A/B along the last of two sweeps at L=32 (default), or at single bonds of "
                          "synthetic blocks")
-    ap.add_argument("--precond-m", type=str, default="512,1500",
+    ap.add_argument("--precond-m", type=str, default="256,1500",
                     help="precond sweep evaluation: bond dimension of each sweep (the A/B runs the last)")
     ap.add_argument("--precond-train-m", type=str, default="256,512",
                     help="precond sweep evaluation: sweeps at L=20..28 whose middle-bond blocks give training pairs")
