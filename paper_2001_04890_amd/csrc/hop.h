@@ -198,6 +198,8 @@ struct dmrg_hop {
                                                 // (0: those run in the one-wave kernel)
     int tune_lds64_w7 = 1;                      // 1: its 7-wavefront class held to 128 VGPRs (two per CU)
     int tune_lds64_cw = 1;                      // 1: a copy wavefront per workgroup issues every LDS copy
+    int tune_lds64_ns3 = 0;                     // 1: its KT = 2 classes keep three LDS slots (copies two steps
+                                                // ahead; measured no faster at L = 24, M = 1024)
     int tune_lds64_task_route = 0;              // 1: a target within its tiles keeps the tasks whose source fits
                                                 // them (larger sources: two-pass or one-wave path); 0: a
                                                 // target with any larger source leaves it entirely

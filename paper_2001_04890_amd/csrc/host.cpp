@@ -780,6 +780,7 @@ extern "C" dmrg_status dmrg_build_blocks(const dmrg_problem* p, const dmrg_block
         if (const char* e = std::getenv("DMRG_LDS64_SMALL")) H->tune_lds64_small = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_W7")) H->tune_lds64_w7 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_CW")) H->tune_lds64_cw = std::atoi(e) != 0;
+        if (const char* e = std::getenv("DMRG_LDS64_NS3")) H->tune_lds64_ns3 = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS64_TASK_ROUTE")) H->tune_lds64_task_route = std::atoi(e) != 0;
         if (const char* e = std::getenv("DMRG_LDS_CW")) H->tune_lds_cw = std::atoi(e) & 0xF;
         if (const char* e = std::getenv("DMRG_SPLIT_TASK_ROUTE")) H->tune_split_task_route = std::atoi(e) != 0;
@@ -1074,6 +1075,7 @@ extern "C" dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* 
         C->tune_lds64_small = hops[0]->tune_lds64_small;
         C->tune_lds64_w7 = hops[0]->tune_lds64_w7;
         C->tune_lds64_cw = hops[0]->tune_lds64_cw;
+        C->tune_lds64_ns3 = hops[0]->tune_lds64_ns3;
         C->tune_lds64_task_route = hops[0]->tune_lds64_task_route;
         C->tune_split_task_route = hops[0]->tune_split_task_route;
         C->tune_part_items = hops[0]->tune_part_items;

@@ -74,7 +74,9 @@ __device__ __forceinline__ TD load_td(const LTask64* __restrict__ p) {
 // target; W: wavefronts, at least the target's row tiles; MINW: wavefronts per SIMD the register
 // allocation must allow (4 holds the 7-wavefront class to 128 VGPRs, so that two of its workgroups
 // share a CU, at the price of a few spilled registers).
-template <int KT, int QT, int W, int MINW, int CW>
+// NS: LDS slots; 3 (with the copy wavefront) puts the copies two steps ahead of the compute
+// wavefronts instead of one, for classes whose steps are short against the copy latency.
+template <int KT, int QT, int W, int MINW, int CW, int NS = 2>
 __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* __restrict__ items,
                                                                 const LTask64* __restrict__ tasks,
                                                                 const double* __restrict__ pool_t,
@@ -82,8 +84,9 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
                                                                 double* __restrict__ y, double* __restrict__ part,
                                                                 const int32_t* __restrict__ mask) {
     if (mask && mask[items[blockIdx.x].part] != kPartActive) return;   // whole workgroup, before any barrier
+    static_assert(NS == 2 || (NS == 3 && CW == 1), "three slots need the copy wavefront");
     constexpr int SLOT = (KT + QT) * kTileD;   // doubles of one slot: X^T slice, then B slice
-    __shared__ __attribute__((aligned(16))) double lds[2 * SLOT];
+    __shared__ __attribute__((aligned(16))) double lds[NS * SLOT];
 
     const Item I = items[blockIdx.x];
     const int64_t y_off = uni64(I.y_off), part_off = uni64(I.part_off);
@@ -112,11 +115,15 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
     };
     // copy the operands of step (T, jc) into a slot: X^T tiles (jc, kt < ka16), contiguous in the
     // tiled X^T, then B tiles (q < tq, jc), one per target column tile; half tiles h0, h0 + hs, ...
-    auto stage = [&](const TD& T, int jc, int slot, int h0, int hs) {
+    // nfix > 0: exactly nfix copy instructions (the last copy repeated: the same bytes to the same
+    // place), so that a wait for all but the newest nfix copies waits for every earlier step
+    auto stage = [&](const TD& T, int jc, int slot, int h0, int hs, int nfix = 0) {
         double* d = lds + slot * SLOT;
         const double* xs = xt + T.x + (int64_t)jc * T.pa16 * kTileD;
         const int nx = 2 * T.ka16, n = nx + 2 * tq;
-        for (int h = h0; h < n; h += hs) {
+        const int nend = nfix > 0 ? nfix : n;
+        for (int h0i = h0; h0i < nend; h0i += hs) {
+            const int h = h0i < n ? h0i : n - 1;
             const double* src;
             double* dst;
             if (h < nx) {
@@ -130,6 +137,7 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
             __builtin_amdgcn_global_load_lds((const void*)(src + lane * 2), (lds_ptr_t)dst, 16, 0, 0);
         }
     };
+    auto next_slot = [](int sl) { return sl + 1 == NS ? 0 : sl + 1; };
 
     // barrier of the step loop: CW = 0, every wave copies (waits for its copies, then the barrier);
     // CW = 1, the compute waves only read LDS (whose values the MFMAs have consumed by then), so a
@@ -146,7 +154,61 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
     };
     int t = t_begin, jc = 0, slot = 0;
     TD T = load_td(tasks + t);
-    if constexpr (CW == 1) {
+    if constexpr (CW == 1 && NS == 3) {
+        if (wave == W) {
+            // the copy wavefront, two steps ahead: while the compute wavefronts run step s it issues the
+            // copies of step s + 2 (exactly kCopies instructions per step) and then waits for those of
+            // step s + 1 (every copy but the newest kCopies), before the barrier that starts step s + 1
+            constexpr int kCopies = 2 * (KT + QT);
+            static_assert(kCopies < 64, "vmcnt holds at most 63");
+            constexpr int kWait = (kCopies & 15) | (7 << 4) | (15 << 8) | (((kCopies >> 4) & 3) << 14);
+            struct Step { int t, jc; TD T; bool ok; };
+            auto advance = [&](Step& c) {
+                if (!c.ok) return;
+                if (c.jc + 1 < c.T.kd16) {
+                    ++c.jc;
+                } else if (c.t + 1 < t_end) {
+                    ++c.t;
+                    c.jc = 0;
+                    c.T = load_td(tasks + c.t);
+                } else {
+                    c.ok = false;
+                }
+            };
+            Step s1{t, 0, T, true};               // the step after the compute waves' current one
+            stage(s1.T, 0, 0, 0, 1, kCopies);
+            advance(s1);
+            int sl = 1;                            // slot of step s1
+            if (s1.ok) {
+                stage(s1.T, s1.jc, sl, 0, 1, kCopies);
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_s_waitcnt(kWait);
+                asm volatile("" ::: "memory");
+            } else {
+                wait_vm();
+            }
+            step_barrier();
+            while (s1.ok) {
+                Step s2 = s1;
+                advance(s2);
+                const int sl2 = next_slot(sl);
+                if (s2.ok) {
+                    stage(s2.T, s2.jc, sl2, 0, 1, kCopies);   // slot read by the compute waves before the last barrier
+                    asm volatile("" ::: "memory");
+                    __builtin_amdgcn_s_waitcnt(kWait);
+                    asm volatile("" ::: "memory");
+                } else {
+                    wait_vm();
+                }
+                step_barrier();
+                s1 = s2;
+                sl = sl2;
+            }
+            step_barrier();                           // the compute waves' barrier after their last step
+            return;
+        }
+    }
+    if constexpr (CW == 1 && NS == 2) {
         if (wave == W) {
             // the copy wavefront: every copy of the item, one step ahead of the compute wavefronts,
             // which then never wait for a copy in flight (the wait before an LDS read that the
@@ -187,7 +249,7 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
         TD Tn = T;
         if (new_task) Tn = load_td(tasks + t + 1);
         if constexpr (CW == 0)
-            if (has_next) stage(Tn, more_cols ? jc + 1 : 0, slot ^ 1, wave, W);   // last read before the previous barrier
+            if (has_next) stage(Tn, more_cols ? jc + 1 : 0, next_slot(slot), wave, W);   // last read before the previous barrier
         const double* xs = lds + slot * SLOT;
         const double* bs = xs + KT * kTileD;
         f64x4 tt = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -225,7 +287,7 @@ __global__ __launch_bounds__((W + CW) * 64, MINW) void k_hpsi_lds64(const Item* 
             jc = 0;
             T = Tn;
         }
-        slot ^= 1;
+        slot = next_slot(slot);
     }
     if (!active) return;
     // store: lane (li, g) holds Y[16 wave + g + 4 v][16 q + li]
@@ -252,13 +314,14 @@ hipError_t launch_hpsi_lds64(const LdsPlan64& P, const double* pool_t, const dou
         const int b = P.cls_begin[c], n = P.cls_begin[c + 1] - b;
         if (n <= 0) continue;
         const dim3 grid(n);
-#define DMRG_L64C(KT_, QT_, W_, MINW_, CW_)                                                               \
-    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_, CW_>), grid, dim3((W_ + CW_) * 64), 0, s, P.items + b, \
-                       P.tasks, pool_t, xt, y, P.partial, active)
-#define DMRG_L64(KT_, QT_, W_, MINW_)                   \
-    do {                                                \
-        if (P.copy_wave) DMRG_L64C(KT_, QT_, W_, MINW_, 1); \
-        else DMRG_L64C(KT_, QT_, W_, MINW_, 0);             \
+#define DMRG_L64C(KT_, QT_, W_, MINW_, CW_, NS_)                                                          \
+    hipLaunchKernelGGL((k_hpsi_lds64<KT_, QT_, W_, MINW_, CW_, NS_>), grid, dim3((W_ + CW_) * 64), 0, s,     \
+                       P.items + b, P.tasks, pool_t, xt, y, P.partial, active)
+#define DMRG_L64(KT_, QT_, W_, MINW_)                                                   \
+    do {                                                                                \
+        if (P.copy_wave && KT_ == 2 && P.three_slots) DMRG_L64C(KT_, QT_, W_, MINW_, 1, 3); \
+        else if (P.copy_wave) DMRG_L64C(KT_, QT_, W_, MINW_, 1, 2);                     \
+        else DMRG_L64C(KT_, QT_, W_, MINW_, 0, 2);                                      \
     } while (0)
         switch (c) {
             case 0: DMRG_L64(2, 3, 6, 1); break;

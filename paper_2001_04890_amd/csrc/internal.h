@@ -214,6 +214,7 @@ struct LdsPlan64 {
     int n_items = 0;
     int w7_min_waves = 1;               // 4: the (7, 7, 7) class held to 128 VGPRs (two workgroups per CU)
     int copy_wave = 1;                  // 1: one more wavefront per workgroup issues every LDS copy
+    int three_slots = 0;                // with the copy wavefront: the KT = 2 classes stage two steps ahead
 };
 // y (one vector) += the plan's targets of f A X B^T; xt = that vector's tiled FP64 X^T
 // (launch_pack_xt64 with the FP64 packing geometry)

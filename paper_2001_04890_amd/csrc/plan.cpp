@@ -1017,6 +1017,7 @@ void build_lds64_plan(dmrg_hop& H, hipStream_t s, const std::vector<char>& large
     H.lplan64.n_items = (int)items.size();
     H.lplan64.w7_min_waves = H.tune_lds64_w7 ? 4 : 1;
     H.lplan64.copy_wave = H.tune_lds64_cw;
+    H.lplan64.three_slots = H.tune_lds64_ns3;
     if (const char* e = std::getenv("DMRG_PLAN_TRACE"))
         if (e[0] == '1') {
             std::fprintf(stderr, "[dmrg lds64 plan] items %zu classes", items.size());

@@ -10,7 +10,10 @@ which share one reduction record); "whole" (few, long items); by
 default tasks whose source is a single 32 x 32 tile run in the one-wavefront kernel next to the
 LDS-staged ones of the same target, "small" (and "cut", "whole") put them in the LDS kernel too;
 the kernel switched off (every target on the one-wavefront kernel); and without the copy wavefront
-(every wavefront issues a share of the LDS copies), cut to its floor. The plan trace names the
+(every wavefront issues a share of the LDS copies), cut to its floor; the classes of sources with
+at most 32 rows stage their copies one step ahead in two LDS slots by default ("two_slots"), two
+steps ahead in three with DMRG_LDS64_NS3=1 ("three_slots_cut": with many short items). The plan
+trace names the
 launch classes and reductions each variant produced, so the test checks that the paths it means to
 cover were taken. Bars: FP64 within 1e-12 of max|y| against the oracle on every element, plans
 within 1e-13 of each other, every plan deterministic bit for bit.
@@ -47,6 +50,8 @@ VARIANTS = {
     "whole": {"DMRG_LDS64_ITEMS": "64", "DMRG_LDS64_SMALL": "1"},
     "off": {"DMRG_LDS64": "0"},
     "no_copy_wave": {"DMRG_LDS64_CW": "0", "DMRG_LDS64_ITEMS": "100000000"},
+    "two_slots": {"DMRG_LDS64_NS3": "0", "DMRG_LDS64_SMALL": "1"},
+    "three_slots_cut": {"DMRG_LDS64_NS3": "1", "DMRG_LDS64_ITEMS": "100000000", "DMRG_LDS64_SMALL": "1"},
 }
 TRACE = re.compile(r"\[dmrg lds64 plan\] items (\d+) classes (\d+) (\d+) (\d+) (\d+) (\d+) reduces (\d+)")
 
