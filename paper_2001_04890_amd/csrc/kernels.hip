@@ -334,8 +334,15 @@ static hipError_t run_phases(const HpsiPlan& plan, double* y, int64_t n_coeff, i
 
 hipError_t launch_hpsi_f64(const HpsiPlan& plan, const double* pool, const double* x, double* y, int64_t n_coeff,
                            int nvec, hipStream_t s, const int32_t* active) {
-    hipError_t e = launch_pack(plan, x, n_coeff, nvec, 0, s);
-    if (e != hipSuccess) return e;
+    // the packed input feeds only this plan's items (the other FP64 kernels pack their own)
+    bool any = false;
+    for (int ph = 0; ph < plan.n_phases && !any; ++ph)
+        for (int l = plan.phases[ph].launch_begin; l < plan.phases[ph].launch_end; ++l)
+            any = any || plan.launches[l].item_count > 0;
+    if (any) {
+        hipError_t e = launch_pack(plan, x, n_coeff, nvec, 0, s);
+        if (e != hipSuccess) return e;
+    }
     const int64_t ss = plan.partial_size;
     return run_phases(plan, y, n_coeff, nvec, s, [&](int c, int b, int n) {
         DMRG_CLASS_SWITCH(k_hpsi_f64, dim3(n, nvec), dim3(64), 0, s, plan.items + b, plan.tasks, pool, plan.xp, y,
