@@ -235,8 +235,9 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK["fp64"], "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK["fp64"], 4),
                 "traffic": (tr64["fetch_bytes"] + tr64["write_bytes"]) if tr64 else None,
-                "kernel": "FP64 H.psi sequence (k_hpsi_lds64 classes, k_hpsi_f64 tile classes for single-tile "
-                          "sources, k_big64 passes above 96 x 96, k_pack, k_pack_xt64, k_reduce, k_reduce_lds)",
+                "kernel": "FP64 H.psi sequence (k_hpsi_lds64 classes for targets within 112 x 112; k_hpsi_f64 "
+                          "tiles and k_big64 passes for the rest, with k_pack when those tiles run; k_pack_xt64, "
+                          "k_reduce_lds, k_zero)",
                 "algorithmic_bytes": st["bytes"],
                 "hbm_frac": round(st["bytes"] / t64 / 1e9 / HBM_PEAK, 4)}
     achieved_sp = st["flops"] / tsp / 1e12
