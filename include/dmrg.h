@@ -354,6 +354,18 @@ dmrg_status dmrg_davidson(dmrg_hop* hop, double* psi, const dmrg_dav_opts* opts,
  * combined handle solves the direct-sum problem (its lowest eigenpair over all parts). */
 dmrg_status dmrg_hop_combine(dmrg_hop* const* hops, int32_t n, void* stream, dmrg_hop** out);
 
+/* Batched H.psi of independent problems (the task lists of Section 2.2.1, one per problem):
+ * y[i] = H_i x[i] for i < n, one vector per handle (device pointers of hops[i]'s n_coeff doubles),
+ * every handle on one device, enqueued in order on `stream` without host synchronization. The
+ * launch sequences stay those of the individual handles; for one launch sequence over a common pool
+ * of work items (and one graph launch), merge the handles once with dmrg_hop_combine and call
+ * dmrg_hpsi / dmrg_hpsi_graph on the merged handle with the vectors concatenated. Errors:
+ * DMRG_ERR_ARG (NULL pointers, n < 0, handles on different devices, bad precision),
+ * DMRG_ERR_ALIAS (x[i] and y[i] overlap, or an output overlaps another problem's vector), and those
+ * of dmrg_hpsi; nothing is launched unless every argument is valid. */
+dmrg_status dmrg_hpsi_batched(dmrg_hop* const* hops, int32_t n, const double* const* x, double* const* y,
+                              int32_t precision, void* stream);
+
 /* Release the parts of a built handle that only its own H.psi uses — launch plans, cached graphs,
  * the tiled split and tiled FP64 operator copies — keeping the FP64 operator pool, diag(H) and the
  * host-side description that dmrg_hop_combine reads: for callers that merge many handles and need

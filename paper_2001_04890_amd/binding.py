@@ -101,6 +101,9 @@ lib.dmrg_hop_layout.restype = C.c_int32
 lib.dmrg_hop_stats.argtypes = [C.c_void_p, f64p, f64p, i64p, i64p]
 lib.dmrg_hop_stats.restype = C.c_int32
 lib.dmrg_hpsi.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
+lib.dmrg_hpsi_batched.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                  C.c_int32, C.c_void_p]
+lib.dmrg_hpsi_batched.restype = C.c_int32
 lib.dmrg_hpsi.restype = C.c_int32
 lib.dmrg_hpsi_graph.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]
 lib.dmrg_hpsi_graph.restype = C.c_int32
@@ -379,6 +382,20 @@ def _stream_ptr(stream):
 
 class Hop:
     """Handle of one bond's H.psi operator (dmrg_build_blocks), or of several merged ones."""
+
+    @staticmethod
+    def hpsi_batched(hops, xs, ys, precision=PREC_FP64, stream=None):
+        """dmrg_hpsi_batched: ys[i] = H_i xs[i] for device tensors (one vector per handle), in one call."""
+        n = len(hops)
+        assert len(xs) == n and len(ys) == n
+        for h, x, y in zip(hops, xs, ys):
+            _device_f64(x, h.device, "x")
+            _device_f64(y, h.device, "y")
+            assert x.numel() == h.n_coeff and y.numel() == h.n_coeff
+        hp = (C.c_void_p * max(n, 1))(*[h._h.value for h in hops])
+        xp = (C.c_void_p * max(n, 1))(*[x.data_ptr() for x in xs])
+        yp = (C.c_void_p * max(n, 1))(*[y.data_ptr() for y in ys])
+        _check(lib.dmrg_hpsi_batched(hp, n, xp, yp, precision, _stream_ptr(stream)))
 
     @classmethod
     def combine(cls, hops, stream=None):

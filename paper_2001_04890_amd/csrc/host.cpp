@@ -972,6 +972,34 @@ extern "C" dmrg_status dmrg_hpsi(dmrg_hop* H, const double* x, double* y, int32_
     }
 }
 
+extern "C" dmrg_status dmrg_hpsi_batched(dmrg_hop* const* hops, int32_t n, const double* const* x, double* const* y,
+                                         int32_t precision, void* stream) {
+    g_err.clear();
+    try {
+        if (n < 0 || (n > 0 && (!hops || !x || !y))) throw Error(DMRG_ERR_ARG, "NULL argument or n < 0");
+        for (int32_t i = 0; i < n; ++i) {
+            check_hpsi_args(hops[i], x[i], y[i], 1, precision);
+            if (hops[i]->device != hops[0]->device) throw Error(DMRG_ERR_ARG, "handles on different devices");
+        }
+        // no output may overlap another problem's input or output (each pair is checked above)
+        for (int32_t i = 0; i < n; ++i)
+            for (int32_t j = 0; j < n; ++j) {
+                if (i == j) continue;
+                const double* yi = y[i];
+                const int64_t ni = hops[i]->n_coeff, nj = hops[j]->n_coeff;
+                const bool over_x = yi < x[j] + nj && x[j] < yi + ni;
+                const bool over_y = yi < y[j] + nj && y[j] < yi + ni;
+                if (over_x || over_y) throw Error(DMRG_ERR_ALIAS, "an output overlaps another problem's vector");
+            }
+        if (n == 0) return DMRG_OK;
+        HIPCHK(hipSetDevice(hops[0]->device));
+        for (int32_t i = 0; i < n; ++i) enqueue_hpsi(hops[i], x[i], y[i], 1, precision, (hipStream_t)stream);
+        return DMRG_OK;
+    } catch (const Error& e) {
+        return fail(e);
+    }
+}
+
 extern "C" dmrg_status dmrg_hpsi_graph(dmrg_hop* H, const double* x, double* y, int32_t nvec, int32_t precision,
                                        void* stream) {
     g_err.clear();

@@ -124,3 +124,24 @@ def test_trimmed_handles_combine_to_the_same_result():
     full[1].diagonal(d_ref)
     torch.cuda.synchronize()
     assert torch.equal(d, d_ref)
+
+
+def test_hpsi_batched_equals_each_handle(batch):
+    """dmrg_hpsi_batched: every output equals its handle's own dmrg_hpsi bit for bit (same launch
+    sequences), in both precisions; an output that overlaps another problem's input is refused."""
+    probs, hops, comb = batch
+    xs = [torch.as_tensor(random_vector(h.n_coeff, 80 + k), device=DEV) for k, h in enumerate(hops)]
+    for prec in (PREC_FP64, PREC_SPLIT2):
+        ys = [torch.empty_like(x) for x in xs]
+        Hop.hpsi_batched(hops, xs, ys, prec)
+        for h, x, y in zip(hops, xs, ys):
+            ref = torch.empty_like(x)
+            h.hpsi(x, ref, prec)
+            torch.cuda.synchronize()
+            assert torch.equal(y, ref)
+    i = int(np.argmin([h.n_coeff for h in hops]))    # the smallest problem's output inside another's input
+    j = (i + 1) % len(hops)
+    bad = [torch.empty_like(x) for x in xs]
+    bad[i] = xs[j][: hops[i].n_coeff]
+    with pytest.raises(lib_mod.DmrgError):
+        Hop.hpsi_batched(hops, xs, bad, PREC_FP64)
